@@ -1,0 +1,262 @@
+"""Brute-force CPU oracle (test infrastructure only).
+
+Plain, slow, obviously correct evaluations of the quantities defined in
+Langrene & Warin, arXiv 2005.03246:
+
+* eq. (ECDF) and eq. (ESF), Section 1: generalized weighted ECDF / ESF at
+  arbitrary evaluation points (rectilinear grid nodes or the sample points);
+* eq. (Laplacian_kde_nD), Section 3.1: weighted Laplacian-kernel density
+  estimate, which with w = response gives the Nadaraya-Watson ratio named in
+  the same section;
+* leave-one-out likelihood and squared-error cross-validation scores built
+  from those sums (Section 3.2 notes that infinite-support kernels such as
+  the Laplacian suit likelihood cross-validation).
+
+The arithmetic lives in ``oracle.c`` (a double loop over query and data
+point, Neumaier-compensated FP64 sums, OpenMP over queries).  This module only
+marshals numpy arrays and applies the normalising constants of the
+definitions.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import it; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or (
+        os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
+             "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        I = ctypes.c_int
+        lib.oracle_dominance.argtypes = [I, I64, P, P, I64, P, I, P, P, P, I]
+        lib.oracle_dominance.restype = I
+        lib.oracle_laplace_sums.argtypes = [I, I64, P, I, P, I64, P, I, P, P,
+                                            P, P, I]
+        lib.oracle_laplace_sums.restype = I
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = I
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _as_2d(x) -> np.ndarray:
+    x = _f64(x)
+    if x.ndim == 1:
+        x = x[None, :]
+    return x
+
+
+# --------------------------------------------------------------------------
+# eq. (ECDF) / eq. (ESF)
+# --------------------------------------------------------------------------
+def dominance_sums(x, z, y=None, survival=False, nthreads=0):
+    """Raw sums of eq. (ECDF) (survival=False) or eq. (ESF) (survival=True).
+
+    x: (d, N) data, z: (d, Q) evaluation points, y: (N,) weights or None.
+    Returns int64 counts when y is None, else (sum, abs_sum) float64 arrays.
+    No 1/N factor is applied here.
+    """
+    x = _as_2d(x)
+    z = _as_2d(z)
+    d, n = x.shape
+    if z.shape[0] != d:
+        raise ValueError("x and z must have the same dimension")
+    q = z.shape[1]
+    lib = _load()
+    if y is None:
+        cnt = np.zeros(q, dtype=np.int64)
+        rc = lib.oracle_dominance(d, n, _ptr(x), None, q, _ptr(z),
+                                  int(bool(survival)), _ptr(cnt), None, None,
+                                  int(nthreads))
+        if rc:
+            raise ValueError("oracle_dominance rejected its arguments")
+        return cnt
+    y = _f64(y)
+    if y.shape != (n,):
+        raise ValueError("y must have shape (N,)")
+    s = np.zeros(q)
+    a = np.zeros(q)
+    rc = lib.oracle_dominance(d, n, _ptr(x), _ptr(y), q, _ptr(z),
+                              int(bool(survival)), None, _ptr(s), _ptr(a),
+                              int(nthreads))
+    if rc:
+        raise ValueError("oracle_dominance rejected its arguments")
+    return s, a
+
+
+def ecdf(x, z, y=None, nthreads=0):
+    """F_N(z; x, y) of eq. (ECDF).  y None: int64 counts (no 1/N, y = 1).
+    Otherwise returns (F_N, A_N) with A_N the same functional over |y|."""
+    r = dominance_sums(x, z, y, survival=False, nthreads=nthreads)
+    if y is None:
+        return r
+    n = _as_2d(x).shape[1]
+    return r[0] / n, r[1] / n
+
+
+def esf(x, z, y=None, nthreads=0):
+    """Fbar_N(z; x, y) of eq. (ESF); same conventions as :func:`ecdf`."""
+    r = dominance_sums(x, z, y, survival=True, nthreads=nthreads)
+    if y is None:
+        return r
+    n = _as_2d(x).shape[1]
+    return r[0] / n, r[1] / n
+
+
+def grid_points(nodes, index=None) -> np.ndarray:
+    """Evaluation points of a rectilinear grid (Section 2.1): the Cartesian
+    product of the per-axis node vectors, C order (last axis fastest).
+
+    index: optional (Q, d) integer array of multi-indices to keep only those
+    nodes (sampled checks at full size)."""
+    nodes = [_f64(v) for v in nodes]
+    d = len(nodes)
+    if index is None:
+        mesh = np.meshgrid(*nodes, indexing="ij")
+        return np.stack([m.reshape(-1) for m in mesh])
+    index = np.asarray(index, dtype=np.int64)
+    return np.stack([nodes[k][index[:, k]] for k in range(d)])
+
+
+# --------------------------------------------------------------------------
+# eq. (Laplacian_kde_nD) and the quantities built on it
+# --------------------------------------------------------------------------
+def _hmat(h, d):
+    """Bandwidths as an (nh, d) matrix.  A scalar is one isotropic bandwidth,
+    a 1-D array is a list of isotropic bandwidths, a 2-D array is taken as
+    (nh, d) per-axis bandwidths (eq. (Laplacian_kde_nD) allows h_k per axis)."""
+    h = np.asarray(h, dtype=np.float64)
+    if h.ndim == 0:
+        return np.full((1, d), float(h))
+    if h.ndim == 1:
+        return np.repeat(h[:, None], d, 1)
+    if h.shape[1] != d:
+        raise ValueError("per-axis bandwidths must have shape (nh, d)")
+    return h
+
+
+def laplace_sums(x, z, h, w=None, skip=None, nthreads=0):
+    """Raw kernel sums sum_i w_c,i exp(-sum_k |x_ki - z_kq| / h_bk).
+
+    h: see _hmat; w: (nw, N) or (N,) or None.
+    skip: (Q,) index of a data point to leave out per query (-1 = none).
+    Returns (S, A) with shape (nw, nh, Q)."""
+    x = _as_2d(x)
+    z = _as_2d(z)
+    d, n = x.shape
+    q = z.shape[1]
+    h = _f64(_hmat(h, d))
+    nh = h.shape[0]
+    if w is None:
+        wv, nw = None, 1
+    else:
+        wv = _f64(w)
+        if wv.ndim == 1:
+            wv = wv[None, :]
+        nw = wv.shape[0]
+        wv = _f64(wv)
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.int64)
+    s = np.zeros((nw, nh, q))
+    a = np.zeros((nw, nh, q))
+    rc = _load().oracle_laplace_sums(d, n, _ptr(x), nw, _ptr(wv), q, _ptr(z),
+                                     nh, _ptr(h), _ptr(sk), _ptr(s), _ptr(a),
+                                     int(nthreads))
+    if rc:
+        raise ValueError("oracle_laplace_sums rejected its arguments")
+    return s, a
+
+
+def kde_laplace(x, z, h, w=None, nthreads=0):
+    """f_KDE(z) of eq. (Laplacian_kde_nD): (nh, Q) values and the |w| scale."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    s, a = laplace_sums(x, z, hm, w, None, nthreads)
+    c = 1.0 / (2.0 ** d * n * np.prod(hm, axis=1))
+    return s[0] * c[:, None], a[0] * c[:, None]
+
+
+def kde_laplace_loo(x, h, w=None, nthreads=0):
+    """Leave-one-out density at every sample point: the kernel sum over
+    i != j normalised with N - 1 instead of N.  Returns (nh, N) and scale."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    s, a = laplace_sums(x, x, hm, w, np.arange(n), nthreads)
+    c = 1.0 / (2.0 ** d * (n - 1) * np.prod(hm, axis=1))
+    return s[0] * c[:, None], a[0] * c[:, None]
+
+
+def lcv(x, h, nthreads=0):
+    """Likelihood cross-validation score LCV(h) = (1/N) sum_j log fhat_{-j}(x_j)
+    for each bandwidth row of h.  Returns (nh,)."""
+    f, _ = kde_laplace_loo(x, h, None, nthreads)
+    with np.errstate(divide="ignore"):
+        return np.log(f).mean(axis=1)
+
+
+def nw_regression(x, y, z, h, nthreads=0):
+    """Nadaraya-Watson estimate m(z) = sum_i y_i K / sum_i K (Section 3.1,
+    weights w = response).  Returns (nh, Q)."""
+    x = _as_2d(x)
+    d = x.shape[0]
+    hm = _hmat(h, d)
+    s, _ = laplace_sums(x, z, hm, np.stack([np.ones_like(_f64(y)), _f64(y)]),
+                        None, nthreads)
+    return s[1] / s[0]
+
+
+def nw_loo(x, y, h, nthreads=0):
+    """Leave-one-out NW estimate at the sample points and the |y| scale of its
+    numerator: (m_loo, num, den, num_abs), each (nh, N)."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    y = _f64(y)
+    s, a = laplace_sums(x, x, hm, np.stack([np.ones_like(y), y]),
+                        np.arange(n), nthreads)
+    return s[1] / s[0], s[1], s[0], a[1]
+
+
+def nw_cv(x, y, h, nthreads=0):
+    """Squared-error LOO CV score CV(h) = (1/N) sum_j (y_j - m_{-j}(x_j))^2."""
+    m, _, _, _ = nw_loo(x, y, h, nthreads)
+    return ((_f64(y)[None, :] - m) ** 2).mean(axis=1)

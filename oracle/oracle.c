@@ -1,0 +1,192 @@
+/*
+ * Brute-force CPU oracle for the generalized multivariate ECDF / ESF and the
+ * Laplacian-kernel sums of Langrene & Warin, "Fast multivariate empirical
+ * cumulative distribution function with connection to kernel density
+ * estimation" (arXiv 2005.03246).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain definition written out:
+ * a double loop over (query, data point) with no sorting, no blocking, no
+ * decomposition.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the GPU library never does, and the two share
+ * no code.
+ *
+ * Floating-point sums use Neumaier's compensated summation (a textbook
+ * refinement of Kahan's) so that the oracle's own rounding error stays near
+ * one ulp of the result even for 2^24 terms.  Every weighted sum is returned
+ * together with the same sum taken over |weight|, which is the scale that
+ * GPU-vs-oracle errors are normalised by.
+ *
+ * Build: gcc -O2 -fopenmp -fPIC -shared oracle.c -o liboracle.so -lm
+ * (no -ffast-math: the compensated sums rely on IEEE evaluation order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double s; /* running sum          */
+    double c; /* running compensation */
+} nsum_t;
+
+static inline void nsum_add(nsum_t *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static inline double nsum_get(const nsum_t *a) { return a->s + a->c; }
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * Weighted dominance sums, the sums inside eq. (ECDF) and eq. (ESF) of
+ * Section 1 without the 1/N factor (the caller divides, as Remark 2.1
+ * suggests, so that integer weights give exact results).
+ *
+ *   survival == 0 :  S_q = sum_i y_i * prod_k [ x_{k,i} <= z_{k,q} ]   (ECDF)
+ *   survival != 0 :  S_q = sum_i y_i * prod_k [ x_{k,i} >  z_{k,q} ]   (ESF)
+ *
+ * Layout: x[k*N + i] (d x N), z[k*Q + q] (d x Q).  Comparisons are IEEE:
+ * a NaN coordinate makes both <= and > false.
+ *
+ * y == NULL : y_i = 1 and the integer count goes to out_cnt[q].
+ * y != NULL : out_sum[q] = compensated S_q, out_abs[q] = same with |y_i|.
+ */
+int oracle_dominance(int d, int64_t N, const double *x, const double *y,
+                     int64_t Q, const double *z, int survival,
+                     int64_t *out_cnt, double *out_sum, double *out_abs,
+                     int nthreads)
+{
+    if (d < 1 || N < 0 || Q < 0 || !x || !z)
+        return -1;
+    if (!y && !out_cnt)
+        return -1;
+    if (y && (!out_sum || !out_abs))
+        return -1;
+    set_threads(nthreads);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < Q; ++q) {
+        int64_t cnt = 0;
+        nsum_t s = {0.0, 0.0}, a = {0.0, 0.0};
+        for (int64_t i = 0; i < N; ++i) {
+            int inside = 1;
+            for (int k = 0; k < d && inside; ++k) {
+                double xi = x[(int64_t)k * N + i];
+                double zq = z[(int64_t)k * Q + q];
+                inside = survival ? (xi > zq) : (xi <= zq);
+            }
+            if (!inside)
+                continue;
+            if (y) {
+                nsum_add(&s, y[i]);
+                nsum_add(&a, fabs(y[i]));
+            } else {
+                ++cnt;
+            }
+        }
+        if (y) {
+            out_sum[q] = nsum_get(&s);
+            out_abs[q] = nsum_get(&a);
+        } else {
+            out_cnt[q] = cnt;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Laplacian kernel sums, the sum inside eq. (Laplacian_kde_nD) of Section 3.1
+ * without its normalising constant 1/(2^d N prod_k h_k):
+ *
+ *   S[c][b][q] = sum_{i != skip[q]} w_c,i * exp( - sum_k |x_{k,i} - z_{k,q}| / h_{b,k} )
+ *   A[c][b][q] = same with |w_c,i|
+ *
+ * for nw weight channels w[c*N + i] (w == NULL: one channel of ones) and nh
+ * bandwidth vectors h[b*d + k].  skip == NULL excludes nothing; skip[q] = i
+ * leaves data point i out of query q (leave-one-out at the sample points).
+ * Output index: (c*nh + b)*Q + q.
+ */
+int oracle_laplace_sums(int d, int64_t N, const double *x, int nw,
+                        const double *w, int64_t Q, const double *z, int nh,
+                        const double *h, const int64_t *skip,
+                        double *out_sum, double *out_abs, int nthreads)
+{
+    if (d < 1 || N < 0 || Q < 0 || nh < 1 || !x || !z || !h || !out_sum ||
+        !out_abs)
+        return -1;
+    if (w == NULL)
+        nw = 1;
+    if (nw < 1 || nw > 8 || nh > 4096)
+        return -1;
+    for (int b = 0; b < nh; ++b)
+        for (int k = 0; k < d; ++k)
+            if (!(h[b * d + k] > 0.0))
+                return -1;
+    set_threads(nthreads);
+
+#pragma omp parallel
+    {
+        /* per-thread accumulators: nw * nh of them */
+        nsum_t acc_s[8 * 64], acc_a[8 * 64];
+        for (int b0 = 0; b0 < nh; b0 += 64) {
+            int nb = nh - b0 < 64 ? nh - b0 : 64;
+#pragma omp for schedule(dynamic, 8)
+            for (int64_t q = 0; q < Q; ++q) {
+                for (int t = 0; t < nw * nb; ++t) {
+                    acc_s[t].s = acc_s[t].c = 0.0;
+                    acc_a[t].s = acc_a[t].c = 0.0;
+                }
+                int64_t sk = skip ? skip[q] : -1;
+                for (int64_t i = 0; i < N; ++i) {
+                    if (i == sk)
+                        continue;
+                    for (int b = 0; b < nb; ++b) {
+                        double e = 0.0;
+                        for (int k = 0; k < d; ++k)
+                            e += fabs(x[(int64_t)k * N + i] -
+                                      z[(int64_t)k * Q + q]) /
+                                 h[(b0 + b) * d + k];
+                        double kv = exp(-e);
+                        for (int c = 0; c < nw; ++c) {
+                            double wc = w ? w[(int64_t)c * N + i] : 1.0;
+                            nsum_add(&acc_s[c * nb + b], wc * kv);
+                            nsum_add(&acc_a[c * nb + b], fabs(wc) * kv);
+                        }
+                    }
+                }
+                for (int c = 0; c < nw; ++c)
+                    for (int b = 0; b < nb; ++b) {
+                        int64_t o = ((int64_t)c * nh + b0 + b) * Q + q;
+                        out_sum[o] = nsum_get(&acc_s[c * nb + b]);
+                        out_abs[o] = nsum_get(&acc_a[c * nb + b]);
+                    }
+            }
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,242 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics
+(hand-enumerated cases, textbook reductions, closed forms, invariants), so that
+the oracle is trusted before any GPU result is compared with it."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+# ---------------------------------------------------------------- ECDF / ESF
+def test_hand_points_d2(golden):
+    g = golden["points_d2"]
+    x = np.array(g["x"], dtype=float)
+    y = np.array(g["y"], dtype=float)
+    assert list(oracle.ecdf(x, x)) == g["ecdf_counts"]
+    assert list(oracle.esf(x, x)) == g["esf_counts"]
+    s, _ = oracle.dominance_sums(x, x, y)
+    assert list(s) == g["ecdf_weighted_sums"]
+    s, _ = oracle.dominance_sums(x, x, y, survival=True)
+    assert list(s) == g["esf_weighted_sums"]
+    f, _ = oracle.ecdf(x, x, y)
+    np.testing.assert_array_equal(f, np.array(g["ecdf_weighted_sums"]) / 5.0)
+
+
+def test_hand_grid_d2(golden):
+    g = golden["grid_d2"]
+    x = np.array(g["x"], dtype=float)
+    z = oracle.grid_points(g["nodes"])
+    assert oracle.ecdf(x, z).reshape(3, 3).tolist() == g["ecdf_counts"]
+    assert oracle.esf(x, z).reshape(3, 3).tolist() == g["esf_counts"]
+
+
+def test_d1_matches_searchsorted():
+    """d = 1: the ECDF count is the upper-bound rank in the sorted sample."""
+    g = np.random.default_rng(1)
+    x = np.round(g.normal(size=3000), 2)  # ties on purpose
+    z = np.concatenate([np.round(g.normal(size=500), 2), x[:200], [-np.inf, np.inf]])
+    xs = np.sort(x)
+    want = np.searchsorted(xs, z, side="right")
+    np.testing.assert_array_equal(oracle.ecdf(x, z), want)
+    np.testing.assert_array_equal(oracle.esf(x, z), x.size - want)
+
+
+def test_inclusion_exclusion_d2_d3():
+    """ESF(z) = sum over subsets S of (-1)^|S| ECDF_S(z_S) for counts, where
+    ECDF_S only constrains the coordinates in S (ECDF of the empty set = N)."""
+    g = np.random.default_rng(2)
+    for d in (2, 3):
+        x = np.round(g.normal(size=(d, 800)), 1)
+        z = np.concatenate([np.round(g.normal(size=(d, 300)), 1), x[:, :50]], axis=1)
+        n = x.shape[1]
+        total = np.zeros(z.shape[1], dtype=np.int64)
+        for mask in range(1 << d):
+            ks = [k for k in range(d) if mask >> k & 1]
+            term = np.full(z.shape[1], n, dtype=np.int64) if not ks else oracle.ecdf(x[ks], z[ks])
+            total += (-1) ** len(ks) * term
+        np.testing.assert_array_equal(oracle.esf(x, z), total)
+
+
+def test_grid_invariants():
+    g = np.random.default_rng(3)
+    x = g.normal(size=(3, 2000))
+    y = g.integers(-3, 4, size=2000).astype(float)
+    nodes = [np.linspace(x[k].min(), x[k].max(), 7) for k in range(3)]
+    for k in range(3):
+        nodes[k][-1] = x[k].max()
+    z = oracle.grid_points(nodes)
+    cnt = oracle.ecdf(x, z).reshape(7, 7, 7)
+    bar = oracle.esf(x, z).reshape(7, 7, 7)
+    for ax in range(3):
+        assert np.all(np.diff(cnt, axis=ax) >= 0)
+        assert np.all(np.diff(bar, axis=ax) <= 0)
+    assert cnt[-1, -1, -1] == x.shape[1]      # top corner dominates every point
+    assert bar[-1, -1, -1] == 0
+    f, a = oracle.ecdf(x, z, y)
+    assert f.reshape(7, 7, 7)[-1, -1, -1] == pytest.approx(y.sum() / x.shape[1], abs=0)
+    # integer weights: exact multiples of 1/N (Remark on the 1/N scaling)
+    s, _ = oracle.dominance_sums(x, z, y)
+    assert np.all(s == np.round(s))
+    # ESF below every data point is the total
+    zlow = np.full((3, 1), -1e300)
+    assert oracle.esf(x, zlow)[0] == x.shape[1]
+
+
+def test_ties_and_strictness():
+    x = np.array([[1.0, 1.0, 2.0], [5.0, 6.0, 5.0]])
+    z = np.array([[1.0], [5.0]])
+    assert oracle.ecdf(x, z)[0] == 1          # (1,5) itself, <= in both
+    assert oracle.esf(x, z)[0] == 0           # (2,5): x2 = 5 is not > 5
+    z2 = np.array([[0.5], [4.0]])
+    assert oracle.esf(x, z2)[0] == 3
+
+
+def test_nan_semantics():
+    x = np.array([[0.0, np.nan, 1.0], [0.0, 0.0, 1.0]])
+    z = np.array([[2.0, np.nan], [2.0, 2.0]])
+    np.testing.assert_array_equal(oracle.ecdf(x, z), [2, 0])
+    np.testing.assert_array_equal(oracle.esf(x, np.array([[-1.0], [-1.0]])), [2])
+
+
+def test_permutation_and_monotone_transform_invariance():
+    g = np.random.default_rng(4)
+    x = np.round(g.normal(size=(3, 1500)), 1)
+    z = np.round(g.normal(size=(3, 200)), 1)
+    c = oracle.ecdf(x, z)
+    p = g.permutation(x.shape[1])
+    np.testing.assert_array_equal(oracle.ecdf(x[:, p], z), c)
+    # a strictly increasing map applied to both data and queries
+    np.testing.assert_array_equal(oracle.ecdf(np.exp(x) ** 3, np.exp(z) ** 3), c)
+    e = oracle.esf(x, z)
+    np.testing.assert_array_equal(oracle.esf(np.arctan(x), np.arctan(z)), e)
+
+
+def test_additivity_in_y():
+    g = np.random.default_rng(5)
+    x = g.normal(size=(2, 1000))
+    z = g.normal(size=(2, 100))
+    y1 = g.integers(-5, 6, 1000).astype(float)
+    y2 = g.integers(-5, 6, 1000).astype(float)
+    s1, _ = oracle.dominance_sums(x, z, y1)
+    s2, _ = oracle.dominance_sums(x, z, y2)
+    s12, _ = oracle.dominance_sums(x, z, y1 + y2)
+    np.testing.assert_array_equal(s1 + s2, s12)
+
+
+def test_compensated_sum_is_near_exact():
+    """Weighted sums with heavy cancellation agree with math.fsum (exactly
+    rounded) to a couple of ulps of the magnitude scale."""
+    g = np.random.default_rng(6)
+    n = 20000
+    x = g.random((2, n))
+    big = g.normal(size=n) * 1e12
+    y = np.concatenate([big, -big]) + np.concatenate([g.normal(size=n), g.normal(size=n)])
+    x2 = np.concatenate([x, x], axis=1)
+    z = g.random((2, 40))
+    s, a = oracle.dominance_sums(x2, z, y)
+    for q in range(z.shape[1]):
+        sel = np.all(x2 <= z[:, q:q + 1], axis=0)
+        exact = math.fsum(y[sel])
+        assert abs(s[q] - exact) <= 4 * np.finfo(float).eps * abs(exact) + 1e-30 * a[q]
+
+
+# ---------------------------------------------------------------- Laplacian KDE
+def test_kde_hand_d1(golden):
+    g = golden["kde_d1"]
+    x = np.array([g["x"]])
+    f, _ = oracle.kde_laplace(x, np.array([[g["z"]]]), g["h"])
+    assert f[0, 0] == pytest.approx(g["f"], rel=1e-15)
+    floo, _ = oracle.kde_laplace_loo(x, g["h"])
+    assert floo[0, 0] == pytest.approx(g["f_loo_point0"], rel=1e-15)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_kde_single_point_closed_form(d):
+    g = np.random.default_rng(7)
+    x = g.normal(size=(d, 1))
+    z = g.normal(size=(d, 5))
+    h = g.uniform(0.2, 2.0, size=(1, d))
+    f, _ = oracle.kde_laplace(x, z, h, w=np.array([2.5]))
+    want = 2.5 * np.exp(-np.sum(np.abs(x - z) / h[0][:, None], axis=0)) / (2 ** d * np.prod(h))
+    np.testing.assert_allclose(f[0], want, rtol=1e-15)
+
+
+def test_kde_d1_two_sided_recursion():
+    """d = 1: on sorted data the kernel sum splits into a forward and a backward
+    exponentially-decayed running sum (the recursion behind the 1-D
+    decomposition of Section 3.1)."""
+    g = np.random.default_rng(8)
+    x = np.sort(g.normal(size=2000))
+    w = g.uniform(0.5, 2.0, size=2000)
+    h = 0.3
+    n = x.size
+    fwd = np.zeros(n)
+    bwd = np.zeros(n)
+    fwd[0] = w[0]
+    for j in range(1, n):
+        fwd[j] = np.exp(-(x[j] - x[j - 1]) / h) * fwd[j - 1] + w[j]
+    for j in range(n - 2, -1, -1):
+        bwd[j] = np.exp(-(x[j + 1] - x[j]) / h) * (bwd[j + 1] + w[j + 1])
+    want = (fwd + bwd) / (2 * h * n)
+    f, _ = oracle.kde_laplace(x[None, :], x[None, :], h, w=w)
+    np.testing.assert_allclose(f[0], want, rtol=1e-12)
+
+
+def test_kde_product_set_separates():
+    """Data on a Cartesian product with product weights: the d-dimensional
+    Laplacian KDE is the product of the 1-D ones."""
+    g = np.random.default_rng(9)
+    a = g.normal(size=30)
+    b = g.normal(size=20)
+    wa = g.uniform(0.5, 1.5, 30)
+    wb = g.uniform(0.5, 1.5, 20)
+    x = np.stack([np.repeat(a, 20), np.tile(b, 30)])
+    w = np.repeat(wa, 20) * np.tile(wb, 30)
+    z = g.normal(size=(2, 25))
+    h = np.array([[0.4, 0.7]])
+    f2, _ = oracle.kde_laplace(x, z, h, w=w)
+    fa, _ = oracle.kde_laplace(a[None, :], z[:1], 0.4, w=wa)
+    fb, _ = oracle.kde_laplace(b[None, :], z[1:], 0.7, w=wb)
+    np.testing.assert_allclose(f2[0], fa[0] * fb[0], rtol=1e-13)
+
+
+def test_kde_large_h_limit_and_multi_h():
+    g = np.random.default_rng(10)
+    x = g.normal(size=(2, 300))
+    z = g.normal(size=(2, 10))
+    hs = np.array([1e6, 2e6])
+    f, _ = oracle.kde_laplace(x, z, hs)
+    np.testing.assert_allclose(f, 1.0 / (4 * hs[:, None] ** 2) * np.ones((2, 10)), rtol=1e-5)
+
+
+def test_loo_and_lcv_two_points():
+    x = np.array([[0.0, 0.5], [0.0, 1.0]])
+    h = 0.5
+    k = np.exp(-(0.5 + 1.0) / h)
+    # each point's LOO density is the other point's kernel with N-1 = 1
+    want = k / (4 * h * h)
+    floo, _ = oracle.kde_laplace_loo(x, h)
+    np.testing.assert_allclose(floo[0], [want, want], rtol=1e-15)
+    assert oracle.lcv(x, [h])[0] == pytest.approx(np.log(want), rel=1e-15)
+
+
+def test_nw_constant_and_cv():
+    g = np.random.default_rng(11)
+    x = g.normal(size=(2, 400))
+    y = np.full(400, 3.25)
+    m = oracle.nw_regression(x, y, g.normal(size=(2, 30)), [0.2, 1.0])
+    np.testing.assert_allclose(m, 3.25, rtol=1e-14)
+    assert np.allclose(oracle.nw_cv(x, y, [0.3]), 0.0, atol=1e-25)
+    # two points: the LOO estimate at one point is the other point's response
+    x2 = np.array([[0.0, 1.0]])
+    y2 = np.array([1.0, 3.0])
+    assert oracle.nw_cv(x2, y2, [0.7])[0] == pytest.approx(4.0, rel=1e-15)
+
+
+def test_far_points_underflow_exactly():
+    """x = (7, 7) vs (-7, -7) with h = 0.01: exp(-2800) is 0 in FP64."""
+    x = np.array([[7.0, -7.0], [7.0, -7.0]])
+    s, _ = oracle.laplace_sums(x, x, 0.01)
+    np.testing.assert_array_equal(s[0, 0], [1.0, 1.0])
