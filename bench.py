@@ -1,0 +1,195 @@
+"""Benchmark of the grid path on one MI355X.
+
+Workload: generalized ECDF and ESF at every node of a 256^3 uniform grid
+spanning the data, from N = 2^24 points in d = 3 drawn from N(0, 0.5 I + 0.5 J)
+with weights y ~ N(0, 1) in float64 (synthetic, seeded).  One step = one
+ecdf_esf_grid call (cell keys, stable radix binning, per-line binning with the
+last-axis scans, the two remaining axis scans), inputs resident in HBM.
+
+Prints one JSON line: throughput in Gpoint-evals/s (2 * 256^3 evaluations per
+step: ECDF and ESF at every node), the dominant kernel's roofline figures
+from HIP events recorded on the library's stream during the timed steps, and
+the brute-force oracle timed on the host cores on a bounded sample of nodes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoint-evals/s + %HBM peak; datasets/s learned-h vs 64-h grid search"
+HBM_PEAK_GBS = 8000.0
+M_NODES = 256
+LOG2N = 24
+
+# Algorithmic (compulsory) bytes per launch of each grid kernel, per point
+# (N) or per output node (G = 256^3) and per output array, float64 weights.
+#   grid_cellkey     reads x (24 B/pt), writes the packed cell key (4 B/pt)
+#   radix_scatter    reads key + y (12 B/pt), writes key + y (12 B/pt)
+#   radix_hist       reads the key (4 B/pt)
+#   grid_line        reads key + y (12 B/pt), writes 2 rows per line (2 * 8 B/node)
+#   grid_axis_scan   reads and writes one array (16 B/node) per launch
+def algorithmic_bytes(kernel: str, n: int, g: int, ysize: int, launches_per_step: int):
+    if kernel == "grid_cellkey":
+        return n * (24 + 4)
+    if kernel == "radix_scatter":
+        return n * 2 * (4 + ysize)
+    if kernel == "radix_hist":
+        return n * 4
+    if kernel == "grid_line":
+        return n * (4 + ysize) + 2 * g * ysize
+    if kernel == "grid_axis_scan":
+        # one ProfScope covers the ECDF and the ESF launch of one axis
+        return 2 * 2 * g * ysize
+    return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=["f64", "f32c"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(x, y, nodes, target_s):
+    """The brute-force oracle on a bounded sample of grid nodes (ECDF and ESF
+    at each sampled node, full N), scaled to Gpoint-evals/s."""
+    import numpy as np
+
+    import oracle
+
+    g = np.random.default_rng(99)
+    d = x.shape[0]
+
+    def run(count):
+        idx = np.stack([g.integers(0, M_NODES, size=count) for _ in range(d)], 1)
+        z = oracle.grid_points(nodes, idx)
+        t0 = time.perf_counter()
+        oracle.ecdf(x, z, y)
+        oracle.esf(x, z, y)
+        return time.perf_counter() - t0
+
+    t = run(16)
+    count = int(max(16, min(8192, 16 * target_s / max(t, 1e-3))))
+    t = run(count)
+    return {
+        "value": 2 * count / t / 1e9,
+        "unit": "Gpoint-evals/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": "ECDF+ESF at %d random nodes of the 256^3 grid over all 2^24 "
+                  "points (%.1f s)" % (count, t),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported "
+              "(the multi-GPU layout is described, not built)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2005_03246_amd import datagen, mecdf
+
+    torch.cuda.set_device(0)
+    x, y, nodes = datagen.config2(n=1 << LOG2N, m=M_NODES)
+    n = x.shape[1]
+    xt = torch.from_numpy(x).cuda()
+    if args.prec == "f64":
+        yt = torch.from_numpy(y).cuda()
+        ysize = 8
+    else:
+        yt = torch.from_numpy(y.astype(np.float32)).cuda()
+        ysize = 4
+    G = M_NODES ** 3
+    F = torch.empty((M_NODES,) * 3, dtype=yt.dtype, device="cuda")
+    Fb = torch.empty_like(F)
+    ms, zs, _ = mecdf._grid_args(nodes)
+    p = mecdf.MECDF_F64 if args.prec == "f64" else mecdf.MECDF_F32C
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc = mecdf.raw.ecdf_esf_grid(3, n, mecdf._ptr(xt), mecdf._ptr(yt), ms, zs,
+                                     mecdf._ptr(F), mecdf._ptr(Fb), p,
+                                     mecdf._stream_ptr(stream))
+        if rc != 0:
+            raise mecdf.MecdfError(rc, "ecdf_esf_grid")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    mecdf.profile_reset()
+    mecdf.profile_enable(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mecdf.profile_enable(False)
+    kern = mecdf.profile_collect()
+    ms_total = start.elapsed_time(end)
+    ms_step = ms_total / args.steps
+    value = 2.0 * G / (ms_step * 1e-3) / 1e9
+
+    # dominant kernel by total time over the timed steps
+    dom = max(kern.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dlaunch) = dom
+    avg_ms = dms / dlaunch
+    ab = algorithmic_bytes(dname, n, G, ysize, dlaunch // args.steps)
+    roof = {"bound": "hbm", "kernel": dname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "achieved": None, "frac": None, "traffic": None,
+            "avg_launch_ms": avg_ms}
+    if ab is not None:
+        gbs = ab / (avg_ms * 1e-3) / 1e9
+        roof.update(achieved=gbs, frac=gbs / HBM_PEAK_GBS,
+                    algorithmic_bytes_per_launch=ab)
+    kernels = {k: {"total_ms_per_step": v[0] / args.steps,
+                   "launches_per_step": v[1] / args.steps} for k, v in kern.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpoint-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "grid ECDF+ESF, d=3, N=2^24, x~N(0,0.5I+0.5J), y~N(0,1), "
+                        "uniform 256^3 grid over per-axis min..max",
+            "N": n, "d": 3, "grid": [M_NODES] * 3, "prec": args.prec,
+        },
+        "roofline": roof,
+        "kernels": kernels,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * mecdf.h -- C ABI of libmecdf, exact multivariate ECDF / ESF and Laplacian
+ * kernel sums on an AMD MI355X (gfx950) GPU.
+ *
+ * Method: Langrene & Warin, "Fast multivariate empirical cumulative
+ * distribution function with connection to kernel density estimation",
+ * arXiv 2005.03246.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Data layout.  Sample points are passed structure-of-arrays as a device
+ * array x of d*N doubles with x[k*N + i] = coordinate k of point i (the
+ * paper's x_{k,i}, Section 1).  x is always float64: membership is decided by
+ * exact comparisons in the input precision and x is never converted.
+ *
+ * Weights.  y (or w) is a device array of N values.  With prec == MECDF_F64
+ * it holds doubles and results are doubles; with prec == MECDF_F32C it holds
+ * floats and results are floats, accumulated with Kahan compensation.  Where
+ * an entry point accepts y == NULL, y is taken as 1 and the result is the raw
+ * integer count (int64, no 1/N factor): the classical ECDF of Section 1
+ * times N.
+ *
+ * Ownership.  The caller owns every buffer.  Device pointers must point to
+ * memory on the current HIP device; host pointers (grid sizes, nodes,
+ * bandwidths) are read before the call returns.  The library owns only an
+ * internal per-device workspace, grown on demand and kept until
+ * mecdf_release(); the environment variable MECDF_WORKSPACE_LIMIT (bytes)
+ * caps it.
+ *
+ * Streams.  stream is a hipStream_t (NULL = the default stream).  Work is
+ * enqueued on it in order and the call returns without waiting for the GPU,
+ * except where a comment says otherwise.  Two calls that overlap in time on
+ * one device share the workspace and race; issue them on one stream.
+ *
+ * Errors.  Every int-returning function returns MECDF_OK (0) or a negative
+ * code.  Argument errors are detected on the host before anything is
+ * enqueued and leave the outputs untouched.  A HIP runtime failure returns
+ * MECDF_EDEVICE.  mecdf_last_error() gives a message for the calling thread's
+ * most recent failure.  NaN inputs are not errors: they follow IEEE
+ * comparisons (a NaN coordinate makes both <= and > false), so a point with a
+ * NaN coordinate counts for no query and a NaN query counts nothing.
+ */
+#ifndef MECDF_H
+#define MECDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MECDF_OK = 0,
+    MECDF_EINVAL = -1,       /* invalid argument                          */
+    MECDF_ENOMEM = -2,       /* workspace allocation failed or over limit */
+    MECDF_EDEVICE = -3,      /* HIP runtime error                         */
+    MECDF_EUNSUPPORTED = -4  /* valid but outside the supported sizes     */
+};
+
+enum {
+    MECDF_F64 = 0,  /* float64 weights and results                        */
+    MECDF_F32C = 1  /* float32 weights and results, compensated summation */
+};
+
+/* Largest supported dimension d (the paper's experiments go up to 6). */
+#define MECDF_MAX_DIM 6
+
+const char *mecdf_strerror(int code);
+const char *mecdf_last_error(void);
+
+/*
+ * ecdf_grid -- generalized ECDF at every node of a rectilinear grid.
+ *
+ * Computes F_N(z) = (1/N) sum_i y_i 1{x_{1,i} <= z_1, ..., x_{d,i} <= z_d}
+ * (eq. (ECDF), Section 1) at the M_1 x ... x M_d nodes of the grid of
+ * Section 2.1, through the local sums of eq. (partial_sums) and the d-fold
+ * prefix sum of eq. (ECDF_decomposition).
+ *
+ *   d      1..MECDF_MAX_DIM
+ *   N      number of sample points (>= 1; 0 is allowed only with y == NULL)
+ *   x      device, d*N doubles, x[k*N + i]
+ *   y      device, N weights (double or float per prec) or NULL for counts
+ *   M      host, d grid sizes M_k >= 1
+ *   z      host, sum(M_k) doubles: the nodes of axis 0, then axis 1, ...;
+ *          each axis strictly increasing and finite
+ *   F      device, prod(M_k) results in C order (last axis fastest):
+ *          int64 counts (y == NULL), else double/float F_N
+ *   prec   MECDF_F64 or MECDF_F32C (ignored when y == NULL)
+ *
+ * Limits: prod(M_k + 1) < 2^31 cells and M_d <= 4000.  Results are
+ * deterministic: the same inputs give bitwise-equal outputs.
+ */
+int ecdf_grid(int d, int64_t N, const double *x, const void *y,
+              const int64_t *M, const double *z, void *F, int prec,
+              void *stream);
+
+/*
+ * esf_grid -- generalized ESF (eq. (ESF), Section 1) at every grid node:
+ * Fbar_N(z) = (1/N) sum_i y_i 1{x_{1,i} > z_1, ..., x_{d,i} > z_d}, strict in
+ * every coordinate.  It equals the ECDF of the reflected data with the strict
+ * inequality (Section 1, eq. (ECDFdelta) with delta = -1) and is obtained
+ * from the same local sums with suffix sums.  Arguments as ecdf_grid, with
+ * the result written to Fbar.
+ */
+int esf_grid(int d, int64_t N, const double *x, const void *y,
+             const int64_t *M, const double *z, void *Fbar, int prec,
+             void *stream);
+
+/*
+ * ecdf_esf_grid -- both of the above from one binning pass.  Either output
+ * pointer may be NULL (then that function is skipped); not both.
+ */
+int ecdf_esf_grid(int d, int64_t N, const double *x, const void *y,
+                  const int64_t *M, const double *z, void *F, void *Fbar,
+                  int prec, void *stream);
+
+/*
+ * ecdf_points -- generalized ECDF at the sample points themselves
+ * (Section 2.2): F[j] = F_N(x_j) = (1/N) sum_i y_i 1{x_i <= x_j componentwise}.
+ * Unlike the recursion's own output in Section 2.2, which leaves the point
+ * itself out and uses strict inequalities, the result follows eq. (ECDF)
+ * literally: <= in every coordinate, the point itself and exact duplicates
+ * included.
+ *
+ *   x   device, d*N doubles;  y  device N weights or NULL (int64 counts)
+ *   F   device, N results in input order
+ */
+int ecdf_points(int d, int64_t N, const double *x, const void *y, void *F,
+                int prec, void *stream);
+
+/*
+ * esf_points -- generalized ESF at the sample points (eq. (ESF) with z = x_j):
+ * F[j] = (1/N) sum_i y_i 1{x_i > x_j strictly in every coordinate}.
+ * Arguments as ecdf_points.
+ */
+int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
+               int prec, void *stream);
+
+/*
+ * kde_laplace -- weighted Laplacian-kernel density estimate at the sample
+ * points for nh bandwidth vectors (eq. (Laplacian_kde_nD), Section 3.1),
+ * evaluated through the 2^d sign-orthant ECDF decomposition of
+ * eq. (Laplacian_decomposition_nD) with all orthants in one recursion
+ * (Appendix D):
+ *
+ *   f[b*N + j] = 1/(2^d N prod_k h_{b,k}) sum_i w_i exp(-sum_k |x_{k,i} - x_{k,j}| / h_{b,k})
+ *
+ * (the point itself included, kernel value 1 at distance 0), and the
+ * likelihood cross-validation score
+ *
+ *   lcv[b] = (1/N) sum_j log fhat_{-j}(x_j),
+ *   fhat_{-j} = 1/(2^d (N-1) prod_k h_{b,k}) sum_{i != j} w_i exp(...).
+ *
+ *   d     1..3
+ *   N     >= 2
+ *   x     device d*N doubles
+ *   w     device N doubles (float with MECDF_F32C) or NULL for w = 1
+ *   nh    number of bandwidth vectors, 1..256
+ *   h     host, nh*d positive finite doubles, h[b*d + k]
+ *   f     device nh*N results (double, or float with MECDF_F32C) or NULL
+ *   lcv   device nh doubles or NULL
+ */
+int kde_laplace(int d, int64_t N, const double *x, const void *w, int nh,
+                const double *h, void *f, double *lcv, int prec, void *stream);
+
+/*
+ * kreg_laplace -- Nadaraya-Watson kernel regression with the Laplacian
+ * kernel at the sample points (weights w = response, Section 3.1):
+ *
+ *   m[b*N + j] = sum_i y_i K_b(x_i - x_j) / sum_i K_b(x_i - x_j)   (self included)
+ *   cv[b]      = (1/N) sum_j (y_j - m_{-j})^2,  m_{-j} the same ratio over i != j
+ *
+ * Arguments as kde_laplace with y the response (required).
+ */
+int kreg_laplace(int d, int64_t N, const double *x, const void *y, int nh,
+                 const double *h, void *m, double *cv, int prec, void *stream);
+
+/* Frees the workspace of every device (synchronises those devices). */
+void mecdf_release(void);
+
+/*
+ * Kernel timing support for benchmarks (not part of the method).  While
+ * enabled, every kernel launch of the entry points above is bracketed by a
+ * pair of HIP events on the caller's stream.  mecdf_profile_collect waits for
+ * the recorded events and writes, for up to max distinct kernel names in
+ * launch order, the name (64 bytes each, NUL-terminated, into names), the
+ * summed duration in milliseconds and the launch count; it returns the number
+ * of names written or a negative error.  mecdf_profile_reset forgets the
+ * records.  Not thread-safe against concurrent entry-point calls.
+ */
+int mecdf_profile_enable(int on);
+void mecdf_profile_reset(void);
+int mecdf_profile_collect(int max, char *names, double *total_ms,
+                          int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MECDF_H */

@@ -1,0 +1,324 @@
+// Stable least-significant-digit radix sort on integer keys with an optional
+// payload, written for 64-lane wavefronts.
+//
+// One pass sorts by the digit (key >> shift) & (2^bits - 1), bits <= 9:
+//   1. k_radix_hist    per-tile digit counts (tile = 4096 keys), digit-major
+//   2. exclusive scan  over the digit-major count table -> global offsets
+//   3. k_radix_scatter per-tile stable ranks from wave ballots, staging of the
+//                      tile in LDS in digit order, then coalesced writes
+// Stability (equal digits keep their input order) makes the result, and
+// everything computed from it, deterministic.
+#pragma once
+
+#include "common.hpp"
+
+namespace mecdf {
+
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys
+constexpr int kRadixMaxBits = 9;
+constexpr int kRadixMaxDigits = 1 << kRadixMaxBits;
+
+struct NoPayload {};
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_radix_hist(const K *__restrict__ keys,
+                                                    int64_t n, int shift,
+                                                    int bits,
+                                                    uint32_t *__restrict__ hist,
+                                                    int64_t ntiles) {
+    __shared__ uint32_t h[kRadixMaxDigits];
+    const int R = 1 << bits;
+    for (int i = threadIdx.x; i < R; i += 256)
+        h[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll 4
+    for (int it = 0; it < kRadixItems; ++it) {
+        int64_t p = base + (int64_t)it * 256 + threadIdx.x;
+        if (p < n) {
+            uint32_t dg = (uint32_t)(keys[p] >> shift) & (uint32_t)(R - 1);
+            atomicAdd(&h[dg], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < R; i += 256)
+        hist[(int64_t)i * ntiles + blockIdx.x] = h[i];
+}
+
+// ---- block-wide exclusive scan of 256 thread values (4 waves) -------------
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan256(T v, T *wtot /*[4]*/,
+                                                    T *total) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(v);
+    if (lane == 63)
+        wtot[w] = inc;
+    __syncthreads();
+    T off = T(0);
+    for (int i = 0; i < w; ++i)
+        off = off + wtot[i];
+    if (total)
+        *total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    T r = off + inc - v;
+    __syncthreads();
+    return r;
+}
+
+// ---- device-wide exclusive scan of uint32 (reduce, scan sums, apply) -----
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = 256 * kScanItems;
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in,
+                                                     int64_t n,
+                                                     uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t wt[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t p = base + (int64_t)i * 256 + threadIdx.x;
+        if (p < n)
+            s += in[p];
+    }
+    uint32_t tot;
+    block_exclusive_scan256<uint32_t>(s, wt, &tot);
+    if (threadIdx.x == 0)
+        bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(uint32_t *__restrict__ bsum,
+                                                   int64_t nb) {
+    __shared__ uint32_t wt[4];
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+        int64_t p = c0 + threadIdx.x;
+        uint32_t v = p < nb ? bsum[p] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan256<uint32_t>(v, wt, &tot);
+        if (p < nb)
+            bsum[p] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in,
+                                                    uint32_t *__restrict__ out,
+                                                    int64_t n,
+                                                    const uint32_t *__restrict__ bsum) {
+    __shared__ uint32_t wt[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    // blocked arrangement: thread t owns items [t*8, t*8+8)
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t p = base + (int64_t)threadIdx.x * kScanItems + i;
+        v[i] = p < n ? in[p] : 0u;
+        s += v[i];
+    }
+    uint32_t ex = block_exclusive_scan256<uint32_t>(s, wt, nullptr) + bsum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t p = base + (int64_t)threadIdx.x * kScanItems + i;
+        if (p < n)
+            out[p] = ex;
+        ex += v[i];
+    }
+}
+
+inline int scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
+                              uint32_t *bsum, hipStream_t s) {
+    int64_t nb = ceil_div(n, kScanBlock);
+    if (nb == 0)
+        return MECDF_OK;
+    ProfScope ps("scan_u32", s);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, bsum, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, out, n, bsum);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
+inline size_t scan_bsum_count(int64_t n) { return (size_t)ceil_div(n, kScanBlock) + 1; }
+
+// ---- scatter ---------------------------------------------------------------
+template <typename K, typename P>
+__global__ __launch_bounds__(256) void k_radix_scatter(
+    const K *__restrict__ kin, const P *__restrict__ pin, K *__restrict__ kout,
+    P *__restrict__ pout, const uint32_t *__restrict__ offs, int64_t n,
+    int shift, int bits, int64_t ntiles) {
+    constexpr bool kPay = !std::is_same<P, NoPayload>::value;
+    constexpr int kPaySize = kPay ? (int)sizeof(P) : 1;
+    __shared__ uint32_t wcnt[4][kRadixMaxDigits];
+    __shared__ uint32_t loff[kRadixMaxDigits];
+    __shared__ uint32_t gbase[kRadixMaxDigits];
+    __shared__ uint32_t wt[4];
+    __shared__ K s_key[kRadixTile];
+    __shared__ char s_pay_raw[kRadixTile * kPaySize];
+    P *s_pay = reinterpret_cast<P *>(s_pay_raw);
+
+    const int R = 1 << bits;
+    const uint32_t mask = (uint32_t)(R - 1);
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kRadixTile;
+
+    for (int i = tid; i < R; i += 256) {
+        wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0;
+        gbase[i] = offs[(int64_t)i * ntiles + tile];
+    }
+    __syncthreads();
+
+    K key[kRadixItems];
+    P pay[kRadixItems];
+    uint32_t rank[kRadixItems];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        // wave w owns the contiguous run [w*16*64, (w+1)*16*64) of the tile
+        int64_t p = base + ((int64_t)(w * kRadixItems + r) << 6) + lane;
+        bool valid = p < n;
+        key[r] = valid ? kin[p] : K(0);
+        if constexpr (kPay)
+            pay[r] = valid ? pin[p] : P();
+        uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            bool bit = (dg >> b) & 1u;
+            uint64_t bal = __ballot(valid && bit);
+            peers &= bit ? bal : ~bal;
+        }
+        uint32_t before = valid ? wcnt[w][dg] : 0u;
+        uint32_t rk = (uint32_t)__popcll(peers & lt);
+        if (valid && rk == 0)
+            wcnt[w][dg] = before + (uint32_t)__popcll(peers);
+        rank[r] = valid ? before + rk : 0xffffffffu;
+    }
+    __syncthreads();
+
+    // per-digit offsets of each wave inside the tile, then digit offsets
+    uint32_t t0 = 0, t1 = 0;
+    {
+        int d0 = 2 * tid, d1 = 2 * tid + 1;
+        if (d0 < R) {
+            uint32_t s = 0;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t t = wcnt[q][d0];
+                wcnt[q][d0] = s;
+                s += t;
+            }
+            t0 = s;
+        }
+        if (d1 < R) {
+            uint32_t s = 0;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t t = wcnt[q][d1];
+                wcnt[q][d1] = s;
+                s += t;
+            }
+            t1 = s;
+        }
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan256<uint32_t>(t0 + t1, wt, &tot);
+    if (2 * tid < R)
+        loff[2 * tid] = ex;
+    if (2 * tid + 1 < R)
+        loff[2 * tid + 1] = ex + t0;
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        if (rank[r] != 0xffffffffu) {
+            uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
+            uint32_t lp = loff[dg] + wcnt[w][dg] + rank[r];
+            s_key[lp] = key[r];
+            if constexpr (kPay)
+                s_pay[lp] = pay[r];
+        }
+    }
+    __syncthreads();
+
+    for (uint32_t q = tid; q < tot; q += 256) {
+        K kk = s_key[q];
+        uint32_t dg = (uint32_t)(kk >> shift) & mask;
+        int64_t dst = (int64_t)gbase[dg] + (q - loff[dg]);
+        kout[dst] = kk;
+        if constexpr (kPay)
+            pout[dst] = s_pay[q];
+    }
+}
+
+// Workspace needed by radix_sort for n keys.
+inline void radix_plan(ArenaPlan &pl, int64_t n) {
+    int64_t nt = ceil_div(n, kRadixTile);
+    pl.add<uint32_t>((size_t)(nt * kRadixMaxDigits));
+    pl.add<uint32_t>(scan_bsum_count(nt * kRadixMaxDigits));
+}
+
+struct RadixScratch {
+    uint32_t *hist = nullptr;
+    uint32_t *bsum = nullptr;
+};
+
+inline RadixScratch radix_take(Arena &a, int64_t n) {
+    int64_t nt = ceil_div(n, kRadixTile);
+    RadixScratch r;
+    r.hist = a.take<uint32_t>((size_t)(nt * kRadixMaxDigits));
+    r.bsum = a.take<uint32_t>(scan_bsum_count(nt * kRadixMaxDigits));
+    return r;
+}
+
+// One stable pass from (kin, pin) to (kout, pout).
+template <typename K, typename P>
+int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
+               int shift, int bits, const RadixScratch &rs, hipStream_t s) {
+    if (n <= 0)
+        return MECDF_OK;
+    int64_t nt = ceil_div(n, kRadixTile);
+    int R = 1 << bits;
+    {
+        ProfScope ps("radix_hist", s);
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nt), dim3(256), 0, s,
+                           kin, n, shift, bits, rs.hist, nt);
+    }
+    MECDF_TRY(scan_exclusive_u32(rs.hist, rs.hist, nt * R, rs.bsum, s));
+    {
+        ProfScope ps("radix_scatter", s);
+        hipLaunchKernelGGL((k_radix_scatter<K, P>), dim3((unsigned)nt), dim3(256), 0,
+                           s, kin, pin, kout, pout, rs.hist, n, shift, bits, nt);
+    }
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
+// Stable sort by key bits [lo, hi).  Data start in (k0, p0) (which may be a
+// read-only input when it is not one of the ping-pong buffers: pass
+// inputs_readonly = true) and ping-pong between (k1, p1) and (k2, p2).  On
+// return *which is 0, 1 or 2: the buffer pair holding the sorted result.
+template <typename K, typename P>
+int radix_sort_bits(const K *k0, const P *p0, K *k1, P *p1, K *k2, P *p2,
+                    int64_t n, int lo, int hi, const RadixScratch &rs,
+                    hipStream_t s, int *which) {
+    const K *ck = k0;
+    const P *cp = p0;
+    int cur = 0;
+    for (int b = lo; b < hi; b += kRadixMaxBits) {
+        int bits = hi - b < kRadixMaxBits ? hi - b : kRadixMaxBits;
+        K *nk = (cur == 1) ? k2 : k1;
+        P *np = (cur == 1) ? p2 : p1;
+        MECDF_TRY((radix_pass<K, P>(ck, cp, nk, np, n, b, bits, rs, s)));
+        cur = (cur == 1) ? 2 : 1;
+        ck = nk;
+        cp = np;
+    }
+    *which = cur;
+    return MECDF_OK;
+}
+
+}  // namespace mecdf

@@ -1,0 +1,284 @@
+"""Thin Python binding of libmecdf (argument marshalling only).
+
+Every function takes torch tensors that live on the current HIP device,
+allocates the outputs with torch, and calls the C ABI of include/mecdf.h with
+raw device pointers and the current torch stream.  All arithmetic happens in
+the library's HIP kernels; there is no CPU fallback: if libmecdf.so is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmecdf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libmecdf.so is not built (expected at %s); run "
+        "`python -m paper_2005_03246_amd.build` first" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MECDF_OK = 0
+MECDF_EINVAL = -1
+MECDF_ENOMEM = -2
+MECDF_EDEVICE = -3
+MECDF_EUNSUPPORTED = -4
+MECDF_F64 = 0
+MECDF_F32C = 1
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+_SIGS = {
+    "ecdf_grid": [_I, _I64, _P, _P, _P, _P, _P, _I, _P],
+    "esf_grid": [_I, _I64, _P, _P, _P, _P, _P, _I, _P],
+    "ecdf_esf_grid": [_I, _I64, _P, _P, _P, _P, _P, _P, _I, _P],
+    "ecdf_points": [_I, _I64, _P, _P, _P, _I, _P],
+    "esf_points": [_I, _I64, _P, _P, _P, _I, _P],
+    "kde_laplace": [_I, _I64, _P, _P, _I, _P, _P, _P, _I, _P],
+    "kreg_laplace": [_I, _I64, _P, _P, _I, _P, _P, _P, _I, _P],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _I
+_lib.mecdf_strerror.argtypes = [_I]
+_lib.mecdf_strerror.restype = ctypes.c_char_p
+_lib.mecdf_last_error.argtypes = []
+_lib.mecdf_last_error.restype = ctypes.c_char_p
+_lib.mecdf_release.argtypes = []
+_lib.mecdf_release.restype = None
+
+# the raw C functions, for callers that marshal pointers themselves
+raw = _lib
+
+
+class MecdfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.mecdf_last_error().decode(errors="replace")
+        super().__init__("%s failed: %s (%d): %s" % (
+            where, _lib.mecdf_strerror(code).decode(), code, msg))
+
+
+def _check(rc: int, where: str):
+    if rc != MECDF_OK:
+        raise MecdfError(rc, where)
+
+
+def _prec(prec) -> int:
+    if prec in (MECDF_F64, "f64", "float64", torch.float64):
+        return MECDF_F64
+    if prec in (MECDF_F32C, "f32c", "float32", torch.float32):
+        return MECDF_F32C
+    raise ValueError("prec must be 'f64' or 'f32c'")
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _x(x: torch.Tensor) -> torch.Tensor:
+    if not (x.is_cuda and x.dtype == torch.float64 and x.dim() == 2):
+        raise TypeError("x must be a (d, N) float64 tensor on the GPU")
+    return x.contiguous()
+
+
+def _y(y, n: int, prec: int, x: torch.Tensor):
+    if y is None:
+        return None
+    want = torch.float64 if prec == MECDF_F64 else torch.float32
+    if not (y.is_cuda and y.dtype == want and y.shape == (n,)):
+        raise TypeError("y must be a (N,) %s tensor on the GPU" % want)
+    if y.device != x.device:
+        raise ValueError("x and y must be on the same device")
+    return y.contiguous()
+
+
+def _out_dtype(y, prec: int):
+    if y is None:
+        return torch.int64
+    return torch.float64 if prec == MECDF_F64 else torch.float32
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _grid_args(nodes):
+    ms = (ctypes.c_int64 * len(nodes))(*[int(len(v)) for v in nodes])
+    flat = []
+    for v in nodes:
+        flat.extend(float(a) for a in (v.tolist() if hasattr(v, "tolist") else v))
+    zs = (ctypes.c_double * max(1, len(flat)))(*flat)
+    return ms, zs, tuple(int(len(v)) for v in nodes)
+
+
+def ecdf_esf_grid(x: torch.Tensor, nodes, y=None, prec="f64", want_ecdf=True,
+                  want_esf=True, stream=None):
+    """ECDF and/or ESF at every node of the rectilinear grid given by the
+    per-axis node lists ``nodes`` (C ABI ``ecdf_esf_grid``).  Returns
+    (F, Fbar), each of shape (M_1, ..., M_d) or None when not requested."""
+    x = _x(x)
+    d, n = x.shape
+    if len(nodes) != d:
+        raise ValueError("need one node vector per dimension")
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    ms, zs, shape = _grid_args(nodes)
+    dt = _out_dtype(y, p)
+    F = torch.empty(shape, dtype=dt, device=x.device) if want_ecdf else None
+    Fb = torch.empty(shape, dtype=dt, device=x.device) if want_esf else None
+    rc = _lib.ecdf_esf_grid(d, n, _ptr(x), _ptr(y), ms, zs, _ptr(F), _ptr(Fb),
+                            p, _stream_ptr(stream))
+    _check(rc, "ecdf_esf_grid")
+    return F, Fb
+
+
+def ecdf_grid(x, nodes, y=None, prec="f64", stream=None):
+    """F_N at every grid node (C ABI ``ecdf_grid``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    ms, zs, shape = _grid_args(nodes)
+    F = torch.empty(shape, dtype=_out_dtype(y, p), device=x.device)
+    _check(_lib.ecdf_grid(d, n, _ptr(x), _ptr(y), ms, zs, _ptr(F), p,
+                          _stream_ptr(stream)), "ecdf_grid")
+    return F
+
+
+def esf_grid(x, nodes, y=None, prec="f64", stream=None):
+    """Fbar_N at every grid node (C ABI ``esf_grid``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    ms, zs, shape = _grid_args(nodes)
+    F = torch.empty(shape, dtype=_out_dtype(y, p), device=x.device)
+    _check(_lib.esf_grid(d, n, _ptr(x), _ptr(y), ms, zs, _ptr(F), p,
+                         _stream_ptr(stream)), "esf_grid")
+    return F
+
+
+def ecdf_points(x, y=None, prec="f64", stream=None):
+    """F_N(x_j) at every sample point (C ABI ``ecdf_points``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    F = torch.empty((n,), dtype=_out_dtype(y, p), device=x.device)
+    _check(_lib.ecdf_points(d, n, _ptr(x), _ptr(y), _ptr(F), p,
+                            _stream_ptr(stream)), "ecdf_points")
+    return F
+
+
+def esf_points(x, y=None, prec="f64", stream=None):
+    """Fbar_N(x_j) at every sample point (C ABI ``esf_points``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    F = torch.empty((n,), dtype=_out_dtype(y, p), device=x.device)
+    _check(_lib.esf_points(d, n, _ptr(x), _ptr(y), _ptr(F), p,
+                           _stream_ptr(stream)), "esf_points")
+    return F
+
+
+def _hmat(h, d):
+    import numpy as np
+
+    h = np.asarray(h, dtype=np.float64)
+    if h.ndim == 0:
+        h = np.full((1, d), float(h))
+    elif h.ndim == 1:
+        h = np.repeat(h[:, None], d, 1)
+    if h.ndim != 2 or h.shape[1] != d:
+        raise ValueError("bandwidths must be scalar, (nh,) or (nh, d)")
+    return np.ascontiguousarray(h)
+
+
+def kde_laplace(x, h, w=None, prec="f64", want_f=True, want_lcv=True,
+                stream=None):
+    """Laplacian KDE at the sample points for each bandwidth row of h and the
+    likelihood CV scores (C ABI ``kde_laplace``).  Returns (f, lcv):
+    f of shape (nh, N) or None, lcv of shape (nh,) float64 or None."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    w = _y(w, n, p, x)
+    hm = _hmat(h, d)
+    nh = hm.shape[0]
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    f = torch.empty((nh, n), dtype=dt, device=x.device) if want_f else None
+    lcv = torch.empty((nh,), dtype=torch.float64, device=x.device) if want_lcv else None
+    _check(_lib.kde_laplace(d, n, _ptr(x), _ptr(w), nh, hs, _ptr(f), _ptr(lcv),
+                            p, _stream_ptr(stream)), "kde_laplace")
+    return f, lcv
+
+
+def kreg_laplace(x, y, h, prec="f64", want_m=True, want_cv=True, stream=None):
+    """Nadaraya-Watson regression at the sample points and squared-error LOO
+    CV scores (C ABI ``kreg_laplace``).  Returns (m, cv)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    if y is None:
+        raise ValueError("kreg_laplace needs the response y")
+    hm = _hmat(h, d)
+    nh = hm.shape[0]
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    m = torch.empty((nh, n), dtype=dt, device=x.device) if want_m else None
+    cv = torch.empty((nh,), dtype=torch.float64, device=x.device) if want_cv else None
+    _check(_lib.kreg_laplace(d, n, _ptr(x), _ptr(y), nh, hs, _ptr(m), _ptr(cv),
+                             p, _stream_ptr(stream)), "kreg_laplace")
+    return m, cv
+
+
+def release():
+    """Free the library's device workspaces."""
+    _lib.mecdf_release()
+
+
+# ---------------------------------------------------------------- profiling
+_lib.mecdf_profile_enable.argtypes = [_I]
+_lib.mecdf_profile_enable.restype = _I
+_lib.mecdf_profile_reset.argtypes = []
+_lib.mecdf_profile_reset.restype = None
+_lib.mecdf_profile_collect.argtypes = [_I, _P, _P, _P]
+_lib.mecdf_profile_collect.restype = _I
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events (timing only)."""
+    _lib.mecdf_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.mecdf_profile_reset()
+
+
+def profile_collect(max_names: int = 64):
+    """{kernel name: (total ms, launches)} for the launches recorded since the
+    last reset; waits for the recorded events."""
+    names = ctypes.create_string_buffer(64 * max_names)
+    ms = (ctypes.c_double * max_names)()
+    cnt = (ctypes.c_int64 * max_names)()
+    n = _lib.mecdf_profile_collect(max_names, names, ms, cnt)
+    if n < 0:
+        raise MecdfError(n, "mecdf_profile_collect")
+    out = {}
+    for i in range(n):
+        nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (float(ms[i]), int(cnt[i]))
+    return out

@@ -1,0 +1,91 @@
+"""The C-ABI library builds for gfx950, loads, exports every declared entry
+point and rejects invalid arguments on the host, before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mecdf.h")
+LIB = os.path.join(ROOT, "paper_2005_03246_amd", "_lib", "libmecdf.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(\w+)\s*\(", src, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2005_03246_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_paper_entry_points():
+    names = declared_functions()
+    for n in ["ecdf_grid", "esf_grid", "ecdf_points", "esf_points",
+              "kde_laplace", "kreg_laplace"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def _c(lib, name, argtypes):
+    f = getattr(lib, name)
+    f.argtypes = argtypes
+    f.restype = ctypes.c_int
+    return f
+
+
+P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+
+
+def test_host_validation_errors(lib):
+    lib.mecdf_last_error.restype = ctypes.c_char_p
+    grid = _c(lib, "ecdf_grid", [I, I64, P, P, P, P, P, I, P])
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    M = (ctypes.c_int64 * 2)(3, 3)
+    z_ok = (ctypes.c_double * 6)(0, 1, 2, 0, 1, 2)
+    z_bad = (ctypes.c_double * 6)(0, 2, 1, 0, 1, 2)
+    z_nan = (ctypes.c_double * 6)(0, float("nan"), 2, 0, 1, 2)
+    assert grid(0, 10, fake, None, M, z_ok, fake, 0, None) == -1
+    assert grid(7, 10, fake, None, M, z_ok, fake, 0, None) == -1
+    assert grid(2, -1, fake, None, M, z_ok, fake, 0, None) == -1
+    assert grid(2, 10, None, None, M, z_ok, fake, 0, None) == -1
+    assert grid(2, 10, fake, None, M, z_bad, fake, 0, None) == -1
+    assert b"strictly increasing" in lib.mecdf_last_error()
+    assert grid(2, 10, fake, None, M, z_nan, fake, 0, None) == -1
+    assert grid(2, 10, fake, None, None, z_ok, fake, 0, None) == -1
+    assert grid(2, 10, fake, None, M, z_ok, None, 0, None) == -1
+    assert grid(2, 10, fake, None, M, z_ok, fake, 5, None) == -1
+    assert grid(2, 0, fake, fake, M, z_ok, fake, 0, None) == -1  # weighted N=0
+    M0 = (ctypes.c_int64 * 2)(0, 3)
+    assert grid(2, 10, fake, None, M0, z_ok, fake, 0, None) == -1
+    big = (ctypes.c_int64 * 1)(5000)
+    zb = (ctypes.c_double * 5000)(*range(5000))
+    assert grid(1, 10, fake, None, big, zb, fake, 0, None) == -4
+    pts = _c(lib, "ecdf_points", [I, I64, P, P, P, I, P])
+    assert pts(0, 10, fake, None, fake, 0, None) == -1
+    assert pts(2, 10, fake, None, None, 0, None) == -1
+    assert pts(2, 1 << 31, fake, None, fake, 0, None) == -4
+    kde = _c(lib, "kde_laplace", [I, I64, P, P, I, P, P, P, I, P])
+    h = (ctypes.c_double * 2)(0.1, 0.1)
+    hneg = (ctypes.c_double * 2)(0.1, -0.1)
+    assert kde(2, 1, fake, None, 1, h, fake, None, 0, None) == -1   # N < 2
+    assert kde(4, 10, fake, None, 1, h, fake, None, 0, None) == -1  # d > 3
+    assert kde(2, 10, fake, None, 0, h, fake, None, 0, None) == -1
+    assert kde(2, 10, fake, None, 1, hneg, fake, None, 0, None) == -1
+    assert kde(2, 10, fake, None, 1, h, None, None, 0, None) == -1
+    kreg = _c(lib, "kreg_laplace", [I, I64, P, P, I, P, P, P, I, P])
+    assert kreg(2, 10, fake, None, 1, h, fake, None, 0, None) == -1  # y NULL
+    lib.mecdf_strerror.restype = ctypes.c_char_p
+    assert lib.mecdf_strerror(-1) == b"invalid argument"

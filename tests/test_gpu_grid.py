@@ -1,0 +1,184 @@
+"""Parity of the grid path (ecdf_grid / esf_grid / ecdf_esf_grid) with the
+brute-force oracle: counts bit-exact, float64 within 1e-12 and float32 with
+compensation within 1e-5 of the |y|-weighted scale of each result."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_03246_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_03246_amd import mecdf
+
+    return mecdf
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def check_weighted(got, want, scale, tol):
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    want = np.asarray(want).reshape(-1)
+    scale = np.asarray(scale).reshape(-1)
+    zero = scale == 0
+    assert np.all(got[zero] == 0.0)
+    nz = ~zero
+    err = np.abs(got[nz] - want[nz]) / scale[nz]
+    assert err.size == 0 or err.max() <= tol, (err.max(), np.argmax(err))
+
+
+def random_case(g, d, n, ms, uniform, ties):
+    x = g.normal(size=(d, n))
+    if ties:
+        x = np.round(x, 1)
+    nodes = []
+    for k in range(d):
+        if uniform:
+            nodes.append(datagen.uniform_grid(x[k:k + 1], ms[k])[0])
+        else:
+            v = np.unique(np.concatenate([g.normal(size=ms[k] * 2) * 1.5, x[k, :3]]))
+            v = np.sort(g.choice(v, size=ms[k], replace=False))
+            nodes.append(v)
+    return x, nodes
+
+
+CASES = [
+    # d, n, M per axis, uniform nodes, ties in x
+    (1, 1, [1], True, False),
+    (1, 5000, [257], False, True),
+    (2, 7, [3, 5], False, False),
+    (2, 5000, [64, 65], True, True),
+    (2, 9000, [1, 130], False, True),
+    (3, 20000, [17, 9, 33], True, True),
+    (3, 4097, [5, 1, 70], False, False),
+    (4, 6000, [6, 7, 5, 9], False, True),
+    (5, 3000, [3, 4, 2, 5, 6], True, False),
+    (6, 2000, [2, 3, 2, 3, 2, 4], False, True),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_grid_counts_and_weighted(lib, case):
+    d, n, ms, uniform, ties = case
+    g = np.random.default_rng(1000 + d * 7 + n)
+    x, nodes = random_case(g, d, n, ms, uniform, ties)
+    shape = tuple(ms)
+    z = oracle.grid_points(nodes)
+    xt = dev(x)
+    # counts
+    F, Fb = lib.ecdf_esf_grid(xt, nodes)
+    np.testing.assert_array_equal(F.cpu().numpy().reshape(-1), oracle.ecdf(x, z))
+    np.testing.assert_array_equal(Fb.cpu().numpy().reshape(-1), oracle.esf(x, z))
+    # integer weights: exact in float64 (1/N applied last)
+    yi = g.integers(-3, 4, size=n).astype(np.float64)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(yi))
+    np.testing.assert_array_equal(F.cpu().numpy().reshape(-1), oracle.ecdf(x, z, yi)[0])
+    np.testing.assert_array_equal(Fb.cpu().numpy().reshape(-1), oracle.esf(x, z, yi)[0])
+    # real weights, float64
+    y = g.normal(size=n)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y))
+    w, a = oracle.ecdf(x, z, y)
+    check_weighted(F.cpu().numpy(), w, a, 1e-12)
+    w, a = oracle.esf(x, z, y)
+    check_weighted(Fb.cpu().numpy(), w, a, 1e-12)
+    # float32 with compensation
+    y32 = y.astype(np.float32)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y32, torch.float32), prec="f32c")
+    assert F.dtype == torch.float32 and F.shape == shape
+    w, a = oracle.ecdf(x, z, y32.astype(np.float64))
+    check_weighted(F.cpu().numpy(), w, a, 1e-5)
+    w, a = oracle.esf(x, z, y32.astype(np.float64))
+    check_weighted(Fb.cpu().numpy(), w, a, 1e-5)
+
+
+def test_single_function_entry_points(lib):
+    g = np.random.default_rng(5)
+    x = g.normal(size=(3, 3000))
+    nodes = datagen.uniform_grid(x, [9, 10, 11])
+    z = oracle.grid_points(nodes)
+    xt = dev(x)
+    np.testing.assert_array_equal(lib.ecdf_grid(xt, nodes).cpu().numpy().reshape(-1),
+                                  oracle.ecdf(x, z))
+    np.testing.assert_array_equal(lib.esf_grid(xt, nodes).cpu().numpy().reshape(-1),
+                                  oracle.esf(x, z))
+
+
+def test_hand_grid(lib, golden):
+    g = golden["grid_d2"]
+    x = np.array(g["x"], dtype=float)
+    F, Fb = lib.ecdf_esf_grid(dev(x), g["nodes"])
+    assert F.cpu().numpy().tolist() == g["ecdf_counts"]
+    assert Fb.cpu().numpy().tolist() == g["esf_counts"]
+
+
+def test_nan_points_and_out_of_grid(lib):
+    x = np.array([[0.0, np.nan, 1.0, 5.0, -9.0], [0.0, 0.0, np.nan, 5.0, -9.0]])
+    nodes = [np.array([-1.0, 0.0, 1.0]), np.array([-1.0, 0.0, 1.0])]
+    z = oracle.grid_points(nodes)
+    F, Fb = lib.ecdf_esf_grid(dev(x), nodes)
+    np.testing.assert_array_equal(F.cpu().numpy().reshape(-1), oracle.ecdf(x, z))
+    np.testing.assert_array_equal(Fb.cpu().numpy().reshape(-1), oracle.esf(x, z))
+
+
+def test_empty_input_counts(lib):
+    x = torch.empty((2, 0), dtype=torch.float64, device="cuda")
+    F, Fb = lib.ecdf_esf_grid(x, [[0.0, 1.0], [0.0, 1.0, 2.0]])
+    assert int(F.abs().sum()) == 0 and int(Fb.abs().sum()) == 0
+
+
+def test_deterministic(lib):
+    g = np.random.default_rng(6)
+    x = g.normal(size=(3, 300000))
+    y = dev(g.normal(size=300000))
+    nodes = datagen.uniform_grid(x, 40)
+    xt = dev(x)
+    a = lib.ecdf_esf_grid(xt, nodes, y)
+    b = lib.ecdf_esf_grid(xt, nodes, y)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.fixture(scope="module")
+def full_c2():
+    x, y, nodes = datagen.config2()
+    return x, y, nodes
+
+
+def sampled_nodes(g, ms, count):
+    idx = np.stack([g.integers(0, m, size=count) for m in ms], axis=1)
+    corners = np.array([[(c >> k & 1) * (m - 1) for k, m in enumerate(ms)]
+                        for c in range(1 << len(ms))])
+    return np.concatenate([idx, corners])
+
+
+def test_full_size_grid_sampled(lib, full_c2):
+    """The 2^24-point, 256^3-node workload, checked at sampled nodes and the
+    grid corners (the oracle evaluates them one by one)."""
+    x, y, nodes = full_c2
+    g = np.random.default_rng(7)
+    idx = sampled_nodes(g, [256] * 3, 120)
+    z = oracle.grid_points(nodes, idx)
+    xt = dev(x)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y))
+    fi = F.cpu().numpy()[tuple(idx.T)]
+    fbi = Fb.cpu().numpy()[tuple(idx.T)]
+    w, a = oracle.ecdf(x, z, y)
+    check_weighted(fi, w, a, 1e-12)
+    w, a = oracle.esf(x, z, y)
+    check_weighted(fbi, w, a, 1e-12)
+    # top corner holds the full weighted total
+    assert fi[-1] == pytest.approx(np.sum(y) / y.size, rel=1e-12, abs=1e-15)
+    y32 = y.astype(np.float32)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y32, torch.float32), prec="f32c")
+    w, a = oracle.ecdf(x, z, y32.astype(np.float64))
+    check_weighted(F.cpu().numpy()[tuple(idx.T)], w, a, 1e-5)
+    w, a = oracle.esf(x, z, y32.astype(np.float64))
+    check_weighted(Fb.cpu().numpy()[tuple(idx.T)], w, a, 1e-5)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes)
+    np.testing.assert_array_equal(F.cpu().numpy()[tuple(idx.T)], oracle.ecdf(x, z))
+    np.testing.assert_array_equal(Fb.cpu().numpy()[tuple(idx.T)], oracle.esf(x, z))
