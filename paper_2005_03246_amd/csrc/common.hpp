@@ -100,6 +100,9 @@ struct ArenaPlan {
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) {
+    return (a + b - 1) / b;
+}
 
 inline int bits_for(uint64_t v) {  // number of bits to hold values 0..v
     int b = 0;

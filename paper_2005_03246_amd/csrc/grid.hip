@@ -40,7 +40,27 @@ struct GridInfo {
     uint32_t C[MECDF_MAX_DIM];
     int bd;      // bits holding the last-axis cell index (values 0..M_last)
     uint32_t L;  // number of lines; points with a NaN coordinate go to line L
+    // Key layout of the line part.  packed != 0: each axis k < d-1 has its own
+    // bit field [sh[k], sh[k] + nb[k]) (axis 0 has room for one extra value,
+    // M_0 + 1, that marks a dropped point), so each radix pass sorts on one
+    // axis's cells.  packed == 0: the mixed-radix line index sits above bd.
+    int packed;
+    int sh[MECDF_MAX_DIM];
+    int nb[MECDF_MAX_DIM];
 };
+
+// mixed-radix line index of a key (L for a dropped point)
+__device__ __forceinline__ uint32_t key_line(uint32_t key, const GridInfo &g) {
+    if (!g.packed)
+        return key >> g.bd;
+    uint32_t c0 = (key >> g.sh[0]) & ((1u << g.nb[0]) - 1u);
+    if (c0 >= g.C[0])
+        return g.L;
+    uint32_t line = c0;
+    for (int k = 1; k < g.d - 1; ++k)
+        line = line * g.C[k] + ((key >> g.sh[k]) & ((1u << g.nb[k]) - 1u));
+    return line;
+}
 
 // Number of nodes strictly below v: the cell of eq. (partial_sums) holding v,
 // cell c meaning z_{c-1} < v <= z_c (z_{-1} = -inf, z_M = +inf).  NaN maps
@@ -70,7 +90,9 @@ __device__ __forceinline__ uint32_t cell_index(NodePtr z, int M, double v) {
     return (uint32_t)lo;
 }
 
-template <bool kLds>
+constexpr int kKeyPts = 4;  // points per thread per iteration
+
+template <int D, bool kLds>
 __global__ __launch_bounds__(256) void k_cellkey(const double *__restrict__ x,
                                                  int64_t n, GridInfo g,
                                                  const double *__restrict__ nodes_g,
@@ -82,40 +104,71 @@ __global__ __launch_bounds__(256) void k_cellkey(const double *__restrict__ x,
             s_nodes[i] = nodes_g[i];
         __syncthreads();
     }
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-        uint32_t line = 0, clast = 0;
-        bool bad = false;
-        for (int k = 0; k < g.d; ++k) {
-            double v = x[(int64_t)k * n + i];
-            bad |= (v != v);
-            uint32_t c;
-            if constexpr (kLds)
-                c = cell_index(s_nodes + g.off[k], g.M[k], v);
-            else
-                c = cell_index(nodes_g + g.off[k], g.M[k], v);
-            if (k < g.d - 1)
-                line = line * g.C[k] + c;
-            else
-                clast = c;
+    const int64_t step = (int64_t)gridDim.x * 256 * kKeyPts;
+    for (int64_t b = (int64_t)blockIdx.x * 256 * kKeyPts + threadIdx.x; b < n; b += step) {
+        double v[kKeyPts][D];
+#pragma unroll
+        for (int q = 0; q < kKeyPts; ++q) {
+            int64_t i = b + (int64_t)q * 256;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                v[q][k] = i < n ? __builtin_nontemporal_load(x + (int64_t)k * n + i) : 0.0;
         }
-        if (bad) {
-            line = g.L;
-            clast = 0;
+#pragma unroll
+        for (int q = 0; q < kKeyPts; ++q) {
+            int64_t i = b + (int64_t)q * 256;
+            if (i >= n)
+                break;
+            uint32_t line = 0, packed = 0, clast = 0;
+            bool bad = false;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                double vv = v[q][k];
+                bad |= (vv != vv);
+                uint32_t c;
+                if constexpr (kLds)
+                    c = cell_index(s_nodes + g.off[k], g.M[k], vv);
+                else
+                    c = cell_index(nodes_g + g.off[k], g.M[k], vv);
+                if (k < D - 1) {
+                    line = line * g.C[k] + c;
+                    packed |= c << g.sh[k];
+                } else {
+                    clast = c;
+                }
+            }
+            uint32_t key;
+            if (g.packed)
+                key = bad ? (g.C[0] << g.sh[0]) : (packed | clast);
+            else
+                key = bad ? (g.L << g.bd) : ((line << g.bd) | clast);
+            keys[i] = key;
         }
-        keys[i] = (line << g.bd) | clast;
     }
 }
 
+template <int D>
+static void launch_cellkey(bool lds, int64_t nb, hipStream_t s, const double *x,
+                           int64_t N, const GridInfo &g, const double *nodes,
+                           int total_nodes, uint32_t *k0) {
+    if (lds)
+        hipLaunchKernelGGL((k_cellkey<D, true>), dim3((unsigned)nb), dim3(256),
+                           sizeof(double) * total_nodes, s, x, N, g, nodes,
+                           total_nodes, k0);
+    else
+        hipLaunchKernelGGL((k_cellkey<D, false>), dim3((unsigned)nb), dim3(256), 0,
+                           s, x, N, g, nodes, total_nodes, k0);
+}
+
 __global__ __launch_bounds__(256) void k_line_bounds(const uint32_t *__restrict__ keys,
-                                                     int64_t n, int bd,
-                                                     uint32_t L,
+                                                     int64_t n, GridInfo g,
                                                      uint32_t *__restrict__ lstart) {
+    const uint32_t L = g.L;
     // lstart[l] = first sorted position whose line is >= l, for l = 0..L+1
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += stride) {
-        int64_t ln = keys[p] >> bd;
-        int64_t prev = p > 0 ? (int64_t)(keys[p - 1] >> bd) : -1;
+        int64_t ln = key_line(keys[p], g);
+        int64_t prev = p > 0 ? (int64_t)key_line(keys[p - 1], g) : -1;
         for (int64_t l = prev + 1; l <= ln; ++l)
             lstart[l] = (uint32_t)p;
         if (p == n - 1)
@@ -157,29 +210,31 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-inline size_t line_wave_bytes(int Cl) {
-    size_t acc = sizeof(BinAcc<double>) > 8 ? 8 : 8;  // all BinAcc are 8 bytes
-    (void)acc;
-    size_t b = (size_t)Cl * 8;
-    b = (b + 15) & ~size_t(15);
-    b += 2 * (((size_t)(Cl - 1) * 8 + 15) & ~size_t(15));
-    return b;
-}
+constexpr int kLineWaves = 4;
 
+// LDS of one line block: the bins of the four waves.  After they are
+// combined into the first set, the prefix and suffix rows reuse the second
+// and third.
+inline size_t line_lds_bytes(int Cl) { return (size_t)kLineWaves * Cl * 8; }
+
+// One workgroup (4 wavefronts) per line.  Wave w bins the chunks w, w+4, ...
+// of 64 points into its own bins: lanes holding the same cell are found with
+// ballots on the cell bits, and the lowest such lane adds their values in
+// lane order.  The four bin sets are then combined in wave order, so every
+// sum is taken in an order fixed by the input order alone.
 template <typename T, typename P>
 __global__ __launch_bounds__(256) void k_line(const uint32_t *__restrict__ keys,
                                               const P *__restrict__ pay,
                                               const uint32_t *__restrict__ lstart,
-                                              GridInfo g, int wpb, size_t wave_bytes,
-                                              T *__restrict__ F, T *__restrict__ Fbar,
-                                              int scale, double N) {
+                                              GridInfo g, T *__restrict__ F,
+                                              T *__restrict__ Fbar, int scale,
+                                              double N) {
     extern __shared__ __attribute__((aligned(16))) char s_raw[];
     constexpr bool kPay = !std::is_same<P, NoPayload>::value;
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int64_t line = (int64_t)blockIdx.x * wpb + w;
-    if (w >= wpb || line >= (int64_t)g.L)
-        return;  // whole wavefront; this kernel has no block barrier
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & 63;
+    const int64_t line = blockIdx.x;
     const int d = g.d;
     const int Cl = (int)g.C[d - 1];
     const int Ml = Cl - 1;
@@ -190,119 +245,123 @@ __global__ __launch_bounds__(256) void k_line(const uint32_t *__restrict__ keys,
     bool doE = F != nullptr, doS = Fbar != nullptr;
     {
         int64_t t = line;
-        int64_t mulE = 1;
+        int64_t mul = 1;
         for (int k = d - 2; k >= 0; --k) {
             int64_t c = t % g.C[k];
             t /= g.C[k];
             doE = doE && (c <= g.M[k] - 1);
             doS = doS && (c >= 1);
-            rowE += c * mulE;
-            rowS += (c - 1) * mulE;
-            mulE *= g.M[k];
+            rowE += c * mul;
+            rowS += (c - 1) * mul;
+            mul *= g.M[k];
         }
     }
     if (!doE && !doS)
-        return;
+        return;  // uniform over the block
 
-    char *wbase = s_raw + (size_t)w * wave_bytes;
-    BinAcc<T> *bins = reinterpret_cast<BinAcc<T> *>(wbase);
-    T *Pout = reinterpret_cast<T *>(wbase + (((size_t)Cl * 8 + 15) & ~size_t(15)));
-    T *Qout = reinterpret_cast<T *>(reinterpret_cast<char *>(Pout) +
-                                    (((size_t)Ml * 8 + 15) & ~size_t(15)));
+    BinAcc<T> *bins = reinterpret_cast<BinAcc<T> *>(s_raw);
+    BinAcc<T> *mybins = bins + (size_t)w * Cl;
+    T *Pout = reinterpret_cast<T *>(bins + Cl);
+    T *Qout = reinterpret_cast<T *>(bins + 2 * (size_t)Cl);
     for (int c = lane; c < Cl; c += 64)
-        bins[c].zero();
+        mybins[c].zero();
     wave_lds_fence();
 
     const uint32_t s0 = lstart[line], e0 = lstart[line + 1];
     const uint32_t cmask = (1u << g.bd) - 1u;
-    for (uint32_t p0 = s0; p0 < e0; p0 += 64) {
+    const uint64_t lt = lanemask_lt();
+    for (uint32_t p0 = s0 + (uint32_t)w * 64u; p0 < e0; p0 += 64u * kLineWaves) {
         uint32_t p = p0 + lane;
         bool v = p < e0;
-        uint32_t c = v ? (keys[p] & cmask) : (uint32_t)Cl;
-        T val;
-        if constexpr (kPay)
-            val = v ? (T)pay[p] : T(0);
-        else
-            val = v ? T(1) : T(0);
-        // bitonic sort of the 64 (cell, lane) keys: equal cells keep lane order
-        uint32_t sk = (c << 6) | (uint32_t)lane;
-#pragma unroll
-        for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                uint32_t ok = shfl_xor(sk, j);
-                T ov = shfl_xor(val, j);
-                bool up = (lane & k) == 0;
-                bool lower = (lane & j) == 0;
-                bool take = (lower == up) ? (ok < sk) : (ok > sk);
-                if (take) {
-                    sk = ok;
-                    val = ov;
+        uint32_t c = v ? (keys[p] & cmask) : 0u;
+        uint64_t peers = __ballot(v);
+        for (int b = 0; b < g.bd; ++b) {
+            bool bit = (c >> b) & 1u;
+            uint64_t bal = __ballot(v && bit);
+            peers &= bit ? bal : ~bal;
+        }
+        bool leader = v && (peers & lt) == 0;
+        if constexpr (kPay) {
+            T val = v ? (T)pay[p] : T(0);
+            // leaders sum their group in lane order (other lanes follow along)
+            T acc = T(0);
+            uint64_t m = leader ? peers : 0ull;
+            while (__ballot(m != 0ull) != 0ull) {
+                int j = m ? (__ffsll((unsigned long long)m) - 1) : lane;
+                T o = shfl(val, j);
+                if (m) {
+                    acc = acc + o;
+                    m &= m - 1ull;
                 }
             }
+            if (leader)
+                mybins[c].add(acc);
+        } else {
+            if (leader)
+                mybins[c].add((T)__popcll(peers));
         }
-        c = sk >> 6;
-        // segmented inclusive scan over runs of equal cells
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t oc = shfl_up(c, off);
-            T ov = shfl_up(val, off);
-            if (lane >= off && oc == c)
-                val = val + ov;
-        }
-        uint32_t nc = shfl_down(c, 1);
-        bool tail = (lane == 63) || (nc != c);
-        if (tail && c < (uint32_t)Cl)
-            bins[c].add(val);
         wave_lds_fence();
     }
+    __syncthreads();
+    // combine the wave bins in wave order into bins[0]
+    for (int c = tid; c < Cl; c += 256) {
+        BinAcc<T> t;
+        t.zero();
+        for (int q = 0; q < kLineWaves; ++q)
+            t.add(bins[(size_t)q * Cl + c].get());
+        bins[c] = t;
+    }
+    __syncthreads();
 
-    // last-axis scans: each lane owns a contiguous run of cells
-    const int ch = (Cl + 63) / 64;
-    const int b0 = lane * ch < Cl ? lane * ch : Cl;
-    const int b1 = b0 + ch < Cl ? b0 + ch : Cl;
-    BinAcc<T> tot;
-    tot.zero();
-    for (int c = b0; c < b1; ++c)
-        tot.add(bins[c].get());
-    T tv = tot.get();
-    T inc = wave_inclusive_scan(tv);
-    T ex = shfl_up(inc, 1);
-    if (lane == 0)
-        ex = T(0);
-    T sinc = wave_inclusive_suffix(tv);
-    T sex = shfl_down(sinc, 1);
-    if (lane == 63)
-        sex = T(0);
-    if (doE) {
-        BinAcc<T> run;
-        run.zero();
-        run.add(ex);
-        for (int c = b0; c < b1; ++c) {
-            run.add(bins[c].get());
-            if (c < Ml)
-                Pout[c] = run.get();
+    // last-axis scans: wave 0 the inclusive prefix (ECDF), wave 1 the
+    // exclusive suffix (ESF); each lane owns a contiguous run of cells
+    if (w < 2) {
+        const int ch = (Cl + 63) / 64;
+        const int b0 = lane * ch < Cl ? lane * ch : Cl;
+        const int b1 = b0 + ch < Cl ? b0 + ch : Cl;
+        BinAcc<T> tot;
+        tot.zero();
+        for (int c = b0; c < b1; ++c)
+            tot.add(bins[c].get());
+        T tv = tot.get();
+        if (w == 0 && doE) {
+            T inc = wave_inclusive_scan(tv);
+            T ex = shfl_up(inc, 1);
+            if (lane == 0)
+                ex = T(0);
+            BinAcc<T> run;
+            run.zero();
+            run.add(ex);
+            for (int c = b0; c < b1; ++c) {
+                run.add(bins[c].get());
+                if (c < Ml)
+                    Pout[c] = run.get();
+            }
+        }
+        if (w == 1 && doS) {
+            T sinc = wave_inclusive_suffix(tv);
+            T sex = shfl_down(sinc, 1);
+            if (lane == 63)
+                sex = T(0);
+            BinAcc<T> run;
+            run.zero();
+            run.add(sex);
+            for (int c = b1 - 1; c >= b0; --c) {
+                if (c < Ml)
+                    Qout[c] = run.get();
+                run.add(bins[c].get());
+            }
         }
     }
-    if (doS) {
-        BinAcc<T> run;
-        run.zero();
-        run.add(sex);
-        for (int c = b1 - 1; c >= b0; --c) {
-            if (c < Ml)
-                Qout[c] = run.get();
-            run.add(bins[c].get());
-        }
-    }
-    wave_lds_fence();
+    __syncthreads();
     if (doE) {
         T *dst = F + rowE * Ml;
-        for (int j = lane; j < Ml; j += 64)
+        for (int j = tid; j < Ml; j += 256)
             dst[j] = finish(Pout[j], scale, N);
     }
     if (doS) {
         T *dst = Fbar + rowS * Ml;
-        for (int j = lane; j < Ml; j += 64)
+        for (int j = tid; j < Ml; j += 256)
             dst[j] = finish(Qout[j], scale, N);
     }
 }
@@ -363,6 +422,15 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
     g.L = (uint32_t)L;
     g.bd = bits_for((uint64_t)M[d - 1]);
     const int lb = bits_for(L);  // line values 0..L (L = dropped)
+    {
+        int tot = g.bd;
+        for (int k = d - 2; k >= 0; --k) {
+            g.nb[k] = bits_for((uint64_t)M[k] + (k == 0 ? 1 : 0));
+            g.sh[k] = tot;
+            tot += g.nb[k];
+        }
+        g.packed = (d >= 2 && tot <= 32) ? 1 : 0;
+    }
     const int Cl = (int)g.C[d - 1];
     const int Ml = Cl - 1;
 
@@ -405,24 +473,50 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
         int64_t nb = ceil_div(N, 256);
         if (nb > 8192)
             nb = 8192;
+        int64_t nbk = ceil_div(N, 256 * kKeyPts);
+        if (nbk > 4096)
+            nbk = 4096;
         bool lds = total_nodes <= 12288;
-        ProfScope prof1("grid_cellkey", s);
-        if (lds)
-            hipLaunchKernelGGL(k_cellkey<true>, dim3((unsigned)nb), dim3(256),
-                               sizeof(double) * total_nodes, s, x, N, g, nodes,
-                               total_nodes, k0);
-        else
-            hipLaunchKernelGGL(k_cellkey<false>, dim3((unsigned)nb), dim3(256), 0,
-                               s, x, N, g, nodes, total_nodes, k0);
+        {
+            ProfScope prof1("grid_cellkey", s);
+            switch (d) {
+            case 1: launch_cellkey<1>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            case 2: launch_cellkey<2>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            case 3: launch_cellkey<3>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            case 4: launch_cellkey<4>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            case 5: launch_cellkey<5>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            default: launch_cellkey<6>(lds, nbk, s, x, N, g, nodes, total_nodes, k0); break;
+            }
+        }
         MECDF_LAUNCH_CHECK();
         int which = 0;
-        MECDF_TRY((radix_sort_bits<uint32_t, P>(k0, y, k1, p1, k2, p2, N, g.bd,
-                                                g.bd + lb, rs, s, &which)));
+        if (g.packed) {
+            // one pass (or more, for axes over 9 bits) per axis, last line axis first
+            const uint32_t *ck = k0;
+            const P *cp = y;
+            int cur = 0;
+            for (int k = d - 2; k >= 0; --k) {
+                for (int b = g.sh[k]; b < g.sh[k] + g.nb[k]; b += kRadixMaxBits) {
+                    int bits = g.sh[k] + g.nb[k] - b;
+                    bits = bits < kRadixMaxBits ? bits : kRadixMaxBits;
+                    uint32_t *nk = (cur == 1) ? k2 : k1;
+                    P *np = (cur == 1) ? p2 : p1;
+                    MECDF_TRY((radix_pass<uint32_t, P>(ck, cp, nk, np, N, b, bits, rs, s)));
+                    cur = (cur == 1) ? 2 : 1;
+                    ck = nk;
+                    cp = np;
+                }
+            }
+            which = cur;
+        } else {
+            MECDF_TRY((radix_sort_bits<uint32_t, P>(k0, y, k1, p1, k2, p2, N, g.bd,
+                                                    g.bd + lb, rs, s, &which)));
+        }
         ks = which == 0 ? k0 : (which == 1 ? k1 : k2);
         ps = which == 0 ? y : (which == 1 ? p1 : p2);
         ProfScope prof2("grid_line_bounds", s);
         hipLaunchKernelGGL(k_line_bounds, dim3((unsigned)nb), dim3(256), 0, s, ks,
-                           N, g.bd, g.L, lstart);
+                           N, g, lstart);
         MECDF_LAUNCH_CHECK();
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)ceil_div(L + 2, 256)), dim3(256),
@@ -430,20 +524,19 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
         MECDF_LAUNCH_CHECK();
     }
 
-    size_t wb = line_wave_bytes(Cl);
-    int wpb = (int)(98304 / wb);
-    if (wpb > 4)
-        wpb = 4;
-    if (wpb < 1) {
+    size_t lb_bytes = line_lds_bytes(Cl);
+    if (lb_bytes > 160 * 1024) {
         set_error("last grid axis too large for the line kernel");
         return MECDF_EUNSUPPORTED;
     }
-    int64_t nlb = ceil_div((int64_t)L, wpb);
+    if (lb_bytes > 64 * 1024)
+        MECDF_TRY_HIP(hipFuncSetAttribute((const void *)k_line<T, P>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lb_bytes));
     {
-    ProfScope prof3("grid_line", s);
-    hipLaunchKernelGGL((k_line<T, P>), dim3((unsigned)nlb), dim3(64 * wpb),
-                       wb * wpb, s, ks, ps, lstart, g, wpb, wb, F, Fbar,
-                       d == 1 ? 1 : 0, (double)N);
+        ProfScope prof3("grid_line", s);
+        hipLaunchKernelGGL((k_line<T, P>), dim3((unsigned)L), dim3(256), lb_bytes, s,
+                           ks, ps, lstart, g, F, Fbar, d == 1 ? 1 : 0, (double)N);
     }
     MECDF_LAUNCH_CHECK();
 

@@ -2,8 +2,11 @@
 // payload, written for 64-lane wavefronts.
 //
 // One pass sorts by the digit (key >> shift) & (2^bits - 1), bits <= 9:
-//   1. k_radix_hist    per-tile digit counts (tile = 4096 keys), digit-major
-//   2. exclusive scan  over the digit-major count table -> global offsets
+//   1. k_radix_hist    per-tile digit counts (tile = 4096 keys), tile-major
+//   2. offsets         for every (tile, digit): the number of keys with a
+//                      smaller digit plus the keys of that digit in earlier
+//                      tiles (column sums over chunks of tiles, a scan of the
+//                      chunk sums, then a rescan), written back tile-major
 //   3. k_radix_scatter per-tile stable ranks from wave ballots, staging of the
 //                      tile in LDS in digit order, then coalesced writes
 // Stability (equal digits keep their input order) makes the result, and
@@ -44,7 +47,94 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K *__restrict__ keys,
     }
     __syncthreads();
     for (int i = threadIdx.x; i < R; i += 256)
-        hist[(int64_t)i * ntiles + blockIdx.x] = h[i];
+        hist[(int64_t)blockIdx.x * R + i] = h[i];
+    (void)ntiles;
+}
+
+// ---- per-(tile, digit) offsets from the tile-major count table ------------
+constexpr int kOffChunk = 64;  // tiles per chunk
+
+// S[c*R + d] = sum of H[t*R + d] over the tiles t of chunk c
+__global__ __launch_bounds__(256) void k_off_chunks(const uint32_t *__restrict__ H,
+                                                    int64_t ntiles, int R,
+                                                    uint32_t *__restrict__ S) {
+    int64_t nch = ceil_div_dev(ntiles, kOffChunk);
+    int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= nch * R)
+        return;
+    int64_t c = id / R;
+    int d = (int)(id - c * R);
+    int64_t t0 = c * kOffChunk, t1 = t0 + kOffChunk < ntiles ? t0 + kOffChunk : ntiles;
+    uint32_t s = 0;
+#pragma unroll 16
+    for (int64_t t = t0; t < t1; ++t)
+        s += H[t * R + d];
+    S[id] = s;
+}
+
+// Per digit: exclusive scan of the chunk sums (in place), and the digit
+// bases B[d] = number of keys with a smaller digit.  One block of 512 threads;
+// loads are issued 16 at a time so that they overlap.
+__global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ S,
+                                                  int64_t nch, int R,
+                                                  uint32_t *__restrict__ B) {
+    __shared__ uint32_t tot[kRadixMaxDigits];
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+    if (d < R) {
+        for (int64_t c0 = 0; c0 < nch; c0 += 16) {
+            uint32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = c0 + u < nch ? S[(c0 + u) * R + d] : 0u;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (c0 + u < nch)
+                    S[(c0 + u) * R + d] = run;
+                run += v[u];
+            }
+        }
+    }
+    tot[d] = d < R ? run : 0u;
+    __syncthreads();
+    if (d == 0) {
+        uint32_t acc = 0;
+        for (int q = 0; q < R; ++q) {
+            uint32_t v = tot[q];
+            tot[q] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    if (d < R)
+        B[d] = tot[d];
+}
+
+// H[t*R + d] <- offset of digit d in tile t (in place)
+__global__ __launch_bounds__(256) void k_off_final(uint32_t *__restrict__ H,
+                                                   int64_t ntiles, int R,
+                                                   const uint32_t *__restrict__ S,
+                                                   const uint32_t *__restrict__ B) {
+    int64_t nch = ceil_div_dev(ntiles, kOffChunk);
+    int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= nch * R)
+        return;
+    int64_t c = id / R;
+    int d = (int)(id - c * R);
+    int64_t t0 = c * kOffChunk, t1 = t0 + kOffChunk < ntiles ? t0 + kOffChunk : ntiles;
+    uint32_t run = S[id] + B[d];
+    for (int64_t t = t0; t < t1; t += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            v[u] = t + u < t1 ? H[(t + u) * R + d] : 0u;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (t + u < t1)
+                H[(t + u) * R + d] = run;
+            run += v[u];
+        }
+    }
 }
 
 // ---- block-wide exclusive scan of 256 thread values (4 waves) -------------
@@ -170,7 +260,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
 
     for (int i = tid; i < R; i += 256) {
         wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0;
-        gbase[i] = offs[(int64_t)i * ntiles + tile];
+        gbase[i] = offs[tile * R + i];
     }
     __syncthreads();
 
@@ -255,10 +345,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
 }
 
 // Workspace needed by radix_sort for n keys.
+inline size_t radix_bsum_count(int64_t n) {
+    int64_t nt = ceil_div(n, kRadixTile);
+    return (size_t)(ceil_div(nt, kOffChunk) * kRadixMaxDigits) +
+           scan_bsum_count(nt * kRadixMaxDigits);
+}
+
 inline void radix_plan(ArenaPlan &pl, int64_t n) {
     int64_t nt = ceil_div(n, kRadixTile);
     pl.add<uint32_t>((size_t)(nt * kRadixMaxDigits));
-    pl.add<uint32_t>(scan_bsum_count(nt * kRadixMaxDigits));
+    pl.add<uint32_t>(radix_bsum_count(n));
 }
 
 struct RadixScratch {
@@ -270,7 +366,7 @@ inline RadixScratch radix_take(Arena &a, int64_t n) {
     int64_t nt = ceil_div(n, kRadixTile);
     RadixScratch r;
     r.hist = a.take<uint32_t>((size_t)(nt * kRadixMaxDigits));
-    r.bsum = a.take<uint32_t>(scan_bsum_count(nt * kRadixMaxDigits));
+    r.bsum = a.take<uint32_t>(radix_bsum_count(n));
     return r;
 }
 
@@ -287,7 +383,17 @@ int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nt), dim3(256), 0, s,
                            kin, n, shift, bits, rs.hist, nt);
     }
-    MECDF_TRY(scan_exclusive_u32(rs.hist, rs.hist, nt * R, rs.bsum, s));
+    {
+        ProfScope ps("radix_offsets", s);
+        int64_t nch = ceil_div(nt, kOffChunk);
+        unsigned nb = (unsigned)ceil_div(nch * R, 256);
+        hipLaunchKernelGGL(k_off_chunks, dim3(nb), dim3(256), 0, s, rs.hist, nt, R,
+                           rs.bsum);
+        uint32_t *B = rs.bsum + nch * R;
+        hipLaunchKernelGGL(k_off_scan, dim3(1), dim3(512), 0, s, rs.bsum, nch, R, B);
+        hipLaunchKernelGGL(k_off_final, dim3(nb), dim3(256), 0, s, rs.hist, nt, R,
+                           rs.bsum, B);
+    }
     {
         ProfScope ps("radix_scatter", s);
         hipLaunchKernelGGL((k_radix_scatter<K, P>), dim3((unsigned)nt), dim3(256), 0,
