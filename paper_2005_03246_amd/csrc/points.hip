@@ -1,9 +1,836 @@
-// placeholder replaced below
+// Points path: generalized ECDF / ESF at the sample points themselves
+// (Section 2.2 of Langrene & Warin, arXiv 2005.03246).
+//
+// The paper's divide-and-conquer (after Bentley) halves the points along one
+// coordinate, recurses on both halves, and merges the cross pairs one
+// coordinate lower; it excludes the point itself and uses strict
+// inequalities, and it is exact only for tie-free data.  Here the result is
+// eq. (ECDF) / eq. (ESF) exactly, ties included:
+//
+//   ranks      per coordinate, order-preserving 64-bit keys of the doubles
+//              (-0 == +0) are radix-sorted and turned into dense integer
+//              ranks r, equal values sharing a rank; a point with a NaN
+//              coordinate is dropped (it dominates nothing and its result is 0).
+//   items      every point is a data item (weight y_i) and a query item.
+//              ECDF: data and query coordinates are r (<= in every axis).
+//              ESF:  x_i > x_j  <=>  r_i >= r_j + 1, so with reversed ranks
+//              a = U-1-r (data) and b = U-2-r (query) it becomes a <= b.
+//              The count for query q is the weight of the data items i with
+//              a_i <= b_q on every axis.
+//   order      items sorted by (coordinate 0, type) with data before queries,
+//              so "i before q" encodes coordinate 0 (ties included).
+//   recursion  level-synchronous, one coordinate per depth m = 1..d-1:
+//              * pairs inside blocks of kBlockT items are counted by brute
+//                force in LDS, which also sorts each block by coordinate m;
+//              * then sorted blocks of size h = kBlockT, 2 kBlockT, ... are
+//                merged pairwise by coordinate m.  Below the last coordinate
+//                each merged block becomes a sub-problem of depth m+1, with a
+//                bit recording whether the item came from the left or right
+//                half; at the last coordinate the merge itself counts, for
+//                every query of the right half, the weight of the left-half
+//                data that precede it (a prefix sum carried over the left
+//                half).  A pair is counted at one depth only, by the items
+//                being data-left / query-right at every enclosing split.
+// Counts are exact int64; weighted sums accumulate in float64 in a fixed
+// order, so results are deterministic.
 #include "common.hpp"
+#include "radix.hpp"
+
 namespace mecdf {
-int points_run(int, int64_t, const double *, const void *, void *, int, int,
-               hipStream_t) {
-    set_error("points path not built yet");
-    return MECDF_EUNSUPPORTED;
+
+constexpr int kBlockT = 512;   // items per LDS brute-force block
+constexpr int kIdShift = 5;    // idt = id << 5 | side bits (1..4) | type (bit 0)
+
+template <int NC> struct Item {
+    uint32_t c[NC];  // coordinates 1..d-1 (ranks, possibly reversed / shifted)
+    uint32_t idt;
+};
+
+__device__ __forceinline__ uint64_t order_key(double v) {
+    if (v == 0.0)
+        v = 0.0;  // -0 -> +0
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    if (v != v)
+        b = 0x7ff8000000000000ull;
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
+
+__global__ __launch_bounds__(256) void k_fp_keys(const double *__restrict__ x,
+                                                 int64_t n, int k,
+                                                 uint64_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ idx,
+                                                 uint32_t *__restrict__ drop) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    double v = x[(int64_t)k * n + i];
+    keys[i] = order_key(v);
+    idx[i] = (uint32_t)i;
+    uint32_t nan = (v != v) ? 1u : 0u;
+    drop[i] = (k == 0) ? nan : (drop[i] | nan);
+}
+
+__global__ __launch_bounds__(256) void k_rank_flags(const uint64_t *__restrict__ keys,
+                                                    int64_t n,
+                                                    uint32_t *__restrict__ flags) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    flags[p] = (p > 0 && keys[p] != keys[p - 1]) ? 1u : 0u;
+}
+
+// dense rank of sorted position p = (number of value changes up to p)
+__global__ __launch_bounds__(256) void k_rank_scatter(const uint32_t *__restrict__ flags,
+                                                      const uint32_t *__restrict__ excl,
+                                                      const uint32_t *__restrict__ idx,
+                                                      int64_t n,
+                                                      uint32_t *__restrict__ rank,
+                                                      uint32_t *__restrict__ U) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    uint32_t r = excl[p] + flags[p];
+    rank[idx[p]] = r;
+    if (p == n - 1)
+        *U = r + 1;
+}
+
+// Two item slots per point: 2i data, 2i+1 query.  Invalid slots get the
+// largest top key so they sort last; nvalid counts the valid ones.
+template <int NC, typename YT>
+__global__ __launch_bounds__(256) void k_make_items(
+    const uint32_t *__restrict__ rank /*[d][N]*/, const uint32_t *__restrict__ U,
+    const uint32_t *__restrict__ drop, const YT *__restrict__ y, int64_t N, int d,
+    int survival, uint64_t invalid_key, uint64_t *__restrict__ topkey,
+    uint32_t *__restrict__ slot, Item<NC> *__restrict__ items,
+    double *__restrict__ W, unsigned int *__restrict__ nvalid) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N)
+        return;
+    bool ok = drop[i] == 0u;
+    Item<NC> di, qi;
+    int64_t a0 = 0, b0 = 0;
+    bool qok = ok;
+    for (int k = 0; k < d; ++k) {
+        int64_t r = rank[(int64_t)k * N + i];
+        int64_t a, b;
+        if (survival) {
+            a = (int64_t)U[k] - 1 - r;
+            b = (int64_t)U[k] - 2 - r;
+        } else {
+            a = r;
+            b = r;
+        }
+        if (b < 0)
+            qok = false;
+        if (k == 0) {
+            a0 = a;
+            b0 = b;
+        } else if (k - 1 < NC) {
+            di.c[k - 1] = (uint32_t)a;
+            qi.c[k - 1] = (uint32_t)(b < 0 ? 0 : b);
+        }
+    }
+    for (int k = d - 1; k < NC; ++k) {
+        di.c[k] = 0u;
+        qi.c[k] = 0u;
+    }
+    di.idt = ((uint32_t)i << kIdShift) | 0u;
+    qi.idt = ((uint32_t)i << kIdShift) | 1u;
+    topkey[2 * i] = ok ? (((uint64_t)a0 << 1) | 0ull) : invalid_key;
+    topkey[2 * i + 1] = qok ? (((uint64_t)(b0 < 0 ? 0 : b0) << 1) | 1ull) : invalid_key;
+    slot[2 * i] = (uint32_t)(2 * i);
+    slot[2 * i + 1] = (uint32_t)(2 * i + 1);
+    items[2 * i] = di;
+    items[2 * i + 1] = qi;
+    if (W) {
+        double w = 1.0;
+        if constexpr (!std::is_same<YT, NoPayload>::value)
+            w = (double)y[i];
+        W[2 * i] = w;
+        W[2 * i + 1] = 0.0;
+    }
+    unsigned int c = (ok ? 1u : 0u) + (qok ? 1u : 0u);
+    if (c)
+        atomicAdd(nvalid, c);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_gather_items(const uint32_t *__restrict__ perm,
+                                                      int64_t n,
+                                                      const Item<NC> *__restrict__ in,
+                                                      const double *__restrict__ win,
+                                                      Item<NC> *__restrict__ out,
+                                                      double *__restrict__ wout) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    uint32_t s = perm[p];
+    out[p] = in[s];
+    if (win)
+        wout[p] = win[s];
+}
+
+template <int NC>
+__device__ __forceinline__ uint64_t item_key(const Item<NC> &it, int m) {
+    return ((uint64_t)it.c[m - 1] << 1) | (uint64_t)(it.idt & 1u);
+}
+
+// active predicates at depth m: enclosing side bits 1..m-1 all 0 (data) or
+// all 1 (query)
+__device__ __forceinline__ bool active_data(uint32_t idt, uint32_t mask) {
+    return (idt & 1u) == 0u && (idt & mask) == 0u;
+}
+__device__ __forceinline__ bool active_query(uint32_t idt, uint32_t mask) {
+    return (idt & 1u) == 1u && (idt & mask) == mask;
+}
+inline uint32_t side_mask(int m) { return ((1u << (m - 1)) - 1u) << 1; }
+
+// Pairs inside each block of kBlockT items at depth m: query i counts the
+// active data j placed before it whose coordinates m..d-1 are all <= its own.
+// The same loop ranks the items by (coordinate m, type, position) and the
+// block is written back sorted by that key.
+template <int NC, bool kW>
+__global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
+                                                     double *__restrict__ W,
+                                                     void *__restrict__ acc_raw,
+                                                     int64_t n, int m,
+                                                     uint32_t mask) {
+    constexpr int IPT = kBlockT / 256;
+    __shared__ Item<NC> sI[kBlockT];
+    __shared__ double sW[kW ? kBlockT : 1];
+    const int64_t base = (int64_t)blockIdx.x * kBlockT;
+    const int cnt = (int)((n - base) < kBlockT ? (n - base) : kBlockT);
+    for (int t = threadIdx.x; t < cnt; t += 256) {
+        sI[t] = S[base + t];
+        if constexpr (kW)
+            sW[t] = W[base + t];
+    }
+    __syncthreads();
+    Item<NC> mine[IPT];
+    double mw[IPT];
+    int rank[IPT];
+    double sum[IPT];
+    int64_t csum[IPT];
+    bool isq[IPT];
+    uint64_t key[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        int li = threadIdx.x + u * 256;
+        if (li < cnt) {
+            mine[u] = sI[li];
+            mw[u] = kW ? sW[li] : 0.0;
+            key[u] = item_key(mine[u], m);
+            isq[u] = active_query(mine[u].idt, mask);
+        } else {
+            isq[u] = false;
+            key[u] = ~0ull;
+        }
+        rank[u] = 0;
+        sum[u] = 0.0;
+        csum[u] = 0;
+    }
+    for (int j = 0; j < cnt; ++j) {
+        Item<NC> J = sI[j];
+        uint64_t kj = item_key(J, m);
+        bool jd = active_data(J.idt, mask);
+        double wj = kW ? sW[j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < IPT; ++u) {
+            int li = threadIdx.x + u * 256;
+            rank[u] += (kj < key[u] || (kj == key[u] && j < li)) ? 1 : 0;
+            if (jd && isq[u] && j < li) {
+                bool dom = true;
+#pragma unroll
+                for (int k = 0; k < NC; ++k)
+                    if (k >= m - 1)
+                        dom = dom && (J.c[k] <= mine[u].c[k]);
+                if (dom) {
+                    if constexpr (kW)
+                        sum[u] += wj;
+                    else
+                        csum[u] += 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        int li = threadIdx.x + u * 256;
+        if (li < cnt) {
+            S[base + rank[u]] = mine[u];
+            if constexpr (kW)
+                W[base + rank[u]] = mw[u];
+            if (isq[u]) {
+                uint32_t id = mine[u].idt >> kIdShift;
+                if constexpr (kW) {
+                    if (sum[u] != 0.0)
+                        reinterpret_cast<double *>(acc_raw)[id] += sum[u];
+                } else {
+                    if (csum[u] != 0)
+                        reinterpret_cast<int64_t *>(acc_raw)[id] += csum[u];
+                }
+            }
+        }
+    }
+}
+
+// Merge of aligned sorted blocks of size h into blocks of size 2h by the
+// depth-m key, one thread per item (its rank in the sibling block by binary
+// search).  kCount: the last coordinate; right-half active queries add the
+// left-half prefix P of active data weight ahead of them.  Otherwise: the
+// side bit of depth m is set and a copy is written for depth m+1.
+template <int NC, bool kW, bool kCount>
+__global__ __launch_bounds__(256) void k_merge_items(
+    const Item<NC> *__restrict__ in, const double *__restrict__ win,
+    Item<NC> *__restrict__ out, double *__restrict__ wout,
+    Item<NC> *__restrict__ copy, double *__restrict__ wcopy,
+    const void *__restrict__ P_raw, void *__restrict__ acc_raw, int64_t n,
+    int64_t h, int m, uint32_t mask) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    int64_t s = (p / (2 * h)) * (2 * h);
+    int64_t ha = (n - s) < h ? (n - s) : h;
+    int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
+    Item<NC> it = in[p];
+    uint64_t key = item_key(it, m);
+    bool inA = (p - s) < ha;
+    int64_t pos;
+    if (inA) {
+        // number of B items with key < this key
+        int64_t lo = 0, hi = hb;
+        const Item<NC> *B = in + s + ha;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (item_key(B[mid], m) < key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        pos = s + (p - s) + lo;
+    } else {
+        // number of A items with key <= this key
+        int64_t lo = 0, hi = ha;
+        const Item<NC> *A = in + s;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (item_key(A[mid], m) <= key)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int64_t ib = p - s - ha;
+        pos = s + ib + lo;
+        if constexpr (kCount) {
+            if (lo > 0 && active_query(it.idt, mask)) {
+                uint32_t id = it.idt >> kIdShift;
+                if constexpr (kW)
+                    reinterpret_cast<double *>(acc_raw)[id] +=
+                        reinterpret_cast<const double *>(P_raw)[s + lo - 1];
+                else
+                    reinterpret_cast<int64_t *>(acc_raw)[id] +=
+                        reinterpret_cast<const int64_t *>(P_raw)[s + lo - 1];
+            }
+        }
+    }
+    if constexpr (!kCount) {
+        const uint32_t bit = 1u << m;
+        it.idt = inA ? (it.idt & ~bit) : (it.idt | bit);
+        copy[pos] = it;
+        if constexpr (kW)
+            wcopy[pos] = win[p];
+    }
+    out[pos] = it;
+    if constexpr (kW)
+        wout[pos] = win[p];
+}
+
+// ---- segmented inclusive prefix of active-data weight ---------------------
+// Segments are the aligned blocks of size h (a power of two >= kBlockT).
+constexpr int kSegItems = 8;
+constexpr int kSegTile = 256 * kSegItems;
+
+template <int NC, bool kW, typename T>
+__device__ __forceinline__ T seg_value(const Item<NC> *S, const double *W, int64_t p,
+                                       int64_t n, uint32_t mask) {
+    if (p >= n)
+        return T(0);
+    if (!active_data(S[p].idt, mask))
+        return T(0);
+    if constexpr (kW)
+        return (T)W[p];
+    else
+        return T(1);
+}
+
+// per tile: sum of the values after the last segment head in the tile, and
+// whether the tile holds a head
+template <int NC, bool kW, typename T>
+__global__ __launch_bounds__(256) void k_seg_tiles(const Item<NC> *__restrict__ S,
+                                                   const double *__restrict__ W,
+                                                   int64_t n, int64_t h, uint32_t mask,
+                                                   T *__restrict__ tagg,
+                                                   uint32_t *__restrict__ thead) {
+    __shared__ T ws[4];
+    __shared__ uint32_t wf[4];
+    const int64_t base = (int64_t)blockIdx.x * kSegTile + (int64_t)threadIdx.x * kSegItems;
+    T v = T(0);
+    uint32_t f = 0;
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        int64_t p = base + u;
+        if (p < n && (p % h) == 0) {
+            v = T(0);
+            f = 1;
+        }
+        v = v + seg_value<NC, kW, T>(S, W, p, n, mask);
+    }
+    // segmented reduction across threads: combine (a,fa) then (b,fb)
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T ov = shfl_up(v, off);
+        uint32_t of = (uint32_t)__shfl_up((int)f, off, 64);
+        if (lane >= off && !f) {
+            v = ov + v;
+            f = of;
+        } else if (lane >= off) {
+            f = f | of;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) {
+        ws[w] = v;
+        wf[w] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T a = ws[0];
+        uint32_t fa = wf[0];
+        for (int q = 1; q < 4; ++q) {
+            if (wf[q]) {
+                a = ws[q];
+                fa = 1;
+            } else {
+                a = a + ws[q];
+            }
+        }
+        tagg[blockIdx.x] = a;
+        thead[blockIdx.x] = fa;
+    }
+}
+
+// carry-in of every tile (exclusive segmented scan over the tiles): one block
+// of 1024 threads, each owning a contiguous chunk of tiles
+template <typename T>
+__global__ __launch_bounds__(1024) void k_seg_carry(T *__restrict__ tagg,
+                                                    const uint32_t *__restrict__ thead,
+                                                    int64_t nt) {
+    __shared__ T ws[16];
+    __shared__ uint32_t wf[16];
+    const int64_t ch = ceil_div_dev(nt, 1024);
+    const int64_t t0 = (int64_t)threadIdx.x * ch;
+    const int64_t t1 = t0 + ch < nt ? t0 + ch : nt;
+    T v = T(0);
+    uint32_t f = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        if (thead[t]) {
+            v = tagg[t];
+            f = 1;
+        } else {
+            v = v + tagg[t];
+        }
+    }
+    const int lane = lane_id();
+    T inc = v;
+    uint32_t finc = f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T ov = shfl_up(inc, off);
+        uint32_t of = (uint32_t)__shfl_up((int)finc, off, 64);
+        if (lane >= off) {
+            if (!finc)
+                inc = ov + inc;
+            finc = finc | of;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) {
+        ws[w] = inc;
+        wf[w] = finc;
+    }
+    __syncthreads();
+    T pre = T(0);
+    for (int q = 0; q < w; ++q)
+        pre = wf[q] ? ws[q] : pre + ws[q];
+    T ex = shfl_up(inc, 1);
+    uint32_t exf = (uint32_t)__shfl_up((int)finc, 1, 64);
+    if (lane == 0)
+        ex = pre;
+    else if (!exf)
+        ex = pre + ex;
+    T carry = ex;
+    for (int64_t t = t0; t < t1; ++t) {
+        T a = tagg[t];
+        uint32_t h = thead[t];
+        tagg[t] = carry;
+        carry = h ? a : carry + a;
+    }
+}
+
+template <int NC, bool kW, typename T>
+__global__ __launch_bounds__(256) void k_seg_apply(const Item<NC> *__restrict__ S,
+                                                   const double *__restrict__ W,
+                                                   int64_t n, int64_t h, uint32_t mask,
+                                                   const T *__restrict__ carry,
+                                                   T *__restrict__ P) {
+    __shared__ T ws[4];
+    __shared__ uint32_t wf[4];
+    const int64_t base = (int64_t)blockIdx.x * kSegTile + (int64_t)threadIdx.x * kSegItems;
+    T vals[kSegItems];
+    T v = T(0);
+    uint32_t f = 0;
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        int64_t p = base + u;
+        if (p < n && (p % h) == 0) {
+            v = T(0);
+            f = 1;
+        }
+        vals[u] = seg_value<NC, kW, T>(S, W, p, n, mask);
+        v = v + vals[u];
+    }
+    // exclusive segmented scan across the block of thread aggregates
+    const int lane = lane_id();
+    T inc = v;
+    uint32_t finc = f;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T ov = shfl_up(inc, off);
+        uint32_t of = (uint32_t)__shfl_up((int)finc, off, 64);
+        if (lane >= off) {
+            if (!finc)
+                inc = ov + inc;
+            finc = finc | of;
+        }
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) {
+        ws[w] = inc;
+        wf[w] = finc;
+    }
+    __syncthreads();
+    // prefix from earlier waves and the tile carry
+    T pre = carry[blockIdx.x];
+    uint32_t pf = 0;
+    for (int q = 0; q < w; ++q) {
+        if (wf[q]) {
+            pre = ws[q];
+            pf = 1;
+        } else {
+            pre = pre + ws[q];
+        }
+    }
+    T ex = shfl_up(inc, 1);
+    uint32_t exf = (uint32_t)__shfl_up((int)finc, 1, 64);
+    if (lane == 0) {
+        ex = pre;
+    } else if (!exf) {
+        ex = pre + ex;
+    }
+    T run = ex;
+#pragma unroll
+    for (int u = 0; u < kSegItems; ++u) {
+        int64_t p = base + u;
+        if (p < n) {
+            if ((p % h) == 0)
+                run = T(0);
+            run = run + vals[u];
+            P[p] = run;
+        }
+    }
+    (void)pf;
+}
+
+// d == 1: the count of query q is the data weight up to its position
+template <bool kW, typename T>
+__global__ __launch_bounds__(256) void k_d1_collect(const Item<1> *__restrict__ S,
+                                                    const T *__restrict__ P, int64_t n,
+                                                    void *__restrict__ acc_raw) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    uint32_t idt = S[p].idt;
+    if ((idt & 1u) == 1u)
+        reinterpret_cast<T *>(acc_raw)[idt >> kIdShift] = P[p];
+}
+
+template <typename OutT, typename AccT>
+__global__ __launch_bounds__(256) void k_points_out(const AccT *__restrict__ acc,
+                                                    int64_t N, int scale,
+                                                    OutT *__restrict__ F) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N)
+        return;
+    if constexpr (std::is_same<AccT, int64_t>::value)
+        F[i] = (OutT)acc[i];
+    else
+        F[i] = scale ? (OutT)(acc[i] / (double)N) : (OutT)acc[i];
+}
+
+__global__ void k_zero_u32(uint32_t *a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        a[i] = 0u;
+}
+__global__ void k_zero_f64(double *a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        a[i] = 0.0;
+}
+
+// ----------------------------------------------------------- host driver
+template <int NC, bool kW> struct Dnc {
+    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    int d;
+    int64_t n;
+    hipStream_t s;
+    Item<NC> *S[MECDF_MAX_DIM];
+    Item<NC> *T[MECDF_MAX_DIM];
+    double *SW[MECDF_MAX_DIM];
+    double *TW[MECDF_MAX_DIM];
+    AccT *acc;
+    AccT *P;
+    AccT *tagg;
+    uint32_t *thead;
+
+    int prefix(int depth, int64_t h, uint32_t mask) {
+        Item<NC> *cur = S[depth];
+        double *cw = SW[depth];
+        int64_t nt = ceil_div(n, kSegTile);
+        hipLaunchKernelGGL((k_seg_tiles<NC, kW, AccT>), dim3((unsigned)nt), dim3(256), 0,
+                           s, cur, cw, n, h, mask, tagg, thead);
+        hipLaunchKernelGGL((k_seg_carry<AccT>), dim3(1), dim3(1024), 0, s, tagg, thead, nt);
+        hipLaunchKernelGGL((k_seg_apply<NC, kW, AccT>), dim3((unsigned)nt), dim3(256), 0,
+                           s, cur, cw, n, h, mask, tagg, P);
+        MECDF_LAUNCH_CHECK();
+        return MECDF_OK;
+    }
+
+    // solves depth `depth` inside aligned blocks of size H of S[depth]
+    int solve(int depth, int64_t H) {
+        const uint32_t mask = side_mask(depth);
+        const bool last = depth == d - 1;
+        {
+            ProfScope prof("points_block_brute", s);
+            hipLaunchKernelGGL((k_block_brute<NC, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
+                               dim3(256), 0, s, S[depth], SW[depth], (void *)acc, n, depth,
+                               mask);
+        }
+        MECDF_LAUNCH_CHECK();
+        const unsigned nb = (unsigned)ceil_div(n, 256);
+        for (int64_t h = kBlockT; h < H; h *= 2) {
+            if (last) {
+                {
+                    ProfScope prof("points_prefix", s);
+                    MECDF_TRY(prefix(depth, h, mask));
+                }
+                ProfScope prof("points_merge_count", s);
+                hipLaunchKernelGGL((k_merge_items<NC, kW, true>), dim3(nb), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], nullptr,
+                                   nullptr, (const void *)P, (void *)acc, n, h, depth, mask);
+            } else {
+                ProfScope prof("points_merge", s);
+                hipLaunchKernelGGL((k_merge_items<NC, kW, false>), dim3(nb), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
+                                   SW[depth + 1], nullptr, nullptr, n, h, depth, mask);
+            }
+            MECDF_LAUNCH_CHECK();
+            std::swap(S[depth], T[depth]);
+            std::swap(SW[depth], TW[depth]);
+            if (!last)
+                MECDF_TRY(solve(depth + 1, 2 * h));
+        }
+        return MECDF_OK;
+    }
+};
+
+template <int NC, bool kW, typename YT, typename OutT>
+static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
+                        int survival, hipStream_t s) {
+    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    const int64_t n2 = 2 * N;
+    const int depths = d > 1 ? d - 1 : 1;
+    ArenaPlan pl;
+    pl.add<uint64_t>((size_t)N);           // keys
+    pl.add<uint64_t>((size_t)N);
+    pl.add<uint64_t>((size_t)N);
+    pl.add<uint32_t>((size_t)N);           // idx
+    pl.add<uint32_t>((size_t)N);
+    pl.add<uint32_t>((size_t)N);
+    pl.add<uint32_t>((size_t)N);           // flags
+    pl.add<uint32_t>((size_t)N);           // excl
+    pl.add<uint32_t>((size_t)N * d);       // ranks
+    pl.add<uint32_t>((size_t)N);           // drop
+    pl.add<uint32_t>(8);                   // U
+    pl.add<uint32_t>(1);                   // nvalid
+    pl.add<uint64_t>((size_t)n2);          // topkey x3
+    pl.add<uint64_t>((size_t)n2);
+    pl.add<uint64_t>((size_t)n2);
+    pl.add<uint32_t>((size_t)n2);          // slot x3
+    pl.add<uint32_t>((size_t)n2);
+    pl.add<uint32_t>((size_t)n2);
+    pl.add<Item<NC>>((size_t)n2);          // items (slot order)
+    if (kW)
+        pl.add<double>((size_t)n2);
+    for (int q = 0; q < depths; ++q) {
+        pl.add<Item<NC>>((size_t)n2);
+        pl.add<Item<NC>>((size_t)n2);
+        if (kW) {
+            pl.add<double>((size_t)n2);
+            pl.add<double>((size_t)n2);
+        }
+    }
+    pl.add<AccT>((size_t)N);               // acc
+    pl.add<AccT>((size_t)n2);              // P
+    pl.add<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
+    pl.add<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
+    radix_plan(pl, n2);
+    void *wsb = nullptr;
+    MECDF_TRY(workspace_reserve(pl.used, &wsb));
+    Arena a;
+    a.base = (char *)wsb;
+    uint64_t *k0 = a.take<uint64_t>((size_t)N), *k1 = a.take<uint64_t>((size_t)N),
+             *k2 = a.take<uint64_t>((size_t)N);
+    uint32_t *i0 = a.take<uint32_t>((size_t)N), *i1 = a.take<uint32_t>((size_t)N),
+             *i2 = a.take<uint32_t>((size_t)N);
+    uint32_t *flags = a.take<uint32_t>((size_t)N);
+    uint32_t *excl = a.take<uint32_t>((size_t)N);
+    uint32_t *rank = a.take<uint32_t>((size_t)N * d);
+    uint32_t *drop = a.take<uint32_t>((size_t)N);
+    uint32_t *U = a.take<uint32_t>(8);
+    unsigned int *nvalid = a.take<unsigned int>(1);
+    uint64_t *tk0 = a.take<uint64_t>((size_t)n2), *tk1 = a.take<uint64_t>((size_t)n2),
+             *tk2 = a.take<uint64_t>((size_t)n2);
+    uint32_t *sl0 = a.take<uint32_t>((size_t)n2), *sl1 = a.take<uint32_t>((size_t)n2),
+             *sl2 = a.take<uint32_t>((size_t)n2);
+    Item<NC> *items = a.take<Item<NC>>((size_t)n2);
+    double *Wslot = kW ? a.take<double>((size_t)n2) : nullptr;
+    Dnc<NC, kW> dnc{};
+    dnc.d = d;
+    dnc.s = s;
+    for (int q = 0; q < depths; ++q) {
+        dnc.S[q + 1] = a.take<Item<NC>>((size_t)n2);
+        dnc.T[q + 1] = a.take<Item<NC>>((size_t)n2);
+        dnc.SW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
+        dnc.TW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
+    }
+    dnc.acc = a.take<AccT>((size_t)N);
+    dnc.P = a.take<AccT>((size_t)n2);
+    dnc.tagg = a.take<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
+    dnc.thead = a.take<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
+    RadixScratch rs = radix_take(a, n2);
+
+    const unsigned nbN = (unsigned)ceil_div(N, 256);
+    // ---- dense ranks per coordinate
+    {
+        ProfScope prof("points_ranks", s);
+        for (int k = 0; k < d; ++k) {
+            hipLaunchKernelGGL(k_fp_keys, dim3(nbN), dim3(256), 0, s, x, N, k, k0, i0, drop);
+            int which = 0;
+            MECDF_TRY((radix_sort_bits<uint64_t, uint32_t>(k0, i0, k1, i1, k2, i2, N, 0, 64,
+                                                           rs, s, &which)));
+            uint64_t *ks = which == 1 ? k1 : (which == 2 ? k2 : k0);
+            uint32_t *is = which == 1 ? i1 : (which == 2 ? i2 : i0);
+            hipLaunchKernelGGL(k_rank_flags, dim3(nbN), dim3(256), 0, s, ks, N, flags);
+            MECDF_TRY(scan_exclusive_u32(flags, excl, N, rs.bsum, s));
+            hipLaunchKernelGGL(k_rank_scatter, dim3(nbN), dim3(256), 0, s, flags, excl, is, N,
+                               rank + (size_t)k * N, U + k);
+        }
+        MECDF_LAUNCH_CHECK();
+    }
+    // ---- items, sorted by (coordinate 0, type)
+    const int kb = bits_for((uint64_t)N) + 1;
+    const uint64_t invalid_key = (kb >= 63) ? ~0ull : ((1ull << (kb + 1)) - 1ull);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, (uint32_t *)nvalid, (int64_t)1);
+    hipLaunchKernelGGL((k_make_items<NC, YT>), dim3(nbN), dim3(256), 0, s, rank, U, drop, y,
+                       N, d, survival, invalid_key, tk0, sl0, items, Wslot, nvalid);
+    MECDF_LAUNCH_CHECK();
+    int which = 0;
+    {
+        ProfScope prof("points_topsort", s);
+        MECDF_TRY((radix_sort_bits<uint64_t, uint32_t>(tk0, sl0, tk1, sl1, tk2, sl2, n2, 0,
+                                                       kb + 1, rs, s, &which)));
+    }
+    uint32_t *perm = which == 1 ? sl1 : (which == 2 ? sl2 : sl0);
+    unsigned int hn = 0;
+    MECDF_TRY_HIP(hipMemcpyAsync(&hn, nvalid, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    MECDF_TRY_HIP(hipStreamSynchronize(s));
+    const int64_t n = hn;
+    dnc.n = n;
+    hipLaunchKernelGGL((k_gather_items<NC>), dim3((unsigned)ceil_div(n > 0 ? n : 1, 256)),
+                       dim3(256), 0, s, perm, n, items, Wslot, dnc.S[1], dnc.SW[1]);
+    if constexpr (kW)
+        hipLaunchKernelGGL(k_zero_f64, dim3(nbN), dim3(256), 0, s, (double *)dnc.acc, N);
+    else
+        hipLaunchKernelGGL(k_zero_f64, dim3(nbN), dim3(256), 0, s, (double *)dnc.acc, N);
+    MECDF_LAUNCH_CHECK();
+
+    if (n > 0) {
+        if (d == 1) {
+            // prefix of data weight in (coordinate 0, type) order
+            MECDF_TRY(dnc.prefix(1, (int64_t)1 << 62, 0u));
+            hipLaunchKernelGGL((k_d1_collect<kW, AccT>), dim3((unsigned)ceil_div(n, 256)),
+                               dim3(256), 0, s, (const Item<1> *)dnc.S[1], dnc.P, n,
+                               (void *)dnc.acc);
+            MECDF_LAUNCH_CHECK();
+        } else {
+            int64_t H = 1;
+            while (H < n)
+                H *= 2;
+            MECDF_TRY(dnc.solve(1, H));
+        }
+    }
+    hipLaunchKernelGGL((k_points_out<OutT, AccT>), dim3(nbN), dim3(256), 0, s, dnc.acc, N,
+                       kW ? 1 : 0, F);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
+template <int NC>
+static int points_dispatch(int d, int64_t N, const double *x, const void *y, void *F,
+                           int survival, int prec, hipStream_t s) {
+    if (y == nullptr)
+        return points_run_t<NC, false, NoPayload, int64_t>(d, N, x, nullptr, (int64_t *)F,
+                                                           survival, s);
+    if (prec == MECDF_F64)
+        return points_run_t<NC, true, double, double>(d, N, x, (const double *)y,
+                                                      (double *)F, survival, s);
+    return points_run_t<NC, true, float, float>(d, N, x, (const float *)y, (float *)F,
+                                                survival, s);
+}
+
+int points_run(int d, int64_t N, const double *x, const void *y, void *F,
+               int survival, int prec, hipStream_t s) {
+    if (N > (int64_t(1) << 26)) {
+        set_error("the points path supports N <= 2^26");
+        return MECDF_EUNSUPPORTED;
+    }
+    switch (d) {
+    case 1:
+    case 2:
+        return points_dispatch<1>(d, N, x, y, F, survival, prec, s);
+    case 3:
+        return points_dispatch<2>(d, N, x, y, F, survival, prec, s);
+    case 4:
+        return points_dispatch<3>(d, N, x, y, F, survival, prec, s);
+    case 5:
+        return points_dispatch<4>(d, N, x, y, F, survival, prec, s);
+    default:
+        return points_dispatch<5>(d, N, x, y, F, survival, prec, s);
+    }
+}
+
 }  // namespace mecdf

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K *__restrict__ keys,
 constexpr int kOffChunk = 64;  // tiles per chunk
 
 // S[c*R + d] = sum of H[t*R + d] over the tiles t of chunk c
-__global__ __launch_bounds__(256) void k_off_chunks(const uint32_t *__restrict__ H,
+static __global__ __launch_bounds__(256) void k_off_chunks(const uint32_t *__restrict__ H,
                                                     int64_t ntiles, int R,
                                                     uint32_t *__restrict__ S) {
     int64_t nch = ceil_div_dev(ntiles, kOffChunk);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_off_chunks(const uint32_t *__restrict__
 // Per digit: exclusive scan of the chunk sums (in place), and the digit
 // bases B[d] = number of keys with a smaller digit.  One block of 512 threads;
 // loads are issued 16 at a time so that they overlap.
-__global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ S,
+static __global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ S,
                                                   int64_t nch, int R,
                                                   uint32_t *__restrict__ B) {
     __shared__ uint32_t tot[kRadixMaxDigits];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ S,
 }
 
 // H[t*R + d] <- offset of digit d in tile t (in place)
-__global__ __launch_bounds__(256) void k_off_final(uint32_t *__restrict__ H,
+static __global__ __launch_bounds__(256) void k_off_final(uint32_t *__restrict__ H,
                                                    int64_t ntiles, int R,
                                                    const uint32_t *__restrict__ S,
                                                    const uint32_t *__restrict__ B) {
@@ -161,7 +161,7 @@ __device__ __forceinline__ T block_exclusive_scan256(T v, T *wtot /*[4]*/,
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = 256 * kScanItems;
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in,
+static __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in,
                                                      int64_t n,
                                                      uint32_t *__restrict__ bsum) {
     __shared__ uint32_t wt[4];
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
         bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_sums(uint32_t *__restrict__ bsum,
+static __global__ __launch_bounds__(256) void k_scan_sums(uint32_t *__restrict__ bsum,
                                                    int64_t nb) {
     __shared__ uint32_t wt[4];
     uint32_t carry = 0;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void k_scan_sums(uint32_t *__restrict__ bsum,
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in,
+static __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in,
                                                     uint32_t *__restrict__ out,
                                                     int64_t n,
                                                     const uint32_t *__restrict__ bsum) {
