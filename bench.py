@@ -58,7 +58,59 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the timings of the other workloads")
     return ap.parse_args()
+
+
+def _time_calls(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(steps):
+        fn()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def secondary():
+    """Per-call times of the other workloads (points, kernel sums); figures of
+    the same library, reported beside the headline grid measurement."""
+    import numpy as np
+    import torch
+
+    from paper_2005_03246_amd import datagen, mecdf
+
+    out = {}
+    x = torch.from_numpy(datagen.config1()).cuda()
+    ms = _time_calls(lambda: (mecdf.ecdf_points(x), mecdf.esf_points(x)), 20, 3)
+    out["points_d2_N4096_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
+                                     "Gpoint-evals/s": 2 * 4096 / (ms * 1e-3) / 1e9}
+    x3 = torch.from_numpy(datagen.config3()).cuda()
+    n3 = x3.shape[1]
+    ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
+    out["points_d4_N2^22_tied_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
+                                          "Gpoint-evals/s": 2 * n3 / (ms * 1e-3) / 1e9}
+    del x3
+    x4, y4, h4 = datagen.config4()
+    n4 = x4.shape[1]
+    x4t = torch.from_numpy(x4).cuda()
+    y4t = torch.from_numpy(y4).cuda()
+    for prec in ("f64", "f32c"):
+        yy = y4t if prec == "f64" else y4t.float()
+        ms_k = _time_calls(lambda: mecdf.kde_laplace(x4t, h4, prec=prec), 2, 1)
+        ms_r = _time_calls(lambda: mecdf.kreg_laplace(x4t, yy, h4, prec=prec), 2, 1)
+        out["kde_nw_d2_N2^22_64h_" + prec] = {
+            "ms_kde_lcv": ms_k, "ms_nw_cv": ms_r,
+            "Gpoint-evals/s": 2 * 64 * n4 / ((ms_k + ms_r) * 1e-3) / 1e9}
+    return out
 
 
 def cpu_baseline(x, y, nodes, target_s):
@@ -186,6 +238,9 @@ def main():
         "kernels": kernels,
         "wall_s_timed": wall,
     }
+    if not args.no_secondary:
+        del F, Fb
+        out["secondary"] = secondary()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -726,24 +726,58 @@ __global__ __launch_bounds__(256) void k_kto_f64(const float *__restrict__ in, i
         out[i] = (double)in[i];
 }
 
-// deterministic mean of each row of terms[nb][n]: one block per row, fixed
-// strided partial sums then a fixed tree
-__global__ __launch_bounds__(256) void k_kmean(const double *__restrict__ terms, int64_t n,
-                                               int b0, double *__restrict__ score) {
-    __shared__ double part[256];
-    const int b = blockIdx.x;
+// deterministic mean of each row of terms[nb][n]: fixed chunks of kMeanChunk
+// items summed by one block each (fixed tree), then the chunk sums of a row
+// summed by one block (fixed tree)
+constexpr int kMeanChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_kpartial(const double *__restrict__ terms, int64_t n,
+                                                  int64_t nch, double *__restrict__ part) {
+    __shared__ double buf[256];
+    const int64_t c = blockIdx.x;
+    const int b = blockIdx.y;
+    const int64_t i0 = c * kMeanChunk;
     double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256)
-        s += terms[(int64_t)b * n + i];
-    part[threadIdx.x] = s;
+    for (int u = 0; u < kMeanChunk / 256; ++u) {
+        int64_t i = i0 + (int64_t)u * 256 + threadIdx.x;
+        if (i < n)
+            s += terms[(int64_t)b * n + i];
+    }
+    buf[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            part[threadIdx.x] += part[threadIdx.x + w];
+            buf[threadIdx.x] += buf[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        score[b0 + b] = part[0] / (double)n;
+        part[(int64_t)b * nch + c] = buf[0];
+}
+
+__global__ __launch_bounds__(256) void k_kmean(const double *__restrict__ part, int64_t nch,
+                                               int64_t n, int b0, double *__restrict__ score) {
+    __shared__ double buf[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < nch; i += 256)
+        s += part[(int64_t)b * nch + i];
+    buf[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            buf[threadIdx.x] += buf[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        score[b0 + b] = buf[0] / (double)n;
+}
+
+static void launch_mean(const double *terms, int64_t n, int nbh, int b0, double *part,
+                        double *score, hipStream_t s) {
+    int64_t nch = ceil_div(n, kMeanChunk);
+    hipLaunchKernelGGL(k_kpartial, dim3((unsigned)nch, (unsigned)nbh), dim3(256), 0, s, terms,
+                       n, nch, part);
+    hipLaunchKernelGGL(k_kmean, dim3((unsigned)nbh), dim3(256), 0, s, part, nch, n, b0, score);
 }
 
 // ----------------------------------------------------------- host driver
@@ -782,6 +816,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     pl.add<double>(3 * kKB);
     pl.add<double>((size_t)n);  // w0 / w1 as double (brute path)
     pl.add<double>((size_t)n);
+    pl.add<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
     radix_plan(pl, n);
     void *wsb = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &wsb));
@@ -815,6 +850,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     KCarry<T, CH> *car = a.take<KCarry<T, CH>>((size_t)nt + 1);
     double *ihk = a.take<double>(3 * kKB);
     double *w0d = a.take<double>(n), *w1d = a.take<double>(n);
+    double *mpart = a.take<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
     RadixScratch rs = radix_take(a, n);
     const unsigned nb = (unsigned)ceil_div(n, 256);
     const unsigned nbw = (unsigned)ceil_div(ceil_div(n, 64), 4);
@@ -858,7 +894,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                                    w0p, w1p, ihk, kb, b0, mode, out, terms);
             }
             if (score)
-                hipLaunchKernelGGL(k_kmean, dim3(kb.nb), dim3(256), 0, s, terms, n, b0, score);
+                launch_mean(terms, n, kb.nb, b0, mpart, score, s);
             MECDF_LAUNCH_CHECK();
         }
         return MECDF_OK;
@@ -932,7 +968,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                                d == 2 ? 1 : 0, kb, b0, mode, out, terms);
         }
         if (score)
-            hipLaunchKernelGGL(k_kmean, dim3(kb.nb), dim3(256), 0, s, terms, n, b0, score);
+            launch_mean(terms, n, kb.nb, b0, mpart, score, s);
         MECDF_LAUNCH_CHECK();
     }
     return MECDF_OK;

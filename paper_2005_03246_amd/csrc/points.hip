@@ -186,93 +186,130 @@ __device__ __forceinline__ bool active_query(uint32_t idt, uint32_t mask) {
 }
 inline uint32_t side_mask(int m) { return ((1u << (m - 1)) - 1u) << 1; }
 
-// Pairs inside each block of kBlockT items at depth m: query i counts the
-// active data j placed before it whose coordinates m..d-1 are all <= its own.
-// The same loop ranks the items by (coordinate m, type, position) and the
-// block is written back sorted by that key.
+// Pairs inside each block of kBlockT items at depth m: every active query
+// adds the weight of the active data placed before it whose coordinates
+// m..d-1 are all <= its own (the active data are first compacted in LDS, in
+// block order, so each query scans only them).  The block is then sorted by
+// (coordinate m, type, position) with a bitonic network in LDS and written
+// back; at the last coordinate (P != nullptr) the inclusive prefix of active
+// data weight in the sorted block is written to P for the merges above.
 template <int NC, bool kW>
 __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
                                                      double *__restrict__ W,
                                                      void *__restrict__ acc_raw,
-                                                     int64_t n, int m,
-                                                     uint32_t mask) {
-    constexpr int IPT = kBlockT / 256;
-    __shared__ Item<NC> sI[kBlockT];
-    __shared__ double sW[kW ? kBlockT : 1];
-    const int64_t base = (int64_t)blockIdx.x * kBlockT;
-    const int cnt = (int)((n - base) < kBlockT ? (n - base) : kBlockT);
-    for (int t = threadIdx.x; t < cnt; t += 256) {
+                                                     void *__restrict__ P_raw, int64_t n,
+                                                     int m, uint32_t mask) {
+    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    constexpr int T = kBlockT;
+    static_assert(T == 512, "two items per thread");
+    __shared__ Item<NC> sI[T];
+    __shared__ double sW[kW ? T : 1];
+    __shared__ uint64_t sk[T];
+    __shared__ uint32_t dIdx[T];
+    __shared__ uint32_t wt[4];
+    __shared__ AccT wtA[4];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * T;
+    const int cnt = (int)((n - base) < T ? (n - base) : T);
+    for (int t = tid; t < cnt; t += 256) {
         sI[t] = S[base + t];
         if constexpr (kW)
             sW[t] = W[base + t];
     }
     __syncthreads();
-    Item<NC> mine[IPT];
-    double mw[IPT];
-    int rank[IPT];
-    double sum[IPT];
-    int64_t csum[IPT];
-    bool isq[IPT];
-    uint64_t key[IPT];
+    // compact the active data (blocked: thread t owns local items 2t, 2t+1)
+    bool fd[2];
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-        int li = threadIdx.x + u * 256;
-        if (li < cnt) {
-            mine[u] = sI[li];
-            mw[u] = kW ? sW[li] : 0.0;
-            key[u] = item_key(mine[u], m);
-            isq[u] = active_query(mine[u].idt, mask);
-        } else {
-            isq[u] = false;
-            key[u] = ~0ull;
-        }
-        rank[u] = 0;
-        sum[u] = 0.0;
-        csum[u] = 0;
+    for (int u = 0; u < 2; ++u) {
+        int li = 2 * tid + u;
+        fd[u] = li < cnt && active_data(sI[li].idt, mask);
     }
-    for (int j = 0; j < cnt; ++j) {
-        Item<NC> J = sI[j];
-        uint64_t kj = item_key(J, m);
-        bool jd = active_data(J.idt, mask);
-        double wj = kW ? sW[j] : 0.0;
+    uint32_t nd;
+    uint32_t off = block_exclusive_scan256<uint32_t>((uint32_t)fd[0] + (uint32_t)fd[1], wt, &nd);
+    if (fd[0])
+        dIdx[off++] = 2 * tid;
+    if (fd[1])
+        dIdx[off] = 2 * tid + 1;
+    __syncthreads();
+    // active queries scan the active data before them
 #pragma unroll
-        for (int u = 0; u < IPT; ++u) {
-            int li = threadIdx.x + u * 256;
-            rank[u] += (kj < key[u] || (kj == key[u] && j < li)) ? 1 : 0;
-            if (jd && isq[u] && j < li) {
-                bool dom = true;
+    for (int u = 0; u < 2; ++u) {
+        int li = 2 * tid + u;
+        if (li >= cnt || !active_query(sI[li].idt, mask))
+            continue;
+        const Item<NC> me = sI[li];
+        AccT sum = AccT(0);
+        for (uint32_t k = 0; k < nd; ++k) {
+            uint32_t j = dIdx[k];
+            if ((int)j >= li)
+                break;
+            const Item<NC> J = sI[j];
+            bool dom = true;
 #pragma unroll
-                for (int k = 0; k < NC; ++k)
-                    if (k >= m - 1)
-                        dom = dom && (J.c[k] <= mine[u].c[k]);
-                if (dom) {
-                    if constexpr (kW)
-                        sum[u] += wj;
-                    else
-                        csum[u] += 1;
-                }
+            for (int q = 0; q < NC; ++q)
+                if (q >= m - 1)
+                    dom = dom && (J.c[q] <= me.c[q]);
+            if (dom) {
+                if constexpr (kW)
+                    sum += sW[j];
+                else
+                    sum += 1;
             }
         }
+        if (sum != AccT(0))
+            reinterpret_cast<AccT *>(acc_raw)[me.idt >> kIdShift] += sum;
+    }
+    // bitonic sort of (key, local index)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        int li = tid + u * 256;
+        sk[li] = li < cnt ? ((item_key(sI[li], m) << 10) | (uint64_t)li) : ~0ull;
     }
     __syncthreads();
+    for (int k = 2; k <= T; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-        int li = threadIdx.x + u * 256;
-        if (li < cnt) {
-            S[base + rank[u]] = mine[u];
-            if constexpr (kW)
-                W[base + rank[u]] = mw[u];
-            if (isq[u]) {
-                uint32_t id = mine[u].idt >> kIdShift;
-                if constexpr (kW) {
-                    if (sum[u] != 0.0)
-                        reinterpret_cast<double *>(acc_raw)[id] += sum[u];
-                } else {
-                    if (csum[u] != 0)
-                        reinterpret_cast<int64_t *>(acc_raw)[id] += csum[u];
+            for (int u = 0; u < 2; ++u) {
+                int i = tid + u * 256;
+                int pr = i ^ j;
+                if (pr > i) {
+                    uint64_t a = sk[i], b = sk[pr];
+                    bool asc = (i & k) == 0;
+                    if (asc ? (a > b) : (a < b)) {
+                        sk[i] = b;
+                        sk[pr] = a;
+                    }
                 }
             }
+            __syncthreads();
         }
+    }
+    // write back in sorted order; prefix of active data for the merges
+    AccT pv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        int r = 2 * tid + u;
+        pv[u] = AccT(0);
+        if (r < cnt) {
+            int li = (int)(sk[r] & 1023ull);
+            S[base + r] = sI[li];
+            if constexpr (kW)
+                W[base + r] = sW[li];
+            if (active_data(sI[li].idt, mask)) {
+                if constexpr (kW)
+                    pv[u] = sW[li];
+                else
+                    pv[u] = 1;
+            }
+        }
+    }
+    if (P_raw) {
+        AccT ex = block_exclusive_scan256<AccT>(pv[0] + pv[1], wtA, nullptr);
+        AccT *P = reinterpret_cast<AccT *>(P_raw);
+        if (2 * tid < cnt)
+            P[base + 2 * tid] = ex + pv[0];
+        if (2 * tid + 1 < cnt)
+            P[base + 2 * tid + 1] = ex + pv[0] + pv[1];
     }
 }
 
@@ -286,8 +323,9 @@ __global__ __launch_bounds__(256) void k_merge_items(
     const Item<NC> *__restrict__ in, const double *__restrict__ win,
     Item<NC> *__restrict__ out, double *__restrict__ wout,
     Item<NC> *__restrict__ copy, double *__restrict__ wcopy,
-    const void *__restrict__ P_raw, void *__restrict__ acc_raw, int64_t n,
-    int64_t h, int m, uint32_t mask) {
+    const void *__restrict__ Pin_raw, void *__restrict__ Pout_raw,
+    void *__restrict__ acc_raw, int64_t n, int64_t h, int m, uint32_t mask) {
+    using AccT = typename std::conditional<kW, double, int64_t>::type;
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n)
         return;
@@ -297,10 +335,10 @@ __global__ __launch_bounds__(256) void k_merge_items(
     Item<NC> it = in[p];
     uint64_t key = item_key(it, m);
     bool inA = (p - s) < ha;
-    int64_t pos;
+    int64_t pos, lo = 0;
     if (inA) {
         // number of B items with key < this key
-        int64_t lo = 0, hi = hb;
+        int64_t hi = hb;
         const Item<NC> *B = in + s + ha;
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
@@ -309,10 +347,10 @@ __global__ __launch_bounds__(256) void k_merge_items(
             else
                 hi = mid;
         }
-        pos = s + (p - s) + lo;
+        pos = p + lo;
     } else {
         // number of A items with key <= this key
-        int64_t lo = 0, hi = ha;
+        int64_t hi = ha;
         const Item<NC> *A = in + s;
         while (lo < hi) {
             int64_t mid = (lo + hi) >> 1;
@@ -321,21 +359,18 @@ __global__ __launch_bounds__(256) void k_merge_items(
             else
                 hi = mid;
         }
-        int64_t ib = p - s - ha;
-        pos = s + ib + lo;
-        if constexpr (kCount) {
-            if (lo > 0 && active_query(it.idt, mask)) {
-                uint32_t id = it.idt >> kIdShift;
-                if constexpr (kW)
-                    reinterpret_cast<double *>(acc_raw)[id] +=
-                        reinterpret_cast<const double *>(P_raw)[s + lo - 1];
-                else
-                    reinterpret_cast<int64_t *>(acc_raw)[id] +=
-                        reinterpret_cast<const int64_t *>(P_raw)[s + lo - 1];
-            }
-        }
+        pos = s + (p - s - ha) + lo;
     }
-    if constexpr (!kCount) {
+    if constexpr (kCount) {
+        // P: inclusive prefix of active data weight within each sorted block
+        const AccT *Pin = reinterpret_cast<const AccT *>(Pin_raw);
+        AccT other = AccT(0);
+        if (lo > 0)
+            other = Pin[(inA ? s + ha : s) + lo - 1];
+        if (!inA && other != AccT(0) && active_query(it.idt, mask))
+            reinterpret_cast<AccT *>(acc_raw)[it.idt >> kIdShift] += other;
+        reinterpret_cast<AccT *>(Pout_raw)[pos] = Pin[p] + other;
+    } else {
         const uint32_t bit = 1u << m;
         it.idt = inA ? (it.idt & ~bit) : (it.idt | bit);
         copy[pos] = it;
@@ -603,6 +638,7 @@ template <int NC, bool kW> struct Dnc {
     double *TW[MECDF_MAX_DIM];
     AccT *acc;
     AccT *P;
+    AccT *P2;
     AccT *tagg;
     uint32_t *thead;
 
@@ -626,26 +662,24 @@ template <int NC, bool kW> struct Dnc {
         {
             ProfScope prof("points_block_brute", s);
             hipLaunchKernelGGL((k_block_brute<NC, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
-                               dim3(256), 0, s, S[depth], SW[depth], (void *)acc, n, depth,
-                               mask);
+                               dim3(256), 0, s, S[depth], SW[depth], (void *)acc,
+                               last ? (void *)P : nullptr, n, depth, mask);
         }
         MECDF_LAUNCH_CHECK();
         const unsigned nb = (unsigned)ceil_div(n, 256);
         for (int64_t h = kBlockT; h < H; h *= 2) {
             if (last) {
-                {
-                    ProfScope prof("points_prefix", s);
-                    MECDF_TRY(prefix(depth, h, mask));
-                }
                 ProfScope prof("points_merge_count", s);
                 hipLaunchKernelGGL((k_merge_items<NC, kW, true>), dim3(nb), dim3(256), 0, s,
                                    S[depth], SW[depth], T[depth], TW[depth], nullptr,
-                                   nullptr, (const void *)P, (void *)acc, n, h, depth, mask);
+                                   nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
+                                   depth, mask);
+                std::swap(P, P2);
             } else {
                 ProfScope prof("points_merge", s);
                 hipLaunchKernelGGL((k_merge_items<NC, kW, false>), dim3(nb), dim3(256), 0, s,
                                    S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
-                                   SW[depth + 1], nullptr, nullptr, n, h, depth, mask);
+                                   SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth, mask);
             }
             MECDF_LAUNCH_CHECK();
             std::swap(S[depth], T[depth]);
@@ -695,6 +729,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     }
     pl.add<AccT>((size_t)N);               // acc
     pl.add<AccT>((size_t)n2);              // P
+    pl.add<AccT>((size_t)n2);              // P2
     pl.add<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
     pl.add<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
     radix_plan(pl, n2);
@@ -729,6 +764,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     }
     dnc.acc = a.take<AccT>((size_t)N);
     dnc.P = a.take<AccT>((size_t)n2);
+    dnc.P2 = a.take<AccT>((size_t)n2);
     dnc.tagg = a.take<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
     dnc.thead = a.take<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
     RadixScratch rs = radix_take(a, n2);

@@ -152,7 +152,10 @@ __device__ __forceinline__ T block_exclusive_scan256(T v, T *wtot /*[4]*/,
         off = off + wtot[i];
     if (total)
         *total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-    T r = off + inc - v;
+    // exclusive value from the left neighbour (no subtraction: exact for
+    // floating-point values too)
+    T ex = shfl_up(inc, 1);
+    T r = lane == 0 ? off : off + ex;
     __syncthreads();
     return r;
 }
