@@ -32,7 +32,7 @@ def hmat(hs, d):
 
 
 CASES = [(1, 2), (1, 700), (1, 5000), (2, 2), (2, 63), (2, 64), (2, 65), (2, 1000),
-         (2, 3000), (3, 2), (3, 900)]
+         (2, 3000), (3, 2), (3, 64), (3, 200), (3, 900), (3, 3000)]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -61,7 +61,7 @@ def test_kde_random(lib, case):
     assert rel_err(f32.cpu().numpy(), want32, scale32) <= 1e-5
 
 
-@pytest.mark.parametrize("case", [(1, 800), (2, 70), (2, 2500), (3, 600)])
+@pytest.mark.parametrize("case", [(1, 800), (2, 70), (2, 2500), (3, 600), (3, 2100)])
 def test_nw_random(lib, case):
     d, n = case
     g = np.random.default_rng(900 + d + n)
