@@ -175,6 +175,80 @@ int kde_laplace(int d, int64_t N, const double *x, const void *w, int nh,
 int kreg_laplace(int d, int64_t N, const double *x, const void *y, int nh,
                  const double *h, void *m, double *cv, int prec, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Bandwidth selection (batched exact LOO likelihood cross-validation, and a
+ * learned proposal that only decides where to evaluate it).
+ * ------------------------------------------------------------------- */
+
+/* One dataset: d coordinates (1..3) of N points, device x[k*N + i]. */
+typedef struct {
+    int d;
+    int64_t N;
+    const double *x;
+} mecdf_dataset;
+
+/*
+ * mecdf_kde_lcv_batched -- the likelihood CV score of kde_laplace for many
+ * datasets and isotropic bandwidths: for dataset s, the nh[s] bandwidths
+ * h[off_s .. off_s + nh[s]) (off_s = nh[0] + ... + nh[s-1]), each used on
+ * every axis, give lcv[off_s + b] (device doubles).  sets, nh and h are host
+ * arrays.  Datasets are processed in order on the stream; same errors as
+ * kde_laplace.
+ */
+int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
+                          const double *h, double *lcv, int prec, void *stream);
+
+/*
+ * mecdf_bw_features -- 32 summary statistics per dataset (device floats,
+ * feat[s*32 + q]), computed on the device in one block per dataset:
+ * log N / 10, d / 3, per-axis log sd, skewness, excess kurtosis / 10,
+ * mean |correlation|, log h0 with h0 = (geometric-mean sd) N^(-1/(d+4))
+ * (index 12), log geometric-mean sd, per-axis mean |x - mean| / sd and the
+ * fraction of points within half a sd of the mean; unused entries are 0.
+ */
+int mecdf_bw_features(const mecdf_dataset *sets, int nsets, float *feat,
+                      void *stream);
+
+/*
+ * Network 32 -> 128 -> 128 -> 1 with ReLU activations; its parameters are
+ * one device float vector of MECDF_MLP_PARAMS entries laid out as
+ * W1[128][32], b1[128], W2[128][128], b2[128], w3[128], b3.  Matrix products
+ * use bfloat16 operands (round to nearest even) with float32 accumulation.
+ *
+ * mecdf_mlp_forward: out[r] for the B rows feat[r*32 .. r*32+32).
+ * mecdf_mlp_grad:    gradient of the mean squared error
+ *                    (1/B) sum_r (out[r] - target[r])^2 into grad[MECDF_MLP_PARAMS]
+ *                    and the loss into loss[0] (loss may be NULL).
+ * mecdf_mlp_train:   `steps` full-batch Adam steps (beta1 0.9, beta2 0.999,
+ *                    eps 1e-8, learning rate lr) updating params in place;
+ *                    adam is device float[2*MECDF_MLP_PARAMS], zero before the
+ *                    first step; losses[t] (device, optional) is the loss
+ *                    before step t.
+ * All pointers are device pointers; B >= 1.
+ */
+#define MECDF_MLP_PARAMS 20865
+int mecdf_mlp_forward(int B, const float *feat, const float *params, float *out,
+                      void *stream);
+int mecdf_mlp_grad(int B, const float *feat, const float *target,
+                   const float *params, float *grad, float *loss, void *stream);
+int mecdf_mlp_train(int B, const float *feat, const float *target, float *params,
+                    float *adam, int steps, float lr, float *losses, void *stream);
+
+/*
+ * mecdf_bw_select -- likelihood-CV bandwidth on an ascending grid of nhg
+ * isotropic bandwidths (hgrid, host).  The network proposes
+ * log h = feat[12] + net(feat); the exact LOO likelihood score is evaluated
+ * at the four grid bandwidths around the proposal, and the evaluated window
+ * is extended by four grid points at a time towards the best score until the
+ * best score is interior to it (or at the grid's end).  Returns, per dataset
+ * (host arrays), the chosen grid index, its LCV score (lcv_out may be NULL)
+ * and the number of bandwidths evaluated (evals_out may be NULL).  Every
+ * returned score is an exact evaluation.  Synchronous: waits for the device.
+ */
+int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params,
+                    int nhg, const double *hgrid, int *hidx_out, double *lcv_out,
+                    int *evals_out, void *stream);
+
 /* Frees the workspace of every device (synchronises those devices). */
 void mecdf_release(void);
 

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -15,6 +16,12 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh,
             const double *h, void *f, double *score, int regression,
             int prec, hipStream_t s);
+int bw_features(const mecdf_dataset *sets, int nsets, float *feat, hipStream_t s);
+int mlp_forward(int B, const float *X, const float *P, float *out, hipStream_t s);
+int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, float *loss,
+             hipStream_t s);
+int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps,
+              float lr, float *losses, hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -173,6 +180,206 @@ int kreg_laplace(int d, int64_t N, const double *x, const void *y, int nh,
     if (y == nullptr)
         return fail(MECDF_EINVAL, "y is NULL");
     return kde_run(d, N, x, y, nh, h, m, cv, 1, prec, (hipStream_t)stream);
+}
+
+static int check_sets(const mecdf_dataset *sets, int nsets) {
+    if (nsets < 1 || sets == nullptr)
+        return fail(MECDF_EINVAL, "need at least one dataset");
+    for (int i = 0; i < nsets; ++i) {
+        if (sets[i].d < 1 || sets[i].d > 3)
+            return fail(MECDF_EINVAL, "dataset dimension must be 1..3");
+        if (sets[i].N < 2 || sets[i].x == nullptr)
+            return fail(MECDF_EINVAL, "datasets need N >= 2 points");
+        if (sets[i].N >= (int64_t(1) << 31))
+            return fail(MECDF_EUNSUPPORTED, "dataset too large");
+    }
+    return MECDF_OK;
+}
+
+int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
+                          const double *h, double *lcv, int prec, void *stream) {
+    MECDF_TRY(check_sets(sets, nsets));
+    if (nh == nullptr || h == nullptr || lcv == nullptr)
+        return fail(MECDF_EINVAL, "nh, h and lcv are required");
+    int64_t off = 0;
+    for (int i = 0; i < nsets; ++i) {
+        if (nh[i] < 0 || nh[i] > 256)
+            return fail(MECDF_EINVAL, "nh must be in 0..256 per dataset");
+        for (int b = 0; b < nh[i]; ++b)
+            if (!(h[off + b] > 0.0) || !std::isfinite(h[off + b]))
+                return fail(MECDF_EINVAL, "bandwidths must be positive and finite");
+        off += nh[i];
+    }
+    off = 0;
+    std::vector<double> hh;
+    for (int i = 0; i < nsets; ++i) {
+        if (nh[i] > 0) {
+            const int d = sets[i].d;
+            hh.assign((size_t)nh[i] * d, 0.0);
+            for (int b = 0; b < nh[i]; ++b)
+                for (int k = 0; k < d; ++k)
+                    hh[(size_t)b * d + k] = h[off + b];
+            MECDF_TRY(kde_run(d, sets[i].N, sets[i].x, nullptr, nh[i], hh.data(), nullptr,
+                              lcv + off, 0, prec, (hipStream_t)stream));
+        }
+        off += nh[i];
+    }
+    return MECDF_OK;
+}
+
+int mecdf_bw_features(const mecdf_dataset *sets, int nsets, float *feat, void *stream) {
+    MECDF_TRY(check_sets(sets, nsets));
+    if (feat == nullptr)
+        return fail(MECDF_EINVAL, "feat is NULL");
+    return bw_features(sets, nsets, feat, (hipStream_t)stream);
+}
+
+int mecdf_mlp_forward(int B, const float *feat, const float *params, float *out,
+                      void *stream) {
+    if (B < 1 || !feat || !params || !out)
+        return fail(MECDF_EINVAL, "mlp_forward: bad arguments");
+    return mlp_forward(B, feat, params, out, (hipStream_t)stream);
+}
+
+int mecdf_mlp_grad(int B, const float *feat, const float *target, const float *params,
+                   float *grad, float *loss, void *stream) {
+    if (B < 1 || !feat || !target || !params || !grad)
+        return fail(MECDF_EINVAL, "mlp_grad: bad arguments");
+    return mlp_grad(B, feat, target, params, grad, loss, (hipStream_t)stream);
+}
+
+int mecdf_mlp_train(int B, const float *feat, const float *target, float *params,
+                    float *adam, int steps, float lr, float *losses, void *stream) {
+    if (B < 1 || !feat || !target || !params || !adam || steps < 0 || !(lr > 0.f))
+        return fail(MECDF_EINVAL, "mlp_train: bad arguments");
+    return mlp_train(B, feat, target, params, adam, steps, lr, losses, (hipStream_t)stream);
+}
+
+int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, int nhg,
+                    const double *hgrid, int *hidx_out, double *lcv_out, int *evals_out,
+                    void *stream) {
+    MECDF_TRY(check_sets(sets, nsets));
+    if (!params || !hgrid || !hidx_out || nhg < 1 || nhg > 4096)
+        return fail(MECDF_EINVAL, "bw_select: bad arguments");
+    for (int j = 0; j < nhg; ++j)
+        if (!(hgrid[j] > 0.0) || (j > 0 && !(hgrid[j] > hgrid[j - 1])))
+            return fail(MECDF_EINVAL, "hgrid must be positive and ascending");
+    hipStream_t s = (hipStream_t)stream;
+    // device buffers of this call (outside the shared workspace, which the
+    // kernel sums below reuse)
+    float *feat = nullptr, *pred = nullptr;
+    double *lcvd = nullptr;
+    MECDF_TRY_HIP(hipMalloc(&feat, sizeof(float) * 32 * nsets));
+    hipError_t e1 = hipMalloc(&pred, sizeof(float) * nsets);
+    hipError_t e2 = hipMalloc(&lcvd, sizeof(double) * 4 * nsets);
+    auto cleanup = [&]() {
+        (void)hipFree(feat);
+        (void)hipFree(pred);
+        (void)hipFree(lcvd);
+    };
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        cleanup();
+        return fail(MECDF_ENOMEM, "bw_select: allocation failed");
+    }
+    int rc = bw_features(sets, nsets, feat, s);
+    if (rc == MECDF_OK)
+        rc = mlp_forward(nsets, feat, params, pred, s);
+    std::vector<float> hf((size_t)32 * nsets), hp(nsets);
+    if (rc == MECDF_OK &&
+        (hipMemcpyAsync(hf.data(), feat, sizeof(float) * 32 * nsets, hipMemcpyDeviceToHost, s) !=
+             hipSuccess ||
+         hipMemcpyAsync(hp.data(), pred, sizeof(float) * nsets, hipMemcpyDeviceToHost, s) !=
+             hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        rc = fail(MECDF_EDEVICE, "bw_select: copy failed");
+    if (rc != MECDF_OK) {
+        cleanup();
+        return rc;
+    }
+    // evaluated window [lo, hi] per dataset and its scores
+    std::vector<int> lo(nsets), hi(nsets), best(nsets), evals(nsets, 0), done(nsets, 0);
+    std::vector<std::vector<double>> sc(nsets, std::vector<double>(nhg, -INFINITY));
+    const double l0 = std::log(hgrid[0]);
+    const double dl = nhg > 1 ? (std::log(hgrid[nhg - 1]) - l0) / (nhg - 1) : 1.0;
+    std::vector<int> nh(nsets);
+    std::vector<double> hv;
+    std::vector<int> want_lo(nsets), want_hi(nsets);
+    for (int i = 0; i < nsets; ++i) {
+        double lh = (double)hf[(size_t)i * 32 + 12] + (double)hp[i];
+        double jf = std::isfinite(lh) ? (lh - l0) / dl : 0.0;
+        int j0 = (int)std::lround(jf) - 1;
+        int w = nhg < 4 ? nhg : 4;
+        if (j0 > nhg - w)
+            j0 = nhg - w;
+        if (j0 < 0)
+            j0 = 0;
+        want_lo[i] = j0;
+        want_hi[i] = j0 + w - 1;
+        lo[i] = j0;
+        hi[i] = j0 - 1;  // nothing evaluated yet
+    }
+    for (int round = 0; round < nhg && rc == MECDF_OK; ++round) {
+        hv.clear();
+        bool any = false;
+        for (int i = 0; i < nsets; ++i) {
+            nh[i] = 0;
+            if (done[i])
+                continue;
+            for (int j = want_lo[i]; j <= want_hi[i]; ++j) {
+                hv.push_back(hgrid[j]);
+                ++nh[i];
+            }
+            any = any || nh[i] > 0;
+        }
+        if (!any)
+            break;
+        rc = mecdf_kde_lcv_batched(sets, nsets, nh.data(), hv.data(), lcvd, MECDF_F64, stream);
+        std::vector<double> got(hv.size());
+        if (rc == MECDF_OK &&
+            (hipMemcpyAsync(got.data(), lcvd, sizeof(double) * hv.size(), hipMemcpyDeviceToHost,
+                            s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            rc = fail(MECDF_EDEVICE, "bw_select: copy failed");
+        if (rc != MECDF_OK)
+            break;
+        size_t off = 0;
+        for (int i = 0; i < nsets; ++i) {
+            if (done[i] || nh[i] == 0)
+                continue;
+            for (int j = want_lo[i]; j <= want_hi[i]; ++j)
+                sc[i][j] = got[off++];
+            evals[i] += nh[i];
+            lo[i] = want_lo[i] < lo[i] ? want_lo[i] : lo[i];
+            hi[i] = want_hi[i] > hi[i] ? want_hi[i] : hi[i];
+            int b = lo[i];
+            for (int j = lo[i]; j <= hi[i]; ++j)
+                if (sc[i][j] > sc[i][b])
+                    b = j;
+            best[i] = b;
+            if (b == lo[i] && lo[i] > 0) {
+                want_hi[i] = lo[i] - 1;
+                want_lo[i] = lo[i] - 4 > 0 ? lo[i] - 4 : 0;
+            } else if (b == hi[i] && hi[i] < nhg - 1) {
+                want_lo[i] = hi[i] + 1;
+                want_hi[i] = hi[i] + 4 < nhg - 1 ? hi[i] + 4 : nhg - 1;
+            } else {
+                done[i] = 1;
+            }
+        }
+        // need room for the next round's scores
+        (void)off;
+    }
+    cleanup();
+    if (rc != MECDF_OK)
+        return rc;
+    for (int i = 0; i < nsets; ++i) {
+        hidx_out[i] = best[i];
+        if (lcv_out)
+            lcv_out[i] = sc[i][best[i]];
+        if (evals_out)
+            evals_out[i] = evals[i];
+    }
+    return MECDF_OK;
 }
 
 void mecdf_release(void) { mecdf::workspace_release_all(); }

@@ -282,3 +282,121 @@ def profile_collect(max_names: int = 64):
         nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (float(ms[i]), int(cnt[i]))
     return out
+
+
+# ------------------------------------------------------- bandwidth selection
+MLP_PARAMS = 20865
+N_FEATURES = 32
+
+
+class _Dataset(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64), ("x", ctypes.c_void_p)]
+
+
+_lib.mecdf_kde_lcv_batched.argtypes = [_P, _I, _P, _P, _P, _I, _P]
+_lib.mecdf_kde_lcv_batched.restype = _I
+_lib.mecdf_bw_features.argtypes = [_P, _I, _P, _P]
+_lib.mecdf_bw_features.restype = _I
+_lib.mecdf_mlp_forward.argtypes = [_I, _P, _P, _P, _P]
+_lib.mecdf_mlp_forward.restype = _I
+_lib.mecdf_mlp_grad.argtypes = [_I, _P, _P, _P, _P, _P, _P]
+_lib.mecdf_mlp_grad.restype = _I
+_lib.mecdf_mlp_train.argtypes = [_I, _P, _P, _P, _P, _I, ctypes.c_float, _P, _P]
+_lib.mecdf_mlp_train.restype = _I
+_lib.mecdf_bw_select.argtypes = [_P, _I, _P, _I, _P, _P, _P, _P, _P]
+_lib.mecdf_bw_select.restype = _I
+
+
+def _sets(datasets):
+    arr = (_Dataset * len(datasets))()
+    keep = []
+    for i, x in enumerate(datasets):
+        x = _x(x)
+        keep.append(x)
+        arr[i].d = x.shape[0]
+        arr[i].N = x.shape[1]
+        arr[i].x = x.data_ptr()
+    return arr, keep
+
+
+def kde_lcv_batched(datasets, hs, prec="f64", stream=None):
+    """LCV scores for a list of (d, N) GPU datasets; hs[i] is the list of
+    isotropic bandwidths of dataset i.  Returns a list of (len(hs[i]),) float64
+    GPU tensors (C ABI ``mecdf_kde_lcv_batched``)."""
+    arr, keep = _sets(datasets)
+    nh = (ctypes.c_int * len(datasets))(*[len(h) for h in hs])
+    flat = [float(v) for h in hs for v in h]
+    hv = (ctypes.c_double * max(1, len(flat)))(*flat)
+    out = torch.empty((max(1, len(flat)),), dtype=torch.float64, device=keep[0].device)
+    _check(_lib.mecdf_kde_lcv_batched(ctypes.addressof(arr), len(datasets), nh, hv,
+                                      _ptr(out), _prec(prec), _stream_ptr(stream)),
+           "mecdf_kde_lcv_batched")
+    res, off = [], 0
+    for h in hs:
+        res.append(out[off:off + len(h)])
+        off += len(h)
+    return res
+
+
+def bw_features(datasets, stream=None):
+    """(nsets, 32) float32 GPU tensor of summary features (C ABI
+    ``mecdf_bw_features``)."""
+    arr, keep = _sets(datasets)
+    feat = torch.empty((len(datasets), N_FEATURES), dtype=torch.float32, device=keep[0].device)
+    _check(_lib.mecdf_bw_features(ctypes.addressof(arr), len(datasets), _ptr(feat),
+                                  _stream_ptr(stream)), "mecdf_bw_features")
+    return feat
+
+
+def _f32(t):
+    if not (t.is_cuda and t.dtype == torch.float32):
+        raise TypeError("expected a float32 GPU tensor")
+    return t.contiguous()
+
+
+def mlp_forward(feat, params, stream=None):
+    feat = _f32(feat)
+    params = _f32(params)
+    out = torch.empty((feat.shape[0],), dtype=torch.float32, device=feat.device)
+    _check(_lib.mecdf_mlp_forward(feat.shape[0], _ptr(feat), _ptr(params), _ptr(out),
+                                  _stream_ptr(stream)), "mecdf_mlp_forward")
+    return out
+
+
+def mlp_grad(feat, target, params, stream=None):
+    feat, target, params = _f32(feat), _f32(target), _f32(params)
+    grad = torch.empty((MLP_PARAMS,), dtype=torch.float32, device=feat.device)
+    loss = torch.empty((1,), dtype=torch.float32, device=feat.device)
+    _check(_lib.mecdf_mlp_grad(feat.shape[0], _ptr(feat), _ptr(target), _ptr(params),
+                               _ptr(grad), _ptr(loss), _stream_ptr(stream)), "mecdf_mlp_grad")
+    return grad, loss
+
+
+def mlp_train(feat, target, params, adam, steps, lr, stream=None):
+    """In-place Adam steps on params (float32 GPU vector); returns the losses."""
+    feat, target = _f32(feat), _f32(target)
+    if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()):
+        raise TypeError("params must be a contiguous float32 GPU tensor")
+    losses = torch.empty((max(1, steps),), dtype=torch.float32, device=feat.device)
+    _check(_lib.mecdf_mlp_train(feat.shape[0], _ptr(feat), _ptr(target), _ptr(params),
+                                _ptr(adam), int(steps), float(lr), _ptr(losses),
+                                _stream_ptr(stream)), "mecdf_mlp_train")
+    return losses[:steps]
+
+
+def bw_select(datasets, params, hgrid, stream=None):
+    """Learned-proposal LCV bandwidth selection (C ABI ``mecdf_bw_select``).
+    Returns numpy arrays (grid index, exact LCV there, bandwidths evaluated)."""
+    import numpy as np
+
+    arr, keep = _sets(datasets)
+    params = _f32(params)
+    n = len(datasets)
+    hg = (ctypes.c_double * len(hgrid))(*[float(v) for v in hgrid])
+    hidx = (ctypes.c_int * n)()
+    lcv = (ctypes.c_double * n)()
+    ev = (ctypes.c_int * n)()
+    _check(_lib.mecdf_bw_select(ctypes.addressof(arr), n, _ptr(params), len(hgrid), hg, hidx,
+                                lcv, ev, _stream_ptr(stream)), "mecdf_bw_select")
+    return (np.array(hidx[:], dtype=np.int64), np.array(lcv[:], dtype=np.float64),
+            np.array(ev[:], dtype=np.int64))
