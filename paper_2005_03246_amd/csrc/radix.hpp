@@ -245,13 +245,15 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     int shift, int bits, int64_t ntiles) {
     constexpr bool kPay = !std::is_same<P, NoPayload>::value;
     constexpr int kPaySize = kPay ? (int)sizeof(P) : 1;
+    constexpr int kStage = (int)sizeof(K) > kPaySize ? (int)sizeof(K) : kPaySize;
     __shared__ uint32_t wcnt[4][kRadixMaxDigits];
     __shared__ uint32_t loff[kRadixMaxDigits];
     __shared__ uint32_t gbase[kRadixMaxDigits];
     __shared__ uint32_t wt[4];
-    __shared__ K s_key[kRadixTile];
-    __shared__ char s_pay_raw[kRadixTile * kPaySize];
-    P *s_pay = reinterpret_cast<P *>(s_pay_raw);
+    // one staging buffer, used for the keys and then for the payloads
+    __shared__ __attribute__((aligned(16))) char s_stage[kRadixTile * kStage];
+    K *s_key = reinterpret_cast<K *>(s_stage);
+    P *s_pay = reinterpret_cast<P *>(s_stage);
 
     const int R = 1 << bits;
     const uint32_t mask = (uint32_t)(R - 1);
@@ -261,24 +263,32 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kRadixTile;
 
+    // all global loads first, so that they are in flight together;
+    // wave w owns the contiguous run [w*16*64, (w+1)*16*64) of the tile
+    K key[kRadixItems];
+    P pay[kRadixItems];
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        int64_t p = base + ((int64_t)(w * kRadixItems + r) << 6) + lane;
+        bool valid = p < n;
+        key[r] = valid ? kin[p] : K(0);
+        if constexpr (kPay)
+            pay[r] = valid ? pin[p] : P();
+    }
     for (int i = tid; i < R; i += 256) {
         wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0;
         gbase[i] = offs[tile * R + i];
     }
     __syncthreads();
 
-    K key[kRadixItems];
-    P pay[kRadixItems];
-    uint32_t rank[kRadixItems];
+    // stable rank of each key among the equal digits of its wave (ballots on
+    // the digit bits), and the per-wave digit counts
+    uint32_t slot[kRadixItems];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
-        // wave w owns the contiguous run [w*16*64, (w+1)*16*64) of the tile
         int64_t p = base + ((int64_t)(w * kRadixItems + r) << 6) + lane;
         bool valid = p < n;
-        key[r] = valid ? kin[p] : K(0);
-        if constexpr (kPay)
-            pay[r] = valid ? pin[p] : P();
         uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -290,7 +300,7 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
         uint32_t rk = (uint32_t)__popcll(peers & lt);
         if (valid && rk == 0)
             wcnt[w][dg] = before + (uint32_t)__popcll(peers);
-        rank[r] = valid ? before + rk : 0xffffffffu;
+        slot[r] = valid ? before + rk : 0xffffffffu;
     }
     __syncthreads();
 
@@ -325,26 +335,45 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
         loff[2 * tid + 1] = ex + t0;
     __syncthreads();
 
+    // keys to their place in the tile (digit order, stable)
 #pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
-        if (rank[r] != 0xffffffffu) {
+        if (slot[r] != 0xffffffffu) {
             uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
-            uint32_t lp = loff[dg] + wcnt[w][dg] + rank[r];
-            s_key[lp] = key[r];
-            if constexpr (kPay)
-                s_pay[lp] = pay[r];
+            slot[r] += loff[dg] + wcnt[w][dg];
+            s_key[slot[r]] = key[r];
         }
     }
     __syncthreads();
 
-    for (uint32_t q = tid; q < tot; q += 256) {
-        K kk = s_key[q];
-        uint32_t dg = (uint32_t)(kk >> shift) & mask;
-        int64_t dst = (int64_t)gbase[dg] + (q - loff[dg]);
-        kout[dst] = kk;
-        if constexpr (kPay)
-            pout[dst] = s_pay[q];
+    // coalesced runs out; remember each destination for the payloads
+    uint32_t dst[kRadixItems];
+#pragma unroll
+    for (int i = 0; i < kRadixItems; ++i) {
+        uint32_t q = (uint32_t)(tid + 256 * i);
+        dst[i] = 0xffffffffu;
+        if (q < tot) {
+            K kk = s_key[q];
+            uint32_t dg = (uint32_t)(kk >> shift) & mask;
+            dst[i] = gbase[dg] + (q - loff[dg]);
+            kout[dst[i]] = kk;
+        }
     }
+    if constexpr (kPay) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRadixItems; ++r)
+            if (slot[r] != 0xffffffffu)
+                s_pay[slot[r]] = pay[r];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            uint32_t q = (uint32_t)(tid + 256 * i);
+            if (q < tot)
+                pout[dst[i]] = s_pay[q];
+        }
+    }
+    (void)ntiles;
 }
 
 // Workspace needed by radix_sort for n keys.
@@ -374,14 +403,17 @@ inline RadixScratch radix_take(Arena &a, int64_t n) {
 }
 
 // One stable pass from (kin, pin) to (kout, pout).
+// hist_ready: the producer of kin already wrote the per-tile digit counts of
+// this pass into rs.hist (tile-major, 1 << bits entries per tile).
 template <typename K, typename P>
 int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
-               int shift, int bits, const RadixScratch &rs, hipStream_t s) {
+               int shift, int bits, const RadixScratch &rs, hipStream_t s,
+               bool hist_ready = false) {
     if (n <= 0)
         return MECDF_OK;
     int64_t nt = ceil_div(n, kRadixTile);
     int R = 1 << bits;
-    {
+    if (!hist_ready) {
         ProfScope ps("radix_hist", s);
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nt), dim3(256), 0, s,
                            kin, n, shift, bits, rs.hist, nt);
@@ -413,7 +445,7 @@ int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
 template <typename K, typename P>
 int radix_sort_bits(const K *k0, const P *p0, K *k1, P *p1, K *k2, P *p2,
                     int64_t n, int lo, int hi, const RadixScratch &rs,
-                    hipStream_t s, int *which) {
+                    hipStream_t s, int *which, bool first_hist_ready = false) {
     const K *ck = k0;
     const P *cp = p0;
     int cur = 0;
@@ -421,7 +453,8 @@ int radix_sort_bits(const K *k0, const P *p0, K *k1, P *p1, K *k2, P *p2,
         int bits = hi - b < kRadixMaxBits ? hi - b : kRadixMaxBits;
         K *nk = (cur == 1) ? k2 : k1;
         P *np = (cur == 1) ? p2 : p1;
-        MECDF_TRY((radix_pass<K, P>(ck, cp, nk, np, n, b, bits, rs, s)));
+        MECDF_TRY((radix_pass<K, P>(ck, cp, nk, np, n, b, bits, rs, s,
+                                    first_hist_ready && b == lo)));
         cur = (cur == 1) ? 2 : 1;
         ck = nk;
         cp = np;

@@ -132,6 +132,41 @@ def test_empty_input_counts(lib):
     assert int(F.abs().sum()) == 0 and int(Fb.abs().sum()) == 0
 
 
+def test_many_lines_with_long_ones(lib):
+    """Over a thousand lines (one wavefront each), a few of them holding
+    thousands of points (handed to the workgroup kernel): every node checked,
+    for both outputs together and each alone."""
+    g = np.random.default_rng(17)
+    n = 50000
+    x = g.normal(size=(2, n))
+    heavy = g.random(n) < 0.2
+    x[0, heavy] = g.choice([-0.5, 0.1, 0.7], size=int(heavy.sum()))
+    x = np.round(x, 3)
+    nodes = [np.sort(g.choice(np.unique(x[0]), size=1100, replace=False)),
+             np.linspace(-2.5, 2.5, 20)]
+    z = oracle.grid_points(nodes)
+    xt = dev(x)
+    y = g.normal(size=n)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes)
+    np.testing.assert_array_equal(F.cpu().numpy().reshape(-1), oracle.ecdf(x, z))
+    np.testing.assert_array_equal(Fb.cpu().numpy().reshape(-1), oracle.esf(x, z))
+    np.testing.assert_array_equal(lib.ecdf_grid(xt, nodes).cpu().numpy().reshape(-1),
+                                  oracle.ecdf(x, z))
+    np.testing.assert_array_equal(lib.esf_grid(xt, nodes).cpu().numpy().reshape(-1),
+                                  oracle.esf(x, z))
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y))
+    w, a = oracle.ecdf(x, z, y)
+    check_weighted(F.cpu().numpy(), w, a, 1e-12)
+    w, a = oracle.esf(x, z, y)
+    check_weighted(Fb.cpu().numpy(), w, a, 1e-12)
+    y32 = y.astype(np.float32)
+    F, Fb = lib.ecdf_esf_grid(xt, nodes, dev(y32, torch.float32), prec="f32c")
+    w, a = oracle.ecdf(x, z, y32.astype(np.float64))
+    check_weighted(F.cpu().numpy(), w, a, 1e-5)
+    w, a = oracle.esf(x, z, y32.astype(np.float64))
+    check_weighted(Fb.cpu().numpy(), w, a, 1e-5)
+
+
 def test_deterministic(lib):
     g = np.random.default_rng(6)
     x = g.normal(size=(3, 300000))
