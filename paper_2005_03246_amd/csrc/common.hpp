@@ -184,6 +184,13 @@ template <typename T> __device__ __forceinline__ T shfl_down(T v, int d) {
     }
 }
 
+// Orders this wavefront's LDS accesses before and after the call (the
+// compiler may not move them across it).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T> __device__ __forceinline__ T shfl(T v, int src) {
     if constexpr (sizeof(T) == 8) {
         union {

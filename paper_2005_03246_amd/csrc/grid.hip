@@ -251,10 +251,6 @@ template <typename T> __device__ __forceinline__ T finish(T v, int scale, double
     }
 }
 
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
 
 // Row offsets of a line in the ECDF array (cells <= M_k-1 on axes 0..d-2) and
 // in the ESF array (cells >= 1, shifted down by one); doE / doS say whether the

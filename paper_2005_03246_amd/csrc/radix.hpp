@@ -7,8 +7,9 @@
 //                      smaller digit plus the keys of that digit in earlier
 //                      tiles (column sums over chunks of tiles, a scan of the
 //                      chunk sums, then a rescan), written back tile-major
-//   3. k_radix_scatter per-tile stable ranks from wave ballots, staging of the
-//                      tile in LDS in digit order, then coalesced writes
+//   3. k_radix_scatter per-tile stable ranks (lanes of equal digit found
+//                      through per-wave LDS masks), staging of the tile in LDS
+//                      in digit order, then coalesced writes
 // Stability (equal digits keep their input order) makes the result, and
 // everything computed from it, deterministic.
 #pragma once
@@ -137,6 +138,32 @@ static __global__ __launch_bounds__(256) void k_off_final(uint32_t *__restrict__
     }
 }
 
+// ---- block-wide exclusive scan of the values of kW waves -------------------
+template <typename T, int kW>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *wtot /*[kW]*/, T *total) {
+    const int lane = lane_id();
+    const int w = threadIdx.x >> 6;
+    T inc = wave_inclusive_scan(v);
+    if (lane == 63)
+        wtot[w] = inc;
+    __syncthreads();
+    T off = T(0);
+    for (int i = 0; i < w; ++i)
+        off = off + wtot[i];
+    if (total) {
+        T t = T(0);
+        for (int i = 0; i < kW; ++i)
+            t = t + wtot[i];
+        *total = t;
+    }
+    // exclusive value from the left neighbour (no subtraction: exact for
+    // floating-point values too)
+    T ex = shfl_up(inc, 1);
+    T r = lane == 0 ? off : off + ex;
+    __syncthreads();
+    return r;
+}
+
 // ---- block-wide exclusive scan of 256 thread values (4 waves) -------------
 template <typename T>
 __device__ __forceinline__ T block_exclusive_scan256(T v, T *wtot /*[4]*/,
@@ -238,20 +265,28 @@ inline int scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n,
 inline size_t scan_bsum_count(int64_t n) { return (size_t)ceil_div(n, kScanBlock) + 1; }
 
 // ---- scatter ---------------------------------------------------------------
+constexpr int kScatWaves = 8;
+constexpr int kScatThreads = kScatWaves * 64;
+constexpr int kScatItems = kRadixTile / kScatThreads;  // 8 keys per thread
+static_assert(kScatThreads >= kRadixMaxDigits, "one digit per thread");
+
 template <typename K, typename P>
-__global__ __launch_bounds__(256) void k_radix_scatter(
+__global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
     const K *__restrict__ kin, const P *__restrict__ pin, K *__restrict__ kout,
     P *__restrict__ pout, const uint32_t *__restrict__ offs, int64_t n,
     int shift, int bits, int64_t ntiles) {
     constexpr bool kPay = !std::is_same<P, NoPayload>::value;
     constexpr int kPaySize = kPay ? (int)sizeof(P) : 1;
-    constexpr int kStage = (int)sizeof(K) > kPaySize ? (int)sizeof(K) : kPaySize;
-    __shared__ uint32_t wcnt[4][kRadixMaxDigits];
+    constexpr int kStage0 = (int)sizeof(K) > kPaySize ? (int)sizeof(K) : kPaySize;
+    constexpr int kStage = kStage0 > 8 ? kStage0 : 8;
+    __shared__ uint32_t wcnt[kScatWaves][kRadixMaxDigits];
     __shared__ uint32_t loff[kRadixMaxDigits];
     __shared__ uint32_t gbase[kRadixMaxDigits];
-    __shared__ uint32_t wt[4];
-    // one staging buffer, used for the keys and then for the payloads
+    __shared__ uint32_t wt[kScatWaves];
+    // one staging buffer: the per-wave peer masks while ranking, then the
+    // keys, then the payloads
     __shared__ __attribute__((aligned(16))) char s_stage[kRadixTile * kStage];
+    static_assert(kRadixTile * kStage >= kScatWaves * kRadixMaxDigits * 8, "mask space");
     K *s_key = reinterpret_cast<K *>(s_stage);
     P *s_pay = reinterpret_cast<P *>(s_stage);
 
@@ -264,80 +299,75 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     const int64_t base = tile * kRadixTile;
 
     // all global loads first, so that they are in flight together;
-    // wave w owns the contiguous run [w*16*64, (w+1)*16*64) of the tile
-    K key[kRadixItems];
-    P pay[kRadixItems];
+    // wave w owns the contiguous run [w*8*64, (w+1)*8*64) of the tile
+    K key[kScatItems];
+    P pay[kScatItems];
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
-        int64_t p = base + ((int64_t)(w * kRadixItems + r) << 6) + lane;
+    for (int r = 0; r < kScatItems; ++r) {
+        int64_t p = base + ((int64_t)(w * kScatItems + r) << 6) + lane;
         bool valid = p < n;
         key[r] = valid ? kin[p] : K(0);
         if constexpr (kPay)
             pay[r] = valid ? pin[p] : P();
     }
-    for (int i = tid; i < R; i += 256) {
-        wcnt[0][i] = wcnt[1][i] = wcnt[2][i] = wcnt[3][i] = 0;
-        gbase[i] = offs[tile * R + i];
+    if (tid < R) {
+#pragma unroll
+        for (int q = 0; q < kScatWaves; ++q)
+            wcnt[q][tid] = 0;
+        gbase[tid] = offs[tile * R + tid];
     }
     __syncthreads();
 
-    // stable rank of each key among the equal digits of its wave (ballots on
-    // the digit bits), and the per-wave digit counts
-    uint32_t slot[kRadixItems];
+    // stable rank of each key among the equal digits of its wave, and the
+    // per-wave digit counts.  The lanes holding the same digit are found
+    // through a per-wave LDS word per digit: cleared by its lanes, then each
+    // lane ORs in its own bit, which gives the same mask whatever the order of
+    // the ORs.
+    uint64_t *wmask = reinterpret_cast<uint64_t *>(s_stage) + (size_t)w * kRadixMaxDigits;
+    uint32_t slot[kScatItems];
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
-        int64_t p = base + ((int64_t)(w * kRadixItems + r) << 6) + lane;
+    for (int r = 0; r < kScatItems; ++r) {
+        int64_t p = base + ((int64_t)(w * kScatItems + r) << 6) + lane;
         bool valid = p < n;
         uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
-            bool bit = (dg >> b) & 1u;
-            uint64_t bal = __ballot(valid && bit);
-            peers &= bit ? bal : ~bal;
-        }
+        if (valid)
+            wmask[dg] = 0ull;
+        wave_lds_fence();
+        if (valid)
+            atomicOr(reinterpret_cast<unsigned long long *>(wmask + dg), 1ull << lane);
+        wave_lds_fence();
+        const uint64_t peers = valid ? wmask[dg] : 0ull;
         uint32_t before = valid ? wcnt[w][dg] : 0u;
         uint32_t rk = (uint32_t)__popcll(peers & lt);
+        wave_lds_fence();
         if (valid && rk == 0)
             wcnt[w][dg] = before + (uint32_t)__popcll(peers);
+        wave_lds_fence();
         slot[r] = valid ? before + rk : 0xffffffffu;
     }
     __syncthreads();
 
-    // per-digit offsets of each wave inside the tile, then digit offsets
-    uint32_t t0 = 0, t1 = 0;
-    {
-        int d0 = 2 * tid, d1 = 2 * tid + 1;
-        if (d0 < R) {
-            uint32_t s = 0;
-            for (int q = 0; q < 4; ++q) {
-                uint32_t t = wcnt[q][d0];
-                wcnt[q][d0] = s;
-                s += t;
-            }
-            t0 = s;
-        }
-        if (d1 < R) {
-            uint32_t s = 0;
-            for (int q = 0; q < 4; ++q) {
-                uint32_t t = wcnt[q][d1];
-                wcnt[q][d1] = s;
-                s += t;
-            }
-            t1 = s;
+    // per digit (one per thread): offsets of each wave inside the digit's
+    // run, then the digits' offsets inside the tile
+    uint32_t td = 0;
+    if (tid < R) {
+#pragma unroll
+        for (int q = 0; q < kScatWaves; ++q) {
+            uint32_t t = wcnt[q][tid];
+            wcnt[q][tid] = td;
+            td += t;
         }
     }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan256<uint32_t>(t0 + t1, wt, &tot);
-    if (2 * tid < R)
-        loff[2 * tid] = ex;
-    if (2 * tid + 1 < R)
-        loff[2 * tid + 1] = ex + t0;
+    uint32_t ex = block_exclusive_scan<uint32_t, kScatWaves>(td, wt, &tot);
+    if (tid < R)
+        loff[tid] = ex;
     __syncthreads();
 
     // keys to their place in the tile (digit order, stable)
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < kScatItems; ++r) {
         if (slot[r] != 0xffffffffu) {
             uint32_t dg = (uint32_t)(key[r] >> shift) & mask;
             slot[r] += loff[dg] + wcnt[w][dg];
@@ -347,10 +377,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     __syncthreads();
 
     // coalesced runs out; remember each destination for the payloads
-    uint32_t dst[kRadixItems];
+    uint32_t dst[kScatItems];
 #pragma unroll
-    for (int i = 0; i < kRadixItems; ++i) {
-        uint32_t q = (uint32_t)(tid + 256 * i);
+    for (int i = 0; i < kScatItems; ++i) {
+        uint32_t q = (uint32_t)(tid + kScatThreads * i);
         dst[i] = 0xffffffffu;
         if (q < tot) {
             K kk = s_key[q];
@@ -362,13 +392,13 @@ __global__ __launch_bounds__(256) void k_radix_scatter(
     if constexpr (kPay) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kRadixItems; ++r)
+        for (int r = 0; r < kScatItems; ++r)
             if (slot[r] != 0xffffffffu)
                 s_pay[slot[r]] = pay[r];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kRadixItems; ++i) {
-            uint32_t q = (uint32_t)(tid + 256 * i);
+        for (int i = 0; i < kScatItems; ++i) {
+            uint32_t q = (uint32_t)(tid + kScatThreads * i);
             if (q < tot)
                 pout[dst[i]] = s_pay[q];
         }
@@ -431,7 +461,7 @@ int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
     }
     {
         ProfScope ps("radix_scatter", s);
-        hipLaunchKernelGGL((k_radix_scatter<K, P>), dim3((unsigned)nt), dim3(256), 0,
+        hipLaunchKernelGGL((k_radix_scatter<K, P>), dim3((unsigned)nt), dim3(kScatThreads), 0,
                            s, kin, pin, kout, pout, rs.hist, n, shift, bits, nt);
     }
     MECDF_LAUNCH_CHECK();
