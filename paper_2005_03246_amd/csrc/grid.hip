@@ -55,6 +55,11 @@ struct GridInfo {
     int packed;
     int sh[MECDF_MAX_DIM];
     int nb[MECDF_MAX_DIM];
+    // per axis: first and last node, and (M_k - 1) / (last - first), the
+    // factor of the mesh-division guess
+    double z0[MECDF_MAX_DIM];
+    double zl[MECDF_MAX_DIM];
+    double gs[MECDF_MAX_DIM];
 };
 
 // mixed-radix line index of a key (L for a dropped point)
@@ -74,17 +79,15 @@ __device__ __forceinline__ uint32_t key_line(uint32_t key, const GridInfo &g) {
 // cell c meaning z_{c-1} < v <= z_c (z_{-1} = -inf, z_M = +inf).  NaN maps
 // to 0 and is filtered by the caller.
 template <typename NodePtr>
-__device__ __forceinline__ uint32_t cell_index(NodePtr z, int M, double v) {
-    double z0 = z[0];
-    double zl = z[M - 1];
+__device__ __forceinline__ uint32_t cell_index(NodePtr z, int M, double z0, double zl,
+                                               double gs, double v) {
     if (!(v > z0))
         return 0u;
     if (v > zl)
         return (uint32_t)M;
     // z0 < v <= zl: the answer is in [1, M-1].  Guess by mesh division (the
     // uniform-grid index of Appendix A.2) and check it exactly.
-    int c = (int)ceil((v - z0) / (zl - z0) * (double)(M - 1));
-    c = c < 1 ? 1 : (c > M - 1 ? M - 1 : c);
+    const int c = (int)fmin(fmax(ceil((v - z0) * gs), 1.0), (double)(M - 1));
     if (z[c - 1] < v && v <= z[c])
         return (uint32_t)c;
     int lo = 1, hi = M - 1;
@@ -98,7 +101,6 @@ __device__ __forceinline__ uint32_t cell_index(NodePtr z, int M, double v) {
     return (uint32_t)lo;
 }
 
-constexpr int kKeyPts = 4;  // points per thread per load group
 
 // One radix tile (kRadixTile consecutive points) per block.  With hist != null
 // the block also writes the tile's counts of the key digit [hshift, hshift +
@@ -134,6 +136,7 @@ __global__ __launch_bounds__(256) void k_cellkey(const double *__restrict__ x,
     }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    constexpr int kKeyPts = D <= 3 ? 8 : 4;  // points per thread per load group
     for (int grp = 0; grp < kRadixItems / kKeyPts; ++grp) {
         const int64_t b = base + (int64_t)grp * kKeyPts * 256 + threadIdx.x;
         double v[kKeyPts][D];
@@ -157,9 +160,9 @@ __global__ __launch_bounds__(256) void k_cellkey(const double *__restrict__ x,
                 bad |= (vv != vv);
                 uint32_t c;
                 if constexpr (kLds)
-                    c = cell_index(s_nodes + g.off[k], g.M[k], vv);
+                    c = cell_index(s_nodes + g.off[k], g.M[k], g.z0[k], g.zl[k], g.gs[k], vv);
                 else
-                    c = cell_index(nodes_g + g.off[k], g.M[k], vv);
+                    c = cell_index(nodes_g + g.off[k], g.M[k], g.z0[k], g.zl[k], g.gs[k], vv);
                 if (k < D - 1) {
                     line = line * g.C[k] + c;
                     packed |= c << g.sh[k];
@@ -393,10 +396,9 @@ template <int kW> inline size_t line_lds_bytes(int Cl) { return (size_t)2 * kW *
 // bins; the bin sets are then combined in wave order, so every sum is taken
 // in an order fixed by the input order alone.
 template <typename T, typename P, int kW>
-__device__ void line_block(int64_t line, const uint32_t *__restrict__ keys,
-                           const P *__restrict__ pay, const uint32_t *__restrict__ lbnd,
-                           const GridInfo &g, T *__restrict__ F, T *__restrict__ Fbar,
-                           int scale, double N, char *s_raw) {
+__device__ void line_block(int64_t line, uint2 range, const uint32_t *__restrict__ keys,
+                           const P *__restrict__ pay, const GridInfo &g, T *__restrict__ F,
+                           T *__restrict__ Fbar, int scale, double N, char *s_raw) {
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
@@ -418,7 +420,7 @@ __device__ void line_block(int64_t line, const uint32_t *__restrict__ keys,
         mybins[c].zero();
     wave_lds_fence();
 
-    uint32_t s0 = lbnd[2 * line], e0 = lbnd[2 * line + 1];
+    uint32_t s0 = range.x, e0 = range.y;
     if (s0 == kNoLine)
         s0 = e0 = 0u;
     bin_chunks<T, P, kLineBatch>(mybins, mymask, keys, pay, s0 + (uint32_t)w * 64u, e0,
@@ -458,14 +460,26 @@ __global__ __launch_bounds__(kW * 64) void k_line(const uint32_t *__restrict__ k
                                                   T *__restrict__ Fbar, int scale,
                                                   double N) {
     extern __shared__ __attribute__((aligned(16))) char s_raw[];
+    const uint2 *rng = reinterpret_cast<const uint2 *>(lbnd);
     if (!list) {
-        line_block<T, P, kW>(blockIdx.x, keys, pay, lbnd, g, F, Fbar, scale, N, s_raw);
+        line_block<T, P, kW>(blockIdx.x, rng[blockIdx.x], keys, pay, g, F, Fbar, scale, N,
+                             s_raw);
         return;
     }
+    // the next line and its range are loaded one line ahead
     const uint32_t n = *count;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    uint32_t i = blockIdx.x;
+    uint32_t nl = i < n ? list[i] : 0u;
+    uint2 nr = i < n ? rng[nl] : make_uint2(0u, 0u);
+    for (; i < n; i += gridDim.x) {
+        const uint32_t cl = nl;
+        const uint2 cr = nr;
+        if (i + gridDim.x < n) {
+            nl = list[i + gridDim.x];
+            nr = rng[nl];
+        }
         __syncthreads();  // the previous line's LDS reads are done
-        line_block<T, P, kW>(list[i], keys, pay, lbnd, g, F, Fbar, scale, N, s_raw);
+        line_block<T, P, kW>(cl, cr, keys, pay, g, F, Fbar, scale, N, s_raw);
     }
 }
 
@@ -502,14 +516,20 @@ __global__ __launch_bounds__(256) void k_line_wave(const uint32_t *__restrict__ 
     const uint64_t lt = lanemask_lt();
     const int64_t nwaves = (int64_t)gridDim.x * kLineWaves;
 
-    for (int64_t line = (int64_t)blockIdx.x * kLineWaves + w; line < (int64_t)g.L;
-         line += nwaves) {
+    // the next line's range is loaded one line ahead
+    int64_t line = (int64_t)blockIdx.x * kLineWaves + w;
+    uint2 nb = line < (int64_t)g.L ? reinterpret_cast<const uint2 *>(lbnd)[line]
+                                   : make_uint2(0u, 0u);
+    for (; line < (int64_t)g.L; line += nwaves) {
+        const uint2 cb = nb;
+        if (line + nwaves < (int64_t)g.L)
+            nb = reinterpret_cast<const uint2 *>(lbnd)[line + nwaves];
         int64_t rowE, rowS;
         bool doE = F != nullptr, doS = Fbar != nullptr;
         line_rows(line, g, rowE, rowS, doE, doS);
         if (!doE && !doS)
             continue;  // uniform over the wave
-        uint32_t s0 = lbnd[2 * line], e0 = lbnd[2 * line + 1];
+        uint32_t s0 = cb.x, e0 = cb.y;
         if (s0 == kNoLine)
             s0 = e0 = 0u;
         if (e0 - s0 > kHeavyLine) {
@@ -640,6 +660,9 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
         g.M[k] = (int)M[k];
         g.off[k] = total_nodes;
         g.C[k] = (uint32_t)(M[k] + 1);
+        g.z0[k] = z[total_nodes];
+        g.zl[k] = z[total_nodes + M[k] - 1];
+        g.gs[k] = g.zl[k] > g.z0[k] ? (double)(M[k] - 1) / (g.zl[k] - g.z0[k]) : 0.0;
         total_nodes += (int)M[k];
     }
     uint64_t L = 1;
