@@ -27,6 +27,38 @@ HBM_PEAK_GBS = 8000.0
 M_NODES = 256
 LOG2N = 24
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes of this
+# bench (float64, N = 2^24, 256^3 nodes), scaled by the same counters of a
+# 1 GiB device-to-device copy (read factor 2.0, write factor 1.0).  Valid only
+# for the kernel source they were taken on, identified by its SHA-256.
+TRAFFIC = {
+    "radix_scatter": {
+        "source": "paper_2005_03246_amd/csrc/radix.hpp",
+        "sha256": "89bb683aac5023b9bba017b58e8116dda48f5847643db643706c79b5d3d9a0b8",
+        "prec": "f64",
+        "fetch_kib": 102447.1, "fetch_factor": 2.0,
+        "write_kib": 225703.3, "write_factor": 1.0,
+    },
+}
+
+
+def measured_traffic(kernel: str, prec: str):
+    """HBM bytes per launch of kernel from the counter runs, or None when they
+    do not apply (other kernel, precision or kernel source)."""
+    import hashlib
+
+    t = TRAFFIC.get(kernel)
+    if t is None or t["prec"] != prec:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    try:
+        with open(path, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+                return None
+    except OSError:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 # Algorithmic (compulsory) bytes per launch of each grid kernel, per point
 # (N) or per output node (G = 256^3) and per output array, float64 weights.
 #   grid_cellkey     reads x (24 B/pt), writes the packed cell key (4 B/pt)
@@ -64,7 +96,26 @@ def parse():
                     help="skip the learned-bandwidth judge")
     ap.add_argument("--bw-train", type=int, default=512,
                     help="training datasets of the bandwidth network")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three device-to-device copies of 1 GiB (the "
+                         "reference kernel that scales the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Three copies of 1 GiB between two device buffers: under rocprofv3
+    --pmc, FETCH_SIZE and WRITE_SIZE of this copy give the factors that turn
+    the counters into bytes."""
+    import torch
+
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": a.numel() * 8, "copies": 3}), flush=True)
 
 
 def _time_calls(fn, steps, warmup):
@@ -212,6 +263,9 @@ def cpu_baseline(x, y, nodes, target_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "
               "(the multi-GPU layout is described, not built)" % args.gpus,
@@ -281,7 +335,7 @@ def main():
     avg_ms = dms / dlaunch
     ab = algorithmic_bytes(dname, n, G, ysize, dlaunch // args.steps)
     roof = {"bound": "hbm", "kernel": dname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "achieved": None, "frac": None, "traffic": None,
+            "achieved": None, "frac": None, "traffic": measured_traffic(dname, args.prec),
             "avg_launch_ms": avg_ms}
     if ab is not None:
         gbs = ab / (avg_ms * 1e-3) / 1e9
