@@ -302,6 +302,26 @@ __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int
     }
 }
 
+// Side-indexed access to small per-thread arrays with the side as a select
+// over all sides, so that the arrays stay in registers (a runtime index
+// would place them in scratch memory).
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ void add_side(T (&l)[NSD][CH], int sd, const T (&v)[CH]) {
+#pragma unroll
+    for (int s = 0; s < NSD; ++s)
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            l[s][c] += (s == sd) ? v[c] : T(0);
+}
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ T get_side(const T (&l)[NSD][CH], int sd, int c) {
+    T r = l[0][c];
+#pragma unroll
+    for (int s = 1; s < NSD; ++s)
+        r = (s == sd) ? l[s][c] : r;
+    return r;
+}
+
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void thread_affs(const T alpha[kKItems][kKB],
                                             const T beta[kKItems][kKB],
@@ -322,9 +342,11 @@ __device__ __forceinline__ void thread_affs(const T alpha[kKItems][kKB],
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
                     fw.l[b][s][c] *= alpha[u][b];
+            T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                fw.l[b][sd[u]][c] += f[u][b] * wv[u][c];
+                add[c] = f[u][b] * wv[u][c];
+            add_side<T, CH, NSD>(fw.l[b], sd[u], add);
         }
     }
 #pragma unroll
@@ -339,9 +361,11 @@ __device__ __forceinline__ void thread_affs(const T alpha[kKItems][kKB],
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
                     bw.l[b][s][c] *= beta[u][b];
+            T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                bw.l[b][sd[u]][c] += f[u][b] * wv[u][c];
+                add[c] = f[u][b] * wv[u][c];
+            add_side<T, CH, NSD>(bw.l[b], sd[u], add);
         }
     }
 }
@@ -528,11 +552,13 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
                     st[s][c] *= alpha[u][b];
+            T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                recv[u][b][c] = st[o][c];
-                st[sd[u]][c] += f[u][b] * wv[u][c];
+                recv[u][b][c] = get_side<T, CH, NSD>(st, o, c);
+                add[c] = f[u][b] * wv[u][c];
             }
+            add_side<T, CH, NSD>(st, sd[u], add);
         }
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
@@ -549,11 +575,13 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
                     st[s][c] *= beta[u][b];
+            T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                recv[u][b][c] = f[u][b] * (recv[u][b][c] + st[o][c]);
-                st[sd[u]][c] += f[u][b] * wv[u][c];
+                recv[u][b][c] = f[u][b] * (recv[u][b][c] + get_side<T, CH, NSD>(st, o, c));
+                add[c] = f[u][b] * wv[u][c];
             }
+            add_side<T, CH, NSD>(st, sd[u], add);
         }
     }
 #pragma unroll
