@@ -203,8 +203,10 @@ int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
  * feat[s*32 + q]), computed on the device in one block per dataset:
  * log N / 10, d / 3, per-axis log sd, skewness, excess kurtosis / 10,
  * mean |correlation|, log h0 with h0 = (geometric-mean sd) N^(-1/(d+4))
- * (index 12), log geometric-mean sd, per-axis mean |x - mean| / sd and the
- * fraction of points within half a sd of the mean; unused entries are 0.
+ * (index 12), log geometric-mean sd, per-axis mean |x - mean| / sd, the
+ * fraction of points within half a sd of the mean (indices 17..19) and the
+ * fractions within a quarter, one and two sd (20 + 3k .. 22 + 3k for axis k);
+ * unused entries are 0.
  */
 int mecdf_bw_features(const mecdf_dataset *sets, int nsets, float *feat,
                       void *stream);
@@ -220,10 +222,11 @@ int mecdf_bw_features(const mecdf_dataset *sets, int nsets, float *feat,
  *                    (1/B) sum_r (out[r] - target[r])^2 into grad[MECDF_MLP_PARAMS]
  *                    and the loss into loss[0] (loss may be NULL).
  * mecdf_mlp_train:   `steps` full-batch Adam steps (beta1 0.9, beta2 0.999,
- *                    eps 1e-8, learning rate lr) updating params in place;
- *                    adam is device float[2*MECDF_MLP_PARAMS], zero before the
- *                    first step; losses[t] (device, optional) is the loss
- *                    before step t.
+ *                    eps 1e-8, learning rate lr) with decoupled weight decay
+ *                    (each step also subtracts lr * wd * params; wd >= 0)
+ *                    updating params in place; adam is device
+ *                    float[2*MECDF_MLP_PARAMS], zero before the first step;
+ *                    losses[t] (device, optional) is the loss before step t.
  * All pointers are device pointers; B >= 1.
  */
 #define MECDF_MLP_PARAMS 20865
@@ -232,22 +235,30 @@ int mecdf_mlp_forward(int B, const float *feat, const float *params, float *out,
 int mecdf_mlp_grad(int B, const float *feat, const float *target,
                    const float *params, float *grad, float *loss, void *stream);
 int mecdf_mlp_train(int B, const float *feat, const float *target, float *params,
-                    float *adam, int steps, float lr, float *losses, void *stream);
+                    float *adam, int steps, float lr, float wd, float *losses,
+                    void *stream);
 
 /*
  * mecdf_bw_select -- likelihood-CV bandwidth on an ascending grid of nhg
  * isotropic bandwidths (hgrid, host).  The network proposes
  * log h = feat[12] + net(feat); the exact LOO likelihood score is evaluated
- * at the four grid bandwidths around the proposal, and the evaluated window
- * is extended by four grid points at a time towards the best score until the
- * best score is interior to it (or at the grid's end).  Returns, per dataset
- * (host arrays), the chosen grid index, its LCV score (lcv_out may be NULL)
- * and the number of bandwidths evaluated (evals_out may be NULL).  Every
- * returned score is an exact evaluation.  Synchronous: waits for the device.
+ * at the four grid bandwidths around the proposal (grid indices
+ * round(j) - 1 .. round(j) + 2 for the proposal's fractional index j,
+ * clamped to the grid).  With mode MECDF_BW_EXTEND the evaluated window is
+ * then extended by four grid points at a time towards the best score until
+ * the best score is interior to it (or at the grid's end); with
+ * MECDF_BW_WINDOW the four-point window is the answer.  Each dataset's
+ * structure over its sample is built once for all its windows.  Returns, per
+ * dataset (host arrays), the chosen grid index, its LCV score (lcv_out may be
+ * NULL) and the number of bandwidths evaluated (evals_out may be NULL).
+ * Every returned score is an exact evaluation.  Synchronous: waits for the
+ * device after each window.
  */
+#define MECDF_BW_EXTEND 0
+#define MECDF_BW_WINDOW 1
 int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params,
-                    int nhg, const double *hgrid, int *hidx_out, double *lcv_out,
-                    int *evals_out, void *stream);
+                    int nhg, const double *hgrid, int mode, int *hidx_out,
+                    double *lcv_out, int *evals_out, void *stream);
 
 /* Frees the workspace of every device (synchronises those devices). */
 void mecdf_release(void);

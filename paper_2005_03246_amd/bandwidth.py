@@ -43,21 +43,22 @@ def targets(feat, hidx, hgrid):
                         device=feat.device) - feat[:, 12]
 
 
-def train(dsets, hgrid, steps: int = 3000, lr: float = 2e-3, seed: int = 0, hidx=None):
-    """Labels from the exact grid search, then full-batch Adam on the device.
-    Returns (params, losses, labels)."""
+def train(dsets, hgrid, steps: int = 2000, lr: float = 1e-3, wd: float = 1.0, seed: int = 0,
+          hidx=None):
+    """Labels from the exact grid search, then full-batch Adam with decoupled
+    weight decay on the device.  Returns (params, losses, labels)."""
     feat = mecdf.bw_features(dsets)
     if hidx is None:
         hidx, _ = grid_search(dsets, hgrid)
     t = targets(feat, hidx, hgrid)
     params = init_params(seed)
     adam = torch.zeros((2 * mecdf.MLP_PARAMS,), dtype=torch.float32, device="cuda")
-    losses = mecdf.mlp_train(feat, t, params, adam, steps, lr)
+    losses = mecdf.mlp_train(feat, t, params, adam, steps, lr, wd)
     return params, losses.cpu().numpy(), hidx
 
 
-def select(dsets, params, hgrid):
-    return mecdf.bw_select(dsets, params, hgrid)
+def select(dsets, params, hgrid, mode=mecdf.BW_EXTEND):
+    return mecdf.bw_select(dsets, params, hgrid, mode)
 
 
 def hgrid64():

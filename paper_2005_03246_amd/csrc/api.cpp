@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -16,12 +17,15 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh,
             const double *h, void *f, double *score, int regression,
             int prec, hipStream_t s);
+using BatchSource = std::function<int(int &b0, int &nb, bool &more)>;
+int kde_lcv_select(int d, int64_t N, const double *x, int nh, const double *h, double *score,
+                   const BatchSource &source, hipStream_t s);
 int bw_features(const mecdf_dataset *sets, int nsets, float *feat, hipStream_t s);
 int mlp_forward(int B, const float *X, const float *P, float *out, hipStream_t s);
 int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, float *loss,
              hipStream_t s);
 int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps,
-              float lr, float *losses, hipStream_t s);
+              float lr, float wd, float *losses, hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -249,17 +253,20 @@ int mecdf_mlp_grad(int B, const float *feat, const float *target, const float *p
 }
 
 int mecdf_mlp_train(int B, const float *feat, const float *target, float *params,
-                    float *adam, int steps, float lr, float *losses, void *stream) {
-    if (B < 1 || !feat || !target || !params || !adam || steps < 0 || !(lr > 0.f))
+                    float *adam, int steps, float lr, float wd, float *losses, void *stream) {
+    if (B < 1 || !feat || !target || !params || !adam || steps < 0 || !(lr > 0.f) ||
+        !(wd >= 0.f))
         return fail(MECDF_EINVAL, "mlp_train: bad arguments");
-    return mlp_train(B, feat, target, params, adam, steps, lr, losses, (hipStream_t)stream);
+    return mlp_train(B, feat, target, params, adam, steps, lr, wd, losses,
+                     (hipStream_t)stream);
 }
 
 int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, int nhg,
-                    const double *hgrid, int *hidx_out, double *lcv_out, int *evals_out,
-                    void *stream) {
+                    const double *hgrid, int mode, int *hidx_out, double *lcv_out,
+                    int *evals_out, void *stream) {
     MECDF_TRY(check_sets(sets, nsets));
-    if (!params || !hgrid || !hidx_out || nhg < 1 || nhg > 4096)
+    if (!params || !hgrid || !hidx_out || nhg < 1 || nhg > 4096 ||
+        (mode != MECDF_BW_EXTEND && mode != MECDF_BW_WINDOW))
         return fail(MECDF_EINVAL, "bw_select: bad arguments");
     for (int j = 0; j < nhg; ++j)
         if (!(hgrid[j] > 0.0) || (j > 0 && !(hgrid[j] > hgrid[j - 1])))
@@ -268,14 +275,14 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
     // device buffers of this call (outside the shared workspace, which the
     // kernel sums below reuse)
     float *feat = nullptr, *pred = nullptr;
-    double *lcvd = nullptr;
+    double *scd = nullptr;
     MECDF_TRY_HIP(hipMalloc(&feat, sizeof(float) * 32 * nsets));
     hipError_t e1 = hipMalloc(&pred, sizeof(float) * nsets);
-    hipError_t e2 = hipMalloc(&lcvd, sizeof(double) * 4 * nsets);
+    hipError_t e2 = hipMalloc(&scd, sizeof(double) * nhg);
     auto cleanup = [&]() {
         (void)hipFree(feat);
         (void)hipFree(pred);
-        (void)hipFree(lcvd);
+        (void)hipFree(scd);
     };
     if (e1 != hipSuccess || e2 != hipSuccess) {
         cleanup();
@@ -296,90 +303,79 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
         cleanup();
         return rc;
     }
-    // evaluated window [lo, hi] per dataset and its scores
-    std::vector<int> lo(nsets), hi(nsets), best(nsets), evals(nsets, 0), done(nsets, 0);
-    std::vector<std::vector<double>> sc(nsets, std::vector<double>(nhg, -INFINITY));
     const double l0 = std::log(hgrid[0]);
     const double dl = nhg > 1 ? (std::log(hgrid[nhg - 1]) - l0) / (nhg - 1) : 1.0;
-    std::vector<int> nh(nsets);
-    std::vector<double> hv;
-    std::vector<int> want_lo(nsets), want_hi(nsets);
-    for (int i = 0; i < nsets; ++i) {
+    const int w = nhg < 4 ? nhg : 4;
+    // the grid repeated on every axis, for d = 1, 2, 3
+    std::vector<double> hh[3];
+    for (int d = 1; d <= 3; ++d) {
+        hh[d - 1].resize((size_t)nhg * d);
+        for (int j = 0; j < nhg; ++j)
+            for (int k = 0; k < d; ++k)
+                hh[d - 1][(size_t)j * d + k] = hgrid[j];
+    }
+    std::vector<double> sc(nhg);
+    for (int i = 0; i < nsets && rc == MECDF_OK; ++i) {
         double lh = (double)hf[(size_t)i * 32 + 12] + (double)hp[i];
         double jf = std::isfinite(lh) ? (lh - l0) / dl : 0.0;
+        jf = jf < -1e6 ? -1e6 : (jf > 1e6 ? 1e6 : jf);
         int j0 = (int)std::lround(jf) - 1;
-        int w = nhg < 4 ? nhg : 4;
         if (j0 > nhg - w)
             j0 = nhg - w;
         if (j0 < 0)
             j0 = 0;
-        want_lo[i] = j0;
-        want_hi[i] = j0 + w - 1;
-        lo[i] = j0;
-        hi[i] = j0 - 1;  // nothing evaluated yet
-    }
-    for (int round = 0; round < nhg && rc == MECDF_OK; ++round) {
-        hv.clear();
-        bool any = false;
-        for (int i = 0; i < nsets; ++i) {
-            nh[i] = 0;
-            if (done[i])
-                continue;
-            for (int j = want_lo[i]; j <= want_hi[i]; ++j) {
-                hv.push_back(hgrid[j]);
-                ++nh[i];
+        // evaluated range [lo, hi], best index, the batch in flight
+        int lo = j0, hi = j0 + w - 1, best = j0, evals = 0;
+        int cur0 = -1, curn = 0;
+        BatchSource source = [&](int &b0, int &nb, bool &more) -> int {
+            if (cur0 < 0) {
+                cur0 = b0 = j0;
+                curn = nb = w;
+                more = true;
+                return MECDF_OK;
             }
-            any = any || nh[i] > 0;
-        }
-        if (!any)
-            break;
-        rc = mecdf_kde_lcv_batched(sets, nsets, nh.data(), hv.data(), lcvd, MECDF_F64, stream);
-        std::vector<double> got(hv.size());
-        if (rc == MECDF_OK &&
-            (hipMemcpyAsync(got.data(), lcvd, sizeof(double) * hv.size(), hipMemcpyDeviceToHost,
-                            s) != hipSuccess ||
-             hipStreamSynchronize(s) != hipSuccess))
-            rc = fail(MECDF_EDEVICE, "bw_select: copy failed");
+            // scores of the batch just enqueued
+            if (hipMemcpyAsync(sc.data() + cur0, scd + cur0, sizeof(double) * curn,
+                               hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(MECDF_EDEVICE, "bw_select: copy failed");
+            evals += curn;
+            lo = cur0 < lo ? cur0 : lo;
+            hi = cur0 + curn - 1 > hi ? cur0 + curn - 1 : hi;
+            best = lo;
+            for (int j = lo; j <= hi; ++j)
+                if (sc[j] > sc[best])
+                    best = j;
+            more = false;
+            if (mode == MECDF_BW_EXTEND) {
+                if (best == lo && lo > 0) {
+                    b0 = lo - 4 > 0 ? lo - 4 : 0;
+                    nb = lo - b0;
+                    more = true;
+                } else if (best == hi && hi < nhg - 1) {
+                    b0 = hi + 1;
+                    nb = hi + 4 < nhg - 1 ? 4 : nhg - 1 - hi;
+                    more = true;
+                }
+            }
+            if (more) {
+                cur0 = b0;
+                curn = nb;
+            }
+            return MECDF_OK;
+        };
+        rc = kde_lcv_select(sets[i].d, sets[i].N, sets[i].x, nhg, hh[sets[i].d - 1].data(),
+                            scd, source, s);
         if (rc != MECDF_OK)
             break;
-        size_t off = 0;
-        for (int i = 0; i < nsets; ++i) {
-            if (done[i] || nh[i] == 0)
-                continue;
-            for (int j = want_lo[i]; j <= want_hi[i]; ++j)
-                sc[i][j] = got[off++];
-            evals[i] += nh[i];
-            lo[i] = want_lo[i] < lo[i] ? want_lo[i] : lo[i];
-            hi[i] = want_hi[i] > hi[i] ? want_hi[i] : hi[i];
-            int b = lo[i];
-            for (int j = lo[i]; j <= hi[i]; ++j)
-                if (sc[i][j] > sc[i][b])
-                    b = j;
-            best[i] = b;
-            if (b == lo[i] && lo[i] > 0) {
-                want_hi[i] = lo[i] - 1;
-                want_lo[i] = lo[i] - 4 > 0 ? lo[i] - 4 : 0;
-            } else if (b == hi[i] && hi[i] < nhg - 1) {
-                want_lo[i] = hi[i] + 1;
-                want_hi[i] = hi[i] + 4 < nhg - 1 ? hi[i] + 4 : nhg - 1;
-            } else {
-                done[i] = 1;
-            }
-        }
-        // need room for the next round's scores
-        (void)off;
+        hidx_out[i] = best;
+        if (lcv_out)
+            lcv_out[i] = sc[best];
+        if (evals_out)
+            evals_out[i] = evals;
     }
     cleanup();
-    if (rc != MECDF_OK)
-        return rc;
-    for (int i = 0; i < nsets; ++i) {
-        hidx_out[i] = best[i];
-        if (lcv_out)
-            lcv_out[i] = sc[i][best[i]];
-        if (evals_out)
-            evals_out[i] = evals[i];
-    }
-    return MECDF_OK;
+    return rc;
 }
 
 void mecdf_release(void) { mecdf::workspace_release_all(); }

@@ -38,6 +38,7 @@
 // d = 1 is the same scan over the sorted sample (the two-sided recursion of
 // the 1-D decomposition).  The sums exclude the point itself (leave-one-out);
 // the full estimate adds w_j K(0).
+#include <functional>
 #include <vector>
 
 #include "common.hpp"
@@ -791,10 +792,16 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
     return MECDF_OK;
 }
 
+// Chooses the next batch of bandwidths: with more = true, [b0, b0 + nb)
+// (nb <= kKB) indexes the bandwidth list; more = false ends the call.  It is
+// called before the first batch and after each batch has been enqueued, and
+// returns an error code.
+using BatchSource = std::function<int(int &b0, int &nb, bool &more)>;
+
 template <typename T, int CH, typename WT, typename OutT>
 static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT *w1in,
                      int nh, const double *h, OutT *out, double *score, int mode,
-                     hipStream_t s) {
+                     hipStream_t s, const BatchSource *source = nullptr) {
     // outer merge levels (x1 split): blocks of hs[q] merged into 2 hs[q]
     std::vector<int64_t> hs;
     if (d >= 2)
@@ -896,9 +903,26 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         MECDF_LAUNCH_CHECK();
     }
 
-    for (int b0 = 0; b0 < nh; b0 += kKB) {
+    int b0 = 0, bcount = 0;
+    for (;;) {
+        if (source) {
+            bool more = false;
+            MECDF_TRY((*source)(b0, bcount, more));
+            if (!more)
+                break;
+            if (b0 < 0 || bcount < 1 || bcount > kKB || b0 + bcount > nh) {
+                set_error("bandwidth batch out of range");
+                return MECDF_EINVAL;
+            }
+        } else {
+            if (bcount > 0)
+                b0 += kKB;
+            if (b0 >= nh)
+                break;
+            bcount = nh - b0 < kKB ? nh - b0 : kKB;
+        }
         KBatch kb{};
-        kb.nb = nh - b0 < kKB ? nh - b0 : kKB;
+        kb.nb = bcount;
         for (int b = 0; b < kKB; ++b) {
             int bb = b0 + (b < kb.nb ? b : 0);
             double prod = 1.0;
@@ -970,6 +994,19 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         MECDF_LAUNCH_CHECK();
     }
     return MECDF_OK;
+}
+
+// Leave-one-out log-likelihood scores of one unweighted sample for the
+// bandwidths h[b0 .. b0+nb) of a list of nh (d entries each), batches chosen
+// by source; the structure over the sample is built once.
+int kde_lcv_select(int d, int64_t N, const double *x, int nh, const double *h, double *score,
+                   const BatchSource &source, hipStream_t s) {
+    if (N > (int64_t(1) << 28) || (d == 3 && N > (int64_t(1) << 24))) {
+        set_error("kernel sums support N <= 2^28 (2^24 for d = 3)");
+        return MECDF_EUNSUPPORTED;
+    }
+    return kde_run_t<double, 1, double, double>(d, N, x, nullptr, nullptr, nh, h, nullptr, score,
+                                                0, s, &source);
 }
 
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh, const double *h,

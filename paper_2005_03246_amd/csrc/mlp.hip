@@ -98,11 +98,20 @@ __global__ __launch_bounds__(256) void k_features(const DevSet *__restrict__ set
         mad[k] = block_sum256(a1, buf) / (double)n;
         sd[k] = sqrt(m2[k]) > 1e-300 ? sqrt(m2[k]) : 1e-300;
     }
+    double frac[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // within 1/4, 1, 2 sd
     for (int k = 0; k < d; ++k) {
-        double c = 0;
-        for (int64_t i = threadIdx.x; i < n; i += 256)
-            c += fabs(S.x[(int64_t)k * n + i] - mean[k]) <= 0.5 * sd[k] ? 1.0 : 0.0;
+        double c = 0, q1 = 0, q4 = 0, q8 = 0;
+        for (int64_t i = threadIdx.x; i < n; i += 256) {
+            const double a = fabs(S.x[(int64_t)k * n + i] - mean[k]);
+            c += a <= 0.5 * sd[k] ? 1.0 : 0.0;
+            q1 += a <= 0.25 * sd[k] ? 1.0 : 0.0;
+            q4 += a <= sd[k] ? 1.0 : 0.0;
+            q8 += a <= 2.0 * sd[k] ? 1.0 : 0.0;
+        }
         half[k] = block_sum256(c, buf) / (double)n;
+        frac[k][0] = block_sum256(q1, buf) / (double)n;
+        frac[k][1] = block_sum256(q4, buf) / (double)n;
+        frac[k][2] = block_sum256(q8, buf) / (double)n;
     }
     int np = 0;
     double corr_sum = 0.0;
@@ -133,6 +142,8 @@ __global__ __launch_bounds__(256) void k_features(const DevSet *__restrict__ set
         f[8 + k] = (float)((m4[k] / (m2[k] * m2[k]) - 3.0) / 10.0);
         f[14 + k] = (float)(mad[k] / sd[k]);
         f[17 + k] = (float)half[k];
+        for (int q = 0; q < 3; ++q)
+            f[20 + 3 * k + q] = (float)frac[k][q];
     }
     f[11] = np ? (float)(corr_sum / np) : 0.f;
     f[12] = (float)(lg - log((double)n) / (d + 4.0));
@@ -400,9 +411,10 @@ __global__ void k_mlp_gsum(const float *__restrict__ p1, int ntile, const float 
     }
 }
 
+// Adam step with decoupled weight decay: p -= lr (m^ / (sqrt(v^) + eps) + wd p)
 __global__ void k_mlp_adam(float *__restrict__ P, const float *__restrict__ G,
-                           float *__restrict__ m, float *__restrict__ v, float lr, float b1,
-                           float b2, float eps, float c1, float c2) {
+                           float *__restrict__ m, float *__restrict__ v, float lr, float wd,
+                           float b1, float b2, float eps, float c1, float c2) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= kParams)
         return;
@@ -411,7 +423,8 @@ __global__ void k_mlp_adam(float *__restrict__ P, const float *__restrict__ G,
     float vi = b2 * v[i] + (1.f - b2) * g * g;
     m[i] = mi;
     v[i] = vi;
-    P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    float p = P[i];
+    P[i] = p - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p);
 }
 
 // ------------------------------------------------------------ host side
@@ -503,7 +516,7 @@ int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, fl
 }
 
 int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps, float lr,
-              float *losses, hipStream_t s) {
+              float wd, float *losses, hipStream_t s) {
     MlpWork w;
     MECDF_TRY(mlp_work(B, w));
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -514,7 +527,7 @@ int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int 
         p1 *= b1;
         p2 *= b2;
         hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)ceil_div(kParams, 256)), dim3(256), 0, s, P,
-                           w.G, adam, adam + kParams, lr, b1, b2, eps, (float)(1.0 - p1),
+                           w.G, adam, adam + kParams, lr, wd, b1, b2, eps, (float)(1.0 - p1),
                            (float)(1.0 - p2));
         MECDF_LAUNCH_CHECK();
     }

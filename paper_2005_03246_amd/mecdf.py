@@ -301,9 +301,9 @@ _lib.mecdf_mlp_forward.argtypes = [_I, _P, _P, _P, _P]
 _lib.mecdf_mlp_forward.restype = _I
 _lib.mecdf_mlp_grad.argtypes = [_I, _P, _P, _P, _P, _P, _P]
 _lib.mecdf_mlp_grad.restype = _I
-_lib.mecdf_mlp_train.argtypes = [_I, _P, _P, _P, _P, _I, ctypes.c_float, _P, _P]
+_lib.mecdf_mlp_train.argtypes = [_I, _P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, _P, _P]
 _lib.mecdf_mlp_train.restype = _I
-_lib.mecdf_bw_select.argtypes = [_P, _I, _P, _I, _P, _P, _P, _P, _P]
+_lib.mecdf_bw_select.argtypes = [_P, _I, _P, _I, _P, _I, _P, _P, _P, _P]
 _lib.mecdf_bw_select.restype = _I
 
 
@@ -372,21 +372,28 @@ def mlp_grad(feat, target, params, stream=None):
     return grad, loss
 
 
-def mlp_train(feat, target, params, adam, steps, lr, stream=None):
-    """In-place Adam steps on params (float32 GPU vector); returns the losses."""
+def mlp_train(feat, target, params, adam, steps, lr, wd=0.0, stream=None):
+    """In-place Adam steps (decoupled weight decay wd) on params (float32 GPU
+    vector); returns the losses."""
     feat, target = _f32(feat), _f32(target)
     if not (params.is_cuda and params.dtype == torch.float32 and params.is_contiguous()):
         raise TypeError("params must be a contiguous float32 GPU tensor")
     losses = torch.empty((max(1, steps),), dtype=torch.float32, device=feat.device)
     _check(_lib.mecdf_mlp_train(feat.shape[0], _ptr(feat), _ptr(target), _ptr(params),
-                                _ptr(adam), int(steps), float(lr), _ptr(losses),
+                                _ptr(adam), int(steps), float(lr), float(wd), _ptr(losses),
                                 _stream_ptr(stream)), "mecdf_mlp_train")
     return losses[:steps]
 
 
-def bw_select(datasets, params, hgrid, stream=None):
-    """Learned-proposal LCV bandwidth selection (C ABI ``mecdf_bw_select``).
-    Returns numpy arrays (grid index, exact LCV there, bandwidths evaluated)."""
+BW_EXTEND = 0
+BW_WINDOW = 1
+
+
+def bw_select(datasets, params, hgrid, mode=BW_EXTEND, stream=None):
+    """Learned-proposal LCV bandwidth selection (C ABI ``mecdf_bw_select``):
+    mode BW_EXTEND widens the window until its best score is interior,
+    BW_WINDOW keeps the four grid points around the proposal.  Returns numpy
+    arrays (grid index, exact LCV there, bandwidths evaluated)."""
     import numpy as np
 
     arr, keep = _sets(datasets)
@@ -396,7 +403,8 @@ def bw_select(datasets, params, hgrid, stream=None):
     hidx = (ctypes.c_int * n)()
     lcv = (ctypes.c_double * n)()
     ev = (ctypes.c_int * n)()
-    _check(_lib.mecdf_bw_select(ctypes.addressof(arr), n, _ptr(params), len(hgrid), hg, hidx,
-                                lcv, ev, _stream_ptr(stream)), "mecdf_bw_select")
+    _check(_lib.mecdf_bw_select(ctypes.addressof(arr), n, _ptr(params), len(hgrid), hg,
+                                int(mode), hidx, lcv, ev, _stream_ptr(stream)),
+           "mecdf_bw_select")
     return (np.array(hidx[:], dtype=np.int64), np.array(lcv[:], dtype=np.float64),
             np.array(ev[:], dtype=np.int64))

@@ -39,7 +39,12 @@ def test_features_match_numpy(lib):
         np.testing.assert_allclose(f[14:14 + d], np.abs(c).mean(1) / sd, rtol=1e-5)
         np.testing.assert_allclose(f[17:17 + d], (np.abs(c) <= 0.5 * sd[:, None]).mean(1),
                                    rtol=1e-6, atol=1e-6)
-        assert np.all(f[20:] == 0)
+        for k in range(d):
+            a = np.abs(c[k]) / sd[k]
+            np.testing.assert_allclose(f[20 + 3 * k:23 + 3 * k],
+                                       [np.mean(a <= 0.25), np.mean(a <= 1.0), np.mean(a <= 2.0)],
+                                       rtol=1e-6, atol=1e-6)
+        assert np.all(f[20 + 3 * d:] == 0)
 
 
 def _rand_problem(B, seed):
@@ -89,6 +94,22 @@ def test_training_reduces_loss(lib):
     assert float(l_now.cpu()) < 0.2 * losses[0]
 
 
+def test_adamw_first_step(lib):
+    """One step from a zero state: the bias-corrected moments are g and g^2,
+    so the update is p - lr (g / (|g| + eps) + wd p)."""
+    X, T, p = _rand_problem(40, 8)
+    Xt, Tt = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    p0 = torch.from_numpy(p).cuda()
+    G, _ = lib.mlp_grad(Xt, Tt, p0)
+    g = G.cpu().numpy().astype(np.float64)
+    lr, wd = 1e-3, 0.7
+    p1 = p0.clone()
+    adam = torch.zeros((2 * lib.MLP_PARAMS,), dtype=torch.float32, device="cuda")
+    lib.mlp_train(Xt, Tt, p1, adam, 1, lr, wd)
+    want = p.astype(np.float64) - lr * (g / (np.abs(g) + 1e-8) + wd * p.astype(np.float64))
+    np.testing.assert_allclose(p1.cpu().numpy(), want, rtol=1e-5, atol=1e-7)
+
+
 def test_lcv_batched_matches_oracle(lib):
     sets = datagen.config5(count=5, log2n_lo=8, log2n_hi=10, seed=21)
     hs = [[0.05, 0.2], [0.1], [0.03, 0.3, 1.0], [0.5], [0.2, 0.4]]
@@ -121,3 +142,9 @@ def test_learned_selection_vs_grid_search(lib):
     assert np.all(gap >= -1e-12)
     assert gap.mean() <= np.log(1 / 0.99)
     assert evals.mean() < 16
+    # the single-window mode: four exact evaluations around the same proposal
+    widx, wlcv, wev = bandwidth.select(test, params, hgrid, lib.BW_WINDOW)
+    np.testing.assert_allclose(wlcv, mat[rows, widx], rtol=1e-12, atol=1e-12)
+    assert np.all(wev == 4)
+    # the extension only adds evaluations, so its choice is at least as good
+    assert np.all(lcv >= wlcv - 1e-12)
