@@ -33,6 +33,8 @@
 //                being data-left / query-right at every enclosing split.
 // Counts are exact int64; weighted sums accumulate in float64 in a fixed
 // order, so results are deterministic.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "radix.hpp"
 
@@ -382,6 +384,146 @@ __global__ __launch_bounds__(256) void k_merge_items(
         wout[pos] = win[p];
 }
 
+// Merge-path version of k_merge_items for blocks of h >= kMpT / 2 items: each
+// workgroup produces kMpT consecutive outputs of one merged block.  Two
+// binary searches on the merge diagonal give the A and B ranges feeding the
+// tile, which are staged in LDS (items, keys, weights, prefix values); each
+// thread finds its own diagonal in LDS and merges four outputs (A first on
+// equal keys, as in k_merge_items), recording where each output comes from;
+// the workgroup then writes the tile with coalesced stores.  An output's count
+// of items from the other side before it is its merge position, so the
+// results equal those of k_merge_items.
+constexpr int kMpT = 1024;
+
+template <int NC>
+__device__ __forceinline__ uint64_t item_key_sel(const Item<NC> &it, int m) {
+    uint32_t c = it.c[0];
+#pragma unroll
+    for (int k = 1; k < NC; ++k)
+        c = (k == m - 1) ? it.c[k] : c;
+    return ((uint64_t)c << 1) | (uint64_t)(it.idt & 1u);
+}
+
+template <int NC, bool kW, bool kCount>
+__global__ __launch_bounds__(256) void k_merge_path(
+    const Item<NC> *__restrict__ in, const double *__restrict__ win,
+    Item<NC> *__restrict__ out, double *__restrict__ wout,
+    Item<NC> *__restrict__ copy, double *__restrict__ wcopy,
+    const void *__restrict__ Pin_raw, void *__restrict__ Pout_raw,
+    void *__restrict__ acc_raw, int64_t n, int64_t h, int m, uint32_t mask) {
+    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    constexpr int kWn = kW ? kMpT : 1;
+    constexpr int kCn = kCount ? kMpT : 1;
+    __shared__ Item<NC> sI[kMpT];     // A range, then B range
+    __shared__ uint64_t sk[kMpT];     // their keys
+    __shared__ double sW[kWn];        // their weights
+    __shared__ AccT sP[kCn];          // their prefix values
+    __shared__ AccT sOther[kCn];      // per output: prefix of the other side
+    __shared__ uint16_t sSrc[kMpT];   // per output: source slot in sI
+    __shared__ int64_t sspl[2];
+    __shared__ AccT sPrev[2];         // prefix just before the A and the B range
+    const int tid = threadIdx.x;
+    const AccT *Pin = reinterpret_cast<const AccT *>(Pin_raw);
+    const int64_t o0 = (int64_t)blockIdx.x * kMpT;
+    const int64_t s = (o0 / (2 * h)) * (2 * h);
+    const int64_t ha = (n - s) < h ? (n - s) : h;
+    const int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
+    const Item<NC> *A = in + s;
+    const Item<NC> *B = A + ha;
+    const int64_t k0 = o0 - s;
+    const int64_t k1 = k0 + kMpT < ha + hb ? k0 + kMpT : ha + hb;
+    if (tid < 2) {
+        const int64_t k = tid ? k1 : k0;
+        int64_t lo = k - hb > 0 ? k - hb : 0;
+        int64_t hi = k < ha ? k : ha;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (item_key_sel(A[mid], m) <= item_key_sel(B[k - mid - 1], m))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        sspl[tid] = lo;
+    }
+    __syncthreads();
+    const int64_t ia0 = sspl[0], ia1 = sspl[1];
+    const int64_t jb0 = k0 - ia0, jb1 = k1 - ia1;
+    const int na = (int)(ia1 - ia0), nb = (int)(jb1 - jb0);
+    const int tot = na + nb;
+    for (int t = tid; t < tot; t += 256) {
+        const int64_t g = t < na ? s + ia0 + t : s + ha + jb0 + (t - na);
+        const Item<NC> it = in[g];
+        sI[t] = it;
+        sk[t] = item_key_sel(it, m);
+        if constexpr (kW)
+            sW[t] = win[g];
+        if constexpr (kCount)
+            sP[t] = Pin[g];
+    }
+    if constexpr (kCount) {
+        if (tid == 0)
+            sPrev[0] = ia0 > 0 ? Pin[s + ia0 - 1] : AccT(0);
+        if (tid == 1)
+            sPrev[1] = jb0 > 0 ? Pin[s + ha + jb0 - 1] : AccT(0);
+    }
+    __syncthreads();
+    const int dl = 4 * tid;
+    if (dl < tot) {
+        const uint64_t *ska = sk;
+        const uint64_t *skb = sk + na;
+        int lo = dl - nb > 0 ? dl - nb : 0;
+        int hi = dl < na ? dl : na;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ska[mid] <= skb[dl - mid - 1])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int i = lo, j = dl - lo;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (dl + u >= tot)
+                break;
+            const bool takeA = (j >= nb) || (i < na && ska[i] <= skb[j]);
+            if (takeA) {
+                sSrc[dl + u] = (uint16_t)i;
+                if constexpr (kCount)  // B items before it: jb0 + j
+                    sOther[dl + u] = j > 0 ? sP[na + j - 1] : sPrev[1];
+                ++i;
+            } else {
+                sSrc[dl + u] = (uint16_t)(na + j);
+                if constexpr (kCount) {  // A items before it: ia0 + i
+                    const AccT other = i > 0 ? sP[i - 1] : sPrev[0];
+                    sOther[dl + u] = other;
+                    const uint32_t idt = sI[na + j].idt;
+                    if (other != AccT(0) && active_query(idt, mask))
+                        reinterpret_cast<AccT *>(acc_raw)[idt >> kIdShift] += other;
+                }
+                ++j;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t bit = 1u << m;
+    for (int q = tid; q < tot; q += 256) {
+        const int src = sSrc[q];
+        const int64_t o = o0 + q;
+        Item<NC> it = sI[src];
+        if constexpr (kCount) {
+            reinterpret_cast<AccT *>(Pout_raw)[o] = sP[src] + sOther[q];
+        } else {
+            it.idt = src < na ? (it.idt & ~bit) : (it.idt | bit);
+            copy[o] = it;
+            if constexpr (kW)
+                wcopy[o] = sW[src];
+        }
+        out[o] = it;
+        if constexpr (kW)
+            wout[o] = sW[src];
+    }
+}
+
 // ---- segmented inclusive prefix of active-data weight ---------------------
 // Segments are the aligned blocks of size h (a power of two >= kBlockT).
 constexpr int kSegItems = 8;
@@ -667,19 +809,35 @@ template <int NC, bool kW> struct Dnc {
         }
         MECDF_LAUNCH_CHECK();
         const unsigned nb = (unsigned)ceil_div(n, 256);
+        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
         for (int64_t h = kBlockT; h < H; h *= 2) {
+            // merged blocks of 2h >= kMpT items: the merge-path kernel
+            const bool path = 2 * h >= kMpT;
             if (last) {
                 ProfScope prof("points_merge_count", s);
-                hipLaunchKernelGGL((k_merge_items<NC, kW, true>), dim3(nb), dim3(256), 0, s,
-                                   S[depth], SW[depth], T[depth], TW[depth], nullptr,
-                                   nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
-                                   depth, mask);
+                if (path)
+                    hipLaunchKernelGGL((k_merge_path<NC, kW, true>), dim3(nbp), dim3(256), 0, s,
+                                       S[depth], SW[depth], T[depth], TW[depth], nullptr,
+                                       nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
+                                       depth, mask);
+                else
+                    hipLaunchKernelGGL((k_merge_items<NC, kW, true>), dim3(nb), dim3(256), 0, s,
+                                       S[depth], SW[depth], T[depth], TW[depth], nullptr,
+                                       nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
+                                       depth, mask);
                 std::swap(P, P2);
             } else {
                 ProfScope prof("points_merge", s);
-                hipLaunchKernelGGL((k_merge_items<NC, kW, false>), dim3(nb), dim3(256), 0, s,
-                                   S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
-                                   SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth, mask);
+                if (path)
+                    hipLaunchKernelGGL((k_merge_path<NC, kW, false>), dim3(nbp), dim3(256), 0, s,
+                                       S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
+                                       SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
+                                       mask);
+                else
+                    hipLaunchKernelGGL((k_merge_items<NC, kW, false>), dim3(nb), dim3(256), 0, s,
+                                       S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
+                                       SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
+                                       mask);
             }
             MECDF_LAUNCH_CHECK();
             std::swap(S[depth], T[depth]);
@@ -835,6 +993,136 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     return MECDF_OK;
 }
 
+// ---- direct evaluation for small samples --------------------------------
+// eq. (ECDF) / (ESF) as written: every (query, point) pair.  64 queries per
+// block, one per lane; wave w of 16 takes the w-th sixteenth of the points, 64
+// at a time through its own LDS slice (broadcast reads), then the
+// partial results are combined in wave order.  Counts are exact; float64
+// weights are summed with Neumaier compensation and float32 weights with
+// Kahan compensation, in a fixed order.
+constexpr int kDirectWaves = 16;
+
+template <typename P> struct DirectAcc;
+template <> struct DirectAcc<NoPayload> {
+    int64_t v = 0;
+    __device__ __forceinline__ void add(NoPayload) { ++v; }
+    __device__ __forceinline__ void merge(const DirectAcc &o) { v += o.v; }
+};
+template <> struct DirectAcc<double> {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double a) {
+        double t = s + a;
+        c += fabs(s) >= fabs(a) ? (s - t) + a : (a - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ void merge(const DirectAcc &o) {
+        add(o.s);
+        c += o.c;
+    }
+};
+template <> struct DirectAcc<float> {
+    KahanF k;
+    __device__ __forceinline__ void add(float a) { k.add(a); }
+    __device__ __forceinline__ void merge(const DirectAcc &o) {
+        k.add(o.k.s);
+        k.c += o.k.c;
+    }
+};
+
+template <int D, typename P, typename OutT>
+__global__ __launch_bounds__(kDirectWaves * 64) void k_points_direct(
+    const double *__restrict__ x, int64_t n, const P *__restrict__ y,
+    OutT *__restrict__ F, int survival) {
+    constexpr bool kW = !std::is_same<P, NoPayload>::value;
+    __shared__ double sx[kDirectWaves][D][64];
+    __shared__ typename std::conditional<kW, P, int>::type sy[kDirectWaves][64];
+    __shared__ __attribute__((aligned(16))) char part_raw[sizeof(DirectAcc<P>) * kDirectWaves * 64];
+    DirectAcc<P> *part = reinterpret_cast<DirectAcc<P> *>(part_raw);
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    double q[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        q[k] = i < n ? x[(int64_t)k * n + i] : 0.0;
+    // this wave's share of the points
+    const int64_t per = (n + kDirectWaves - 1) / kDirectWaves;
+    const int64_t j0 = (int64_t)w * per;
+    const int64_t j1 = j0 + per < n ? j0 + per : n;
+    DirectAcc<P> acc;
+    for (int64_t t0 = j0; t0 < j1; t0 += 64) {
+        const int64_t j = t0 + lane;
+        if (j < j1) {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                sx[w][k][lane] = x[(int64_t)k * n + j];
+            if constexpr (kW)
+                sy[w][lane] = y[j];
+        }
+        wave_lds_fence();
+        const int cnt = j1 - t0 < 64 ? (int)(j1 - t0) : 64;
+        for (int t = 0; t < cnt; ++t) {
+            bool dom = true;
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+                dom = dom && (survival ? (sx[w][k][t] > q[k]) : (sx[w][k][t] <= q[k]));
+            if (dom) {
+                if constexpr (kW)
+                    acc.add(sy[w][t]);
+                else
+                    acc.add(NoPayload{});
+            }
+        }
+        wave_lds_fence();
+    }
+    part[w * 64 + lane] = acc;
+    __syncthreads();
+    if (w != 0 || i >= n)
+        return;
+    DirectAcc<P> r = part[lane];
+#pragma unroll
+    for (int q2 = 1; q2 < kDirectWaves; ++q2)
+        r.merge(part[q2 * 64 + lane]);
+    if constexpr (kW) {
+        if constexpr (std::is_same<P, double>::value)
+            F[i] = (OutT)((r.s + r.c) / (double)n);
+        else
+            F[i] = (OutT)((double)r.k.get() / (double)n);
+    } else {
+        F[i] = (OutT)r.v;
+    }
+}
+
+template <int D>
+static int points_direct_d(int64_t N, const double *x, const void *y, void *F, int survival,
+                           int prec, hipStream_t s) {
+    const unsigned nb = (unsigned)ceil_div(N, 64);
+    ProfScope prof("points_direct", s);
+    if (y == nullptr)
+        hipLaunchKernelGGL((k_points_direct<D, NoPayload, int64_t>), dim3(nb),
+                           dim3(kDirectWaves * 64), 0, s, x, N, (const NoPayload *)nullptr,
+                           (int64_t *)F, survival);
+    else if (prec == MECDF_F64)
+        hipLaunchKernelGGL((k_points_direct<D, double, double>), dim3(nb),
+                           dim3(kDirectWaves * 64), 0, s, x, N, (const double *)y,
+                           (double *)F, survival);
+    else
+        hipLaunchKernelGGL((k_points_direct<D, float, float>), dim3(nb),
+                           dim3(kDirectWaves * 64), 0, s, x, N, (const float *)y,
+                           (float *)F, survival);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
+// Samples up to this size use the direct evaluation (cost N^2 d); the
+// environment variable MECDF_POINTS_DIRECT_MAX overrides it (0: never).
+static int64_t points_direct_max() {
+    const char *e = std::getenv("MECDF_POINTS_DIRECT_MAX");
+    if (e && *e)
+        return (int64_t)std::strtoll(e, nullptr, 10);
+    return int64_t(1) << 16;
+}
+
 template <int NC>
 static int points_dispatch(int d, int64_t N, const double *x, const void *y, void *F,
                            int survival, int prec, hipStream_t s) {
@@ -853,6 +1141,16 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
     if (N > (int64_t(1) << 26)) {
         set_error("the points path supports N <= 2^26");
         return MECDF_EUNSUPPORTED;
+    }
+    if (N > 0 && N <= points_direct_max()) {
+        switch (d) {
+        case 1: return points_direct_d<1>(N, x, y, F, survival, prec, s);
+        case 2: return points_direct_d<2>(N, x, y, F, survival, prec, s);
+        case 3: return points_direct_d<3>(N, x, y, F, survival, prec, s);
+        case 4: return points_direct_d<4>(N, x, y, F, survival, prec, s);
+        case 5: return points_direct_d<5>(N, x, y, F, survival, prec, s);
+        default: return points_direct_d<6>(N, x, y, F, survival, prec, s);
+        }
     }
     switch (d) {
     case 1:

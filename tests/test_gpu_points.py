@@ -18,6 +18,17 @@ def lib():
     return mecdf
 
 
+@pytest.fixture(params=["direct", "recursion"])
+def path(request, monkeypatch):
+    """Small samples go to the direct (all pairs) kernel unless
+    MECDF_POINTS_DIRECT_MAX is 0; each small case runs on both paths."""
+    if request.param == "recursion":
+        monkeypatch.setenv("MECDF_POINTS_DIRECT_MAX", "0")
+    else:
+        monkeypatch.delenv("MECDF_POINTS_DIRECT_MAX", raising=False)
+    return request.param
+
+
 def dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
 
@@ -39,7 +50,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-def test_points_random(lib, case):
+def test_points_random(lib, path, case):
     d, n, dec = case
     g = np.random.default_rng(77 + 13 * d + n)
     x = np.round(g.normal(size=(d, n)), dec)   # ties on purpose
@@ -63,7 +74,7 @@ def test_points_random(lib, case):
     check_weighted(f.cpu().numpy(), w, a, 1e-5)
 
 
-def test_hand_points(lib, golden):
+def test_hand_points(lib, path, golden):
     g = golden["points_d2"]
     x = np.array(g["x"], dtype=float)
     y = np.array(g["y"], dtype=float)
@@ -75,7 +86,7 @@ def test_hand_points(lib, golden):
     np.testing.assert_array_equal(got, np.array(g["esf_weighted_sums"]) / 5.0)
 
 
-def test_all_equal_points_and_nan(lib):
+def test_all_equal_points_and_nan(lib, path):
     x = np.ones((3, 1000))
     np.testing.assert_array_equal(lib.ecdf_points(dev(x)).cpu().numpy(), np.full(1000, 1000))
     np.testing.assert_array_equal(lib.esf_points(dev(x)).cpu().numpy(), np.zeros(1000))
@@ -87,7 +98,7 @@ def test_all_equal_points_and_nan(lib):
     np.testing.assert_array_equal(lib.esf_points(dev(x)).cpu().numpy(), oracle.esf(x, x))
 
 
-def test_config1_uniform_d2_full(lib):
+def test_config1_uniform_d2_full(lib, path):
     """d = 2, N = 4096 uniform points: bit-exact counts against the full brute force."""
     x = datagen.config1()
     xt = dev(x)
@@ -95,7 +106,7 @@ def test_config1_uniform_d2_full(lib):
     np.testing.assert_array_equal(lib.esf_points(xt).cpu().numpy(), oracle.esf(x, x))
 
 
-def test_config3_reduced_full(lib):
+def test_config3_reduced_full(lib, path):
     """The d = 4 tied t(3)-copula workload at N = 2^15, every point checked."""
     x = datagen.config3(n=1 << 15)
     xt = dev(x)
@@ -120,7 +131,7 @@ def test_config3_full_size_sampled(lib):
     assert Fb.max() < x.shape[1]
 
 
-def test_points_deterministic(lib):
+def test_points_deterministic(lib, path):
     g = np.random.default_rng(9)
     x = dev(np.round(g.normal(size=(3, 20000)), 2))
     y = dev(g.normal(size=20000))
