@@ -306,9 +306,9 @@ __global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
     for (int r = 0; r < kScatItems; ++r) {
         int64_t p = base + ((int64_t)(w * kScatItems + r) << 6) + lane;
         bool valid = p < n;
-        key[r] = valid ? kin[p] : K(0);
+        key[r] = valid ? __builtin_nontemporal_load(kin + p) : K(0);
         if constexpr (kPay)
-            pay[r] = valid ? pin[p] : P();
+            pay[r] = valid ? __builtin_nontemporal_load(pin + p) : P();
     }
     if (tid < R) {
 #pragma unroll
