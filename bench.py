@@ -32,6 +32,13 @@ LOG2N = 24
 # 1 GiB device-to-device copy (read factor 2.0, write factor 1.0).  Valid only
 # for the kernel source they were taken on, identified by its SHA-256.
 TRAFFIC = {
+    "grid_axis_scan": {
+        "source": "paper_2005_03246_amd/csrc/grid.hip",
+        "sha256": "4976e688ff536acd10368e7fd81f6659852b4308bdc404c6ee46d4a6a493c7a1",
+        "prec": "f64",
+        "fetch_kib": 131125.1, "fetch_factor": 2.0,
+        "write_kib": 262144.0, "write_factor": 1.0,
+    },
     "radix_scatter": {
         "source": "paper_2005_03246_amd/csrc/radix.hpp",
         "sha256": "89bb683aac5023b9bba017b58e8116dda48f5847643db643706c79b5d3d9a0b8",
@@ -102,6 +109,32 @@ def parse():
     return ap.parse_args()
 
 
+def copy_ceiling(reps: int = 5):
+    """Measured copy rate: median over reps of a 1 GiB device-to-device copy
+    (1 GiB read + 1 GiB written), in GB/s."""
+    import torch
+
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        b.copy_(a)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    ms = ts[len(ts) // 2]
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
 def copy_calibration():
     """Three copies of 1 GiB between two device buffers: under rocprofv3
     --pmc, FETCH_SIZE and WRITE_SIZE of this copy give the factors that turn
@@ -147,12 +180,31 @@ def secondary():
     x = torch.from_numpy(datagen.config1()).cuda()
     ms = _time_calls(lambda: (mecdf.ecdf_points(x), mecdf.esf_points(x)), 20, 3)
     out["points_d2_N4096_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
-                                     "Gpoint-evals/s": 2 * 4096 / (ms * 1e-3) / 1e9}
+                                     "Gpoint-evals/s": 2 * 4096 / (ms * 1e-3) / 1e9,
+                                     "note": "latency bound (96 KB in and out); no roofline"}
     x3 = torch.from_numpy(datagen.config3()).cuda()
     n3 = x3.shape[1]
     ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
+    # merge levels of the last coordinate: per item, the 16-byte item and the
+    # 8-byte prefix value read and written once
+    torch.cuda.synchronize()
+    mecdf.profile_reset()
+    mecdf.profile_enable(True)
+    mecdf.ecdf_points(x3)
+    torch.cuda.synchronize()
+    mecdf.profile_enable(False)
+    kern = mecdf.profile_collect()
+    mc_ms, mc_n = kern.get("points_merge_count", (0.0, 0))
+    merge = None
+    if mc_n:
+        ab = 2 * n3 * (2 * 16 + 2 * 8)
+        gbs = ab / (mc_ms / mc_n * 1e-3) / 1e9
+        merge = {"kernel": "points_merge_count", "launches": mc_n,
+                 "avg_launch_ms": mc_ms / mc_n, "algorithmic_bytes_per_launch": ab,
+                 "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
     out["points_d4_N2^22_tied_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
-                                          "Gpoint-evals/s": 2 * n3 / (ms * 1e-3) / 1e9}
+                                          "Gpoint-evals/s": 2 * n3 / (ms * 1e-3) / 1e9,
+                                          "merge_levels": merge}
     del x3
     x4, y4, h4 = datagen.config4()
     n4 = x4.shape[1]
@@ -341,9 +393,11 @@ def main():
     roof = {"bound": "hbm", "kernel": dname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "achieved": None, "frac": None, "traffic": measured_traffic(dname, args.prec),
             "avg_launch_ms": avg_ms}
+    ceil = copy_ceiling()
+    roof["copy_ceiling"] = ceil
     if ab is not None:
         gbs = ab / (avg_ms * 1e-3) / 1e9
-        roof.update(achieved=gbs, frac=gbs / HBM_PEAK_GBS,
+        roof.update(achieved=gbs, frac=gbs / HBM_PEAK_GBS, frac_of_copy=gbs / ceil,
                     algorithmic_bytes_per_launch=ab)
     kernels = {k: {"total_ms_per_step": v[0] / args.steps,
                    "launches_per_step": v[1] / args.steps} for k, v in kern.items()}

@@ -432,18 +432,42 @@ __global__ __launch_bounds__(256) void k_merge_path(
     const Item<NC> *B = A + ha;
     const int64_t k0 = o0 - s;
     const int64_t k1 = k0 + kMpT < ha + hb ? k0 + kMpT : ha + hb;
-    if (tid < 2) {
-        const int64_t k = tid ? k1 : k0;
+    if (tid < 64) {
+        // wave 0: lanes 0..31 search diagonal k0, lanes 32..63 diagonal k1,
+        // for the smallest i with A[i] after B[k-i-1] (32 probes per step)
+        const int half = tid >> 5, l = tid & 31;
+        const int64_t k = half ? k1 : k0;
         int64_t lo = k - hb > 0 ? k - hb : 0;
         int64_t hi = k < ha ? k : ha;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (item_key_sel(A[mid], m) <= item_key_sel(B[k - mid - 1], m))
-                lo = mid + 1;
-            else
-                hi = mid;
+        const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+        for (;;) {
+            const int64_t span = hi - lo;
+            const bool go = span > 0;  // uniform over the half wave
+            int64_t step = (span + 31) / 32;
+            int64_t q = lo + (int64_t)(l + 1) * step - 1;
+            const bool probe = go && q < hi;
+            bool after = false;
+            if (probe)
+                after = item_key_sel(A[q], m) > item_key_sel(B[k - q - 1], m);
+            const uint64_t bal = __ballot(probe && after) & hmask;
+            const uint64_t any = __ballot(go) & hmask;
+            if (any == 0ull)
+                break;
+            if (go) {
+                if (bal) {
+                    const int f = (__ffsll((unsigned long long)bal) - 1) & 31;
+                    const int64_t qf = lo + (int64_t)(f + 1) * step - 1;
+                    hi = qf;
+                    lo = f == 0 ? lo : lo + (int64_t)f * step;
+                } else {
+                    // every probe below hi said "before": past the last one
+                    const int64_t nvalid = span / step < 32 ? span / step : 32;
+                    lo += nvalid * step;
+                }
+            }
         }
-        sspl[tid] = lo;
+        if (l == 0)
+            sspl[half] = lo;
     }
     __syncthreads();
     const int64_t ia0 = sspl[0], ia1 = sspl[1];
