@@ -415,10 +415,9 @@ __global__ __launch_bounds__(256) void k_merge_path(
     constexpr int kWn = kW ? kMpT : 1;
     constexpr int kCn = kCount ? kMpT : 1;
     __shared__ Item<NC> sI[kMpT];     // A range, then B range
-    __shared__ uint64_t sk[kMpT];     // their keys
+    __shared__ uint32_t sk[kMpT];     // their keys (ranks < 2^31)
     __shared__ double sW[kWn];        // their weights
     __shared__ AccT sP[kCn];          // their prefix values
-    __shared__ AccT sOther[kCn];      // per output: prefix of the other side
     __shared__ uint16_t sSrc[kMpT];   // per output: source slot in sI
     __shared__ int64_t sspl[2];
     __shared__ AccT sPrev[2];         // prefix just before the A and the B range
@@ -478,7 +477,7 @@ __global__ __launch_bounds__(256) void k_merge_path(
         const int64_t g = t < na ? s + ia0 + t : s + ha + jb0 + (t - na);
         const Item<NC> it = in[g];
         sI[t] = it;
-        sk[t] = item_key_sel(it, m);
+        sk[t] = (uint32_t)item_key_sel(it, m);
         if constexpr (kW)
             sW[t] = win[g];
         if constexpr (kCount)
@@ -493,8 +492,8 @@ __global__ __launch_bounds__(256) void k_merge_path(
     __syncthreads();
     const int dl = 4 * tid;
     if (dl < tot) {
-        const uint64_t *ska = sk;
-        const uint64_t *skb = sk + na;
+        const uint32_t *ska = sk;
+        const uint32_t *skb = sk + na;
         int lo = dl - nb > 0 ? dl - nb : 0;
         int hi = dl < na ? dl : na;
         while (lo < hi) {
@@ -510,22 +509,11 @@ __global__ __launch_bounds__(256) void k_merge_path(
             if (dl + u >= tot)
                 break;
             const bool takeA = (j >= nb) || (i < na && ska[i] <= skb[j]);
-            if (takeA) {
-                sSrc[dl + u] = (uint16_t)i;
-                if constexpr (kCount)  // B items before it: jb0 + j
-                    sOther[dl + u] = j > 0 ? sP[na + j - 1] : sPrev[1];
+            sSrc[dl + u] = (uint16_t)(takeA ? i : na + j);
+            if (takeA)
                 ++i;
-            } else {
-                sSrc[dl + u] = (uint16_t)(na + j);
-                if constexpr (kCount) {  // A items before it: ia0 + i
-                    const AccT other = i > 0 ? sP[i - 1] : sPrev[0];
-                    sOther[dl + u] = other;
-                    const uint32_t idt = sI[na + j].idt;
-                    if (other != AccT(0) && active_query(idt, mask))
-                        reinterpret_cast<AccT *>(acc_raw)[idt >> kIdShift] += other;
-                }
+            else
                 ++j;
-            }
         }
     }
     __syncthreads();
@@ -535,7 +523,19 @@ __global__ __launch_bounds__(256) void k_merge_path(
         const int64_t o = o0 + q;
         Item<NC> it = sI[src];
         if constexpr (kCount) {
-            reinterpret_cast<AccT *>(Pout_raw)[o] = sP[src] + sOther[q];
+            // the output at tile position q takes src; the items of the other
+            // side before it in the tile number q - (its index in its range)
+            AccT other;
+            if (src < na) {
+                const int jb = q - src;  // B items before it: jb0 + jb
+                other = jb > 0 ? sP[na + jb - 1] : sPrev[1];
+            } else {
+                const int ia = q - (src - na);  // A items before it: ia0 + ia
+                other = ia > 0 ? sP[ia - 1] : sPrev[0];
+                if (other != AccT(0) && active_query(it.idt, mask))
+                    reinterpret_cast<AccT *>(acc_raw)[it.idt >> kIdShift] += other;
+            }
+            reinterpret_cast<AccT *>(Pout_raw)[o] = sP[src] + other;
         } else {
             it.idt = src < na ? (it.idt & ~bit) : (it.idt | bit);
             copy[o] = it;
