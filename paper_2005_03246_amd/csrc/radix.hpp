@@ -406,6 +406,36 @@ __global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
     (void)ntiles;
 }
 
+// All per-(tile, digit) offsets in one workgroup, for at most kOffSmall
+// tiles: thread d walks digit d's column of the tile-major count table
+// (exclusive running sum), the digit totals are scanned across the
+// workgroup, and the digit bases are added in a second walk.
+constexpr int kOffSmall = 64;
+static __global__ __launch_bounds__(512) void k_off_small(uint32_t *__restrict__ H, int64_t nt,
+                                                          int R) {
+    __shared__ uint32_t wt[8];
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+    if (d < R) {
+        for (int64_t t0 = 0; t0 < nt; t0 += 16) {
+            uint32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = t0 + u < nt ? H[(t0 + u) * R + d] : 0u;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                if (t0 + u < nt)
+                    H[(t0 + u) * R + d] = run;
+                run += v[u];
+            }
+        }
+    }
+    const uint32_t base = block_exclusive_scan<uint32_t, 8>(d < R ? run : 0u, wt, nullptr);
+    if (d < R)
+        for (int64_t t = 0; t < nt; ++t)
+            H[t * R + d] += base;
+}
+
 // Workspace needed by radix_sort for n keys.
 inline size_t radix_bsum_count(int64_t n) {
     int64_t nt = ceil_div(n, kRadixTile);
@@ -448,7 +478,10 @@ int radix_pass(const K *kin, const P *pin, K *kout, P *pout, int64_t n,
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nt), dim3(256), 0, s,
                            kin, n, shift, bits, rs.hist, nt);
     }
-    {
+    if (nt <= kOffSmall) {
+        ProfScope ps("radix_offsets", s);
+        hipLaunchKernelGGL(k_off_small, dim3(1), dim3(512), 0, s, rs.hist, nt, R);
+    } else {
         ProfScope ps("radix_offsets", s);
         int64_t nch = ceil_div(nt, kOffChunk);
         unsigned nb = (unsigned)ceil_div(nch * R, 256);
