@@ -288,7 +288,8 @@ def bandwidth_judge(train_count):
 
 def cpu_baseline(x, y, nodes, target_s):
     """The brute-force oracle on a bounded sample of grid nodes (ECDF and ESF
-    at each sampled node, full N), scaled to Gpoint-evals/s."""
+    at each sampled node, full N), scaled to Gpoint-evals/s, on all host
+    cores and on one core."""
     import numpy as np
 
     import oracle
@@ -296,24 +297,32 @@ def cpu_baseline(x, y, nodes, target_s):
     g = np.random.default_rng(99)
     d = x.shape[0]
 
-    def run(count):
+    def run(count, threads):
         idx = np.stack([g.integers(0, M_NODES, size=count) for _ in range(d)], 1)
         z = oracle.grid_points(nodes, idx)
         t0 = time.perf_counter()
-        oracle.ecdf(x, z, y)
-        oracle.esf(x, z, y)
+        oracle.ecdf(x, z, y, nthreads=threads)
+        oracle.esf(x, z, y, nthreads=threads)
         return time.perf_counter() - t0
 
-    t = run(16)
-    count = int(max(16, min(8192, 16 * target_s / max(t, 1e-3))))
-    t = run(count)
+    cores = oracle.max_threads()
+    run(4, 0)  # first touch of the sample and thread start-up, not timed
+    t = run(32, 0)
+    count = int(max(32, min(16384, 32 * target_s / max(t, 1e-3))))
+    t = run(count, 0)
+    # one core: a sample of a twentieth of the work time budget
+    t1 = run(4, 1)
+    c1 = int(max(4, min(4096, 4 * (target_s / 20.0) / max(t1, 1e-3))))
+    t1 = run(c1, 1)
     return {
         "value": 2 * count / t / 1e9,
         "unit": "Gpoint-evals/s",
-        "cores": oracle.max_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": "ECDF+ESF at %d random nodes of the 256^3 grid over all 2^24 "
-                  "points (%.1f s)" % (count, t),
+                  "points (%.1f s on %d threads)" % (count, t, cores),
+        "single_core": {"value": 2 * c1 / t1 / 1e9, "sample_nodes": c1,
+                        "seconds": t1},
     }
 
 
