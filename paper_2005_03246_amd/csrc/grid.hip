@@ -382,7 +382,7 @@ __device__ __forceinline__ void bin_chunks(BinAcc<T> *bins, uint64_t *mask,
 
 constexpr int kLineWaves = 4;         // waves per block of the wave kernel
 constexpr int kLineBatch = 8;         // chunks loaded together
-constexpr uint32_t kHeavyLine = 1024;  // longer lines go to the block kernel
+constexpr uint32_t kHeavyLine = 16384;  // longer lines go to the block kernel
 constexpr int kHeavyWaves = 8;
 
 // LDS of the block kernel with kW waves: the bins and the peer masks of every

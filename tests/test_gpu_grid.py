@@ -133,17 +133,19 @@ def test_empty_input_counts(lib):
 
 
 def test_many_lines_with_long_ones(lib):
-    """Over a thousand lines (one wavefront each), a few of them holding
-    thousands of points (handed to the workgroup kernel): every node checked,
+    """Over a thousand lines (one wavefront each), two of them holding more
+    than 16384 points (handed to the workgroup kernel): every node checked,
     for both outputs together and each alone."""
     g = np.random.default_rng(17)
-    n = 50000
+    n = 120000
     x = g.normal(size=(2, n))
-    heavy = g.random(n) < 0.2
-    x[0, heavy] = g.choice([-0.5, 0.1, 0.7], size=int(heavy.sum()))
+    heavy = g.random(n) < 0.4
+    x[0, heavy] = g.choice([-0.5, 0.7], size=int(heavy.sum()))
     x = np.round(x, 3)
-    nodes = [np.sort(g.choice(np.unique(x[0]), size=1100, replace=False)),
-             np.linspace(-2.5, 2.5, 20)]
+    nodes = [np.sort(g.choice(np.unique(x[0]), size=1030, replace=False)),
+             np.linspace(-2.5, 2.5, 8)]
+    c0 = np.searchsorted(nodes[0], x[0], side="left")
+    assert np.bincount(c0).max() > 16384 and len(nodes[0]) + 1 >= 1024
     z = oracle.grid_points(nodes)
     xt = dev(x)
     y = g.normal(size=n)
