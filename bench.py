@@ -103,6 +103,8 @@ def parse():
                     help="skip the learned-bandwidth judge")
     ap.add_argument("--bw-train", type=int, default=2048,
                     help="training datasets of the bandwidth network")
+    ap.add_argument("--secondary-only", action="store_true",
+                    help="only time the other workloads (points, kernel sums)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the "
                          "reference kernel that scales the HBM byte counters)")
@@ -330,6 +332,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.secondary_only:
+        print(json.dumps({"secondary": secondary()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported "

@@ -604,14 +604,16 @@ template <int CH>
 __global__ __launch_bounds__(256) void k_kacc_down(const double *__restrict__ hi,
                                                    const uint32_t *__restrict__ map, int64_t n,
                                                    double *__restrict__ lo, int add) {
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n)
+    // one thread per double of the [n][kKB * CH] arrays: stores coalesced,
+    // each record gathered by kKB * CH neighbouring threads
+    constexpr int W = kKB * CH;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n * W)
         return;
-    const double *s = hi + (map ? (int64_t)map[p] : p) * (kKB * CH);
-    double *d = lo + p * (kKB * CH);
-#pragma unroll
-    for (int q = 0; q < kKB * CH; ++q)
-        d[q] = add ? d[q] + s[q] : s[q];
+    const int64_t p = e / W;
+    const int q = (int)(e - p * W);
+    const double v = hi[(map ? (int64_t)map[p] : p) * W + q];
+    lo[e] = add ? lo[e] + v : v;
 }
 
 __global__ void k_kzero(double *a, int64_t n) {
@@ -958,27 +960,27 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                         KLevelArgs la{Mi.x[2], 2, Mi.x[0], S0.x[0], hs[q], Mi.x[1], M.x[1], h2,
                                       Mi.w0, Mi.w1, Mi.bits, n, h2, 0};
                         MECDF_TRY((run_scan<T, CH, 4>(la, kb, nt, agg, car, ai, s)));
-                        hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nb), dim3(256), 0, s, ai,
+                        hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ai,
                                            I[r - 1].map, n, aj, 0);
                         std::swap(ai, aj);
                     }
                     // ai in I[0] order (64-blocks of M sorted by x3): back to M order
-                    hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nb), dim3(256), 0, s, ai, imap[q],
+                    hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ai, imap[q],
                                        n, aj, 0);
                     // pairs inside the inner 64-blocks (M order) with different x1 sides
                     hipLaunchKernelGGL((k_kblock_pairs<T, CH>), dim3(nbw), dim3(256), 0, s, M, d,
                                        n, kb, 1, aj);
-                    hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nb), dim3(256), 0, s, aj, nullptr,
+                    hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, aj, nullptr,
                                        n, ao, 1);
                     MECDF_LAUNCH_CHECK();
                 }
                 ProfScope prof2("kde_down", s);
-                hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nb), dim3(256), 0, s, ao, So[q].map, n,
+                hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ao, So[q].map, n,
                                    an, 0);
                 std::swap(ao, an);
             }
             // ao in So[0] order (64-blocks of S0 sorted by x2): back to S0 order
-            hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nb), dim3(256), 0, s, ao, S0.map, n, an, 0);
+            hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ao, S0.map, n, an, 0);
             std::swap(ao, an);
             ProfScope prof3("kde_block_pairs", s);
             hipLaunchKernelGGL((k_kblock_pairs<T, CH>), dim3(nbw), dim3(256), 0, s, S0, d, n, kb,
