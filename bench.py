@@ -34,17 +34,17 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "4976e688ff536acd10368e7fd81f6659852b4308bdc404c6ee46d4a6a493c7a1",
+        "sha256": "da9da8e53cae686e63f4284498da187e09817cbe6653564273bec6701137b441",
         "prec": "f64",
-        "fetch_kib": 131125.1, "fetch_factor": 2.0,
+        "fetch_kib": 131121.7, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
         "source": "paper_2005_03246_amd/csrc/radix.hpp",
-        "sha256": "89bb683aac5023b9bba017b58e8116dda48f5847643db643706c79b5d3d9a0b8",
+        "sha256": "304ea30b51ac835c160e645c3f8729daa746bb6ddb31bb07918d70e969be742d",
         "prec": "f64",
-        "fetch_kib": 102447.1, "fetch_factor": 2.0,
-        "write_kib": 225703.3, "write_factor": 1.0,
+        "fetch_kib": 102452.6, "fetch_factor": 2.0,
+        "write_kib": 225440.3, "write_factor": 1.0,
     },
 }
 
