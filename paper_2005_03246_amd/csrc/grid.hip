@@ -295,9 +295,26 @@ __device__ __forceinline__ void bin_chunk(BinAcc<T> *bins, uint64_t *mask, bool 
     const int rank = (int)__popcll(peers & lt);
     if constexpr (!kPay)
         val = T(1);
-    for (int r = 0; __ballot(v && rank >= r) != 0ull; ++r) {
-        if (v && rank == r)
-            bins[c].add(val);
+    if constexpr (std::is_same<T, float>::value) {
+        // compensated bins: read-modify-write, one round after the other
+        for (int r = 0; __ballot(v && rank >= r) != 0ull; ++r) {
+            if (v && rank == r)
+                bins[c].add(val);
+            wave_lds_fence();
+        }
+    } else {
+        // one lane per cell in each round, so the LDS atomic adds never
+        // collide and each equals the plain add; they are issued round after
+        // round without waiting for one another
+        for (int r = 0; __ballot(v && rank >= r) != 0ull; ++r) {
+            if (v && rank == r) {
+                if constexpr (std::is_same<T, double>::value)
+                    atomicAdd(&bins[c].v, val);
+                else
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&bins[c].v),
+                              (unsigned long long)val);
+            }
+        }
         wave_lds_fence();
     }
 }
