@@ -187,8 +187,9 @@ def secondary():
     x3 = torch.from_numpy(datagen.config3()).cuda()
     n3 = x3.shape[1]
     ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
-    # merge levels of the last coordinate: per item, the 16-byte item and the
-    # 8-byte prefix value read and written once
+    # merge levels of the last coordinate: per item, the 8-byte compact item
+    # (last coordinate, id and side bits) and the 8-byte prefix value read
+    # and written once
     torch.cuda.synchronize()
     mecdf.profile_reset()
     mecdf.profile_enable(True)
@@ -199,7 +200,7 @@ def secondary():
     mc_ms, mc_n = kern.get("points_merge_count", (0.0, 0))
     merge = None
     if mc_n:
-        ab = 2 * n3 * (2 * 16 + 2 * 8)
+        ab = 2 * n3 * (2 * 8 + 2 * 8)
         gbs = ab / (mc_ms / mc_n * 1e-3) / 1e9
         merge = {"kernel": "points_merge_count", "launches": mc_n,
                  "avg_launch_ms": mc_ms / mc_n, "algorithmic_bytes_per_launch": ab,

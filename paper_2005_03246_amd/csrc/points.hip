@@ -316,83 +316,18 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
 }
 
 // Merge of aligned sorted blocks of size h into blocks of size 2h by the
-// depth-m key, one thread per item (its rank in the sibling block by binary
-// search).  kCount: the last coordinate; right-half active queries add the
-// left-half prefix P of active data weight ahead of them.  Otherwise: the
-// side bit of depth m is set and a copy is written for depth m+1.
-template <int NC, bool kW, bool kCount>
-__global__ __launch_bounds__(256) void k_merge_items(
-    const Item<NC> *__restrict__ in, const double *__restrict__ win,
-    Item<NC> *__restrict__ out, double *__restrict__ wout,
-    Item<NC> *__restrict__ copy, double *__restrict__ wcopy,
-    const void *__restrict__ Pin_raw, void *__restrict__ Pout_raw,
-    void *__restrict__ acc_raw, int64_t n, int64_t h, int m, uint32_t mask) {
-    using AccT = typename std::conditional<kW, double, int64_t>::type;
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n)
-        return;
-    int64_t s = (p / (2 * h)) * (2 * h);
-    int64_t ha = (n - s) < h ? (n - s) : h;
-    int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
-    Item<NC> it = in[p];
-    uint64_t key = item_key(it, m);
-    bool inA = (p - s) < ha;
-    int64_t pos, lo = 0;
-    if (inA) {
-        // number of B items with key < this key
-        int64_t hi = hb;
-        const Item<NC> *B = in + s + ha;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (item_key(B[mid], m) < key)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        pos = p + lo;
-    } else {
-        // number of A items with key <= this key
-        int64_t hi = ha;
-        const Item<NC> *A = in + s;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (item_key(A[mid], m) <= key)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        pos = s + (p - s - ha) + lo;
-    }
-    if constexpr (kCount) {
-        // P: inclusive prefix of active data weight within each sorted block
-        const AccT *Pin = reinterpret_cast<const AccT *>(Pin_raw);
-        AccT other = AccT(0);
-        if (lo > 0)
-            other = Pin[(inA ? s + ha : s) + lo - 1];
-        if (!inA && other != AccT(0) && active_query(it.idt, mask))
-            reinterpret_cast<AccT *>(acc_raw)[it.idt >> kIdShift] += other;
-        reinterpret_cast<AccT *>(Pout_raw)[pos] = Pin[p] + other;
-    } else {
-        const uint32_t bit = 1u << m;
-        it.idt = inA ? (it.idt & ~bit) : (it.idt | bit);
-        copy[pos] = it;
-        if constexpr (kW)
-            wcopy[pos] = win[p];
-    }
-    out[pos] = it;
-    if constexpr (kW)
-        wout[pos] = win[p];
-}
-
-// Merge-path version of k_merge_items for blocks of h >= kMpT / 2 items: each
-// workgroup produces kMpT consecutive outputs of one merged block.  Two
+// depth-m key (A = left block first on equal keys).  kCount (the last
+// coordinate): right-half active queries add the left-half prefix P of active
+// data weight ahead of them, and the merged prefix is written to Pout.
+// Otherwise the side bit of depth m is set and a copy is written for depth
+// m + 1 (with only the last coordinate when NCC == 1).  Each workgroup
+// produces kMpT consecutive outputs of one merged block (h >= kMpT / 2).  Two
 // binary searches on the merge diagonal give the A and B ranges feeding the
 // tile, which are staged in LDS (items, keys, weights, prefix values); each
-// thread finds its own diagonal in LDS and merges four outputs (A first on
-// equal keys, as in k_merge_items), recording where each output comes from;
-// the workgroup then writes the tile with coalesced stores.  An output's count
-// of items from the other side before it is its merge position, so the
-// results equal those of k_merge_items.
+// thread finds its own diagonal in LDS and merges four outputs, recording
+// where each output comes from; the workgroup then writes the tile with
+// coalesced stores.  An output's count of items from the other side before it
+// is its merge position.
 constexpr int kMpT = 1024;
 
 template <int NC>
@@ -404,11 +339,11 @@ __device__ __forceinline__ uint64_t item_key_sel(const Item<NC> &it, int m) {
     return ((uint64_t)c << 1) | (uint64_t)(it.idt & 1u);
 }
 
-template <int NC, bool kW, bool kCount>
+template <int NC, bool kW, bool kCount, int NCC = NC>
 __global__ __launch_bounds__(256) void k_merge_path(
     const Item<NC> *__restrict__ in, const double *__restrict__ win,
     Item<NC> *__restrict__ out, double *__restrict__ wout,
-    Item<NC> *__restrict__ copy, double *__restrict__ wcopy,
+    Item<NCC> *__restrict__ copy, double *__restrict__ wcopy,
     const void *__restrict__ Pin_raw, void *__restrict__ Pout_raw,
     void *__restrict__ acc_raw, int64_t n, int64_t h, int m, uint32_t mask) {
     using AccT = typename std::conditional<kW, double, int64_t>::type;
@@ -538,7 +473,15 @@ __global__ __launch_bounds__(256) void k_merge_path(
             reinterpret_cast<AccT *>(Pout_raw)[o] = sP[src] + other;
         } else {
             it.idt = src < na ? (it.idt & ~bit) : (it.idt | bit);
-            copy[o] = it;
+            if constexpr (NCC == NC) {
+                copy[o] = it;
+            } else {
+                static_assert(NCC == 1, "compact copies keep the last coordinate");
+                Item<1> c1;
+                c1.c[0] = it.c[NC - 1];
+                c1.idt = it.idt;
+                copy[o] = c1;
+            }
             if constexpr (kW)
                 wcopy[o] = sW[src];
         }
@@ -821,10 +764,18 @@ template <int NC, bool kW> struct Dnc {
         return MECDF_OK;
     }
 
+    // The last depth works on compact items (its coordinate and the id/side
+    // word) when NC > 1: SL / TL with the weights of SW / TW at that depth.
+    Item<1> *SL = nullptr, *TL = nullptr;
+
     // solves depth `depth` inside aligned blocks of size H of S[depth]
     int solve(int depth, int64_t H) {
         const uint32_t mask = side_mask(depth);
         const bool last = depth == d - 1;
+        if (last && NC > 1)
+            return solve_last(depth, H);
+        static_assert(2 * kBlockT >= kMpT, "every merge uses the merge-path kernel");
+        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
         {
             ProfScope prof("points_block_brute", s);
             hipLaunchKernelGGL((k_block_brute<NC, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
@@ -832,42 +783,58 @@ template <int NC, bool kW> struct Dnc {
                                last ? (void *)P : nullptr, n, depth, mask);
         }
         MECDF_LAUNCH_CHECK();
-        const unsigned nb = (unsigned)ceil_div(n, 256);
-        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
         for (int64_t h = kBlockT; h < H; h *= 2) {
-            // merged blocks of 2h >= kMpT items: the merge-path kernel
-            const bool path = 2 * h >= kMpT;
             if (last) {
                 ProfScope prof("points_merge_count", s);
-                if (path)
-                    hipLaunchKernelGGL((k_merge_path<NC, kW, true>), dim3(nbp), dim3(256), 0, s,
-                                       S[depth], SW[depth], T[depth], TW[depth], nullptr,
-                                       nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
-                                       depth, mask);
-                else
-                    hipLaunchKernelGGL((k_merge_items<NC, kW, true>), dim3(nb), dim3(256), 0, s,
-                                       S[depth], SW[depth], T[depth], TW[depth], nullptr,
-                                       nullptr, (const void *)P, (void *)P2, (void *)acc, n, h,
-                                       depth, mask);
+                hipLaunchKernelGGL((k_merge_path<NC, kW, true>), dim3(nbp), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth],
+                                   (Item<NC> *)nullptr, nullptr, (const void *)P, (void *)P2,
+                                   (void *)acc, n, h, depth, mask);
                 std::swap(P, P2);
+            } else if (depth + 1 == d - 1 && NC > 1) {
+                ProfScope prof("points_merge", s);
+                hipLaunchKernelGGL((k_merge_path<NC, kW, false, 1>), dim3(nbp), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], SL, SW[depth + 1],
+                                   nullptr, nullptr, nullptr, n, h, depth, mask);
             } else {
                 ProfScope prof("points_merge", s);
-                if (path)
-                    hipLaunchKernelGGL((k_merge_path<NC, kW, false>), dim3(nbp), dim3(256), 0, s,
-                                       S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
-                                       SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
-                                       mask);
-                else
-                    hipLaunchKernelGGL((k_merge_items<NC, kW, false>), dim3(nb), dim3(256), 0, s,
-                                       S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
-                                       SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
-                                       mask);
+                hipLaunchKernelGGL((k_merge_path<NC, kW, false>), dim3(nbp), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
+                                   SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
+                                   mask);
             }
             MECDF_LAUNCH_CHECK();
             std::swap(S[depth], T[depth]);
             std::swap(SW[depth], TW[depth]);
             if (!last)
                 MECDF_TRY(solve(depth + 1, 2 * h));
+        }
+        return MECDF_OK;
+    }
+
+    // the last depth on compact items: coordinate index 1 of Item<1>, the
+    // side mask of the real depth
+    int solve_last(int depth, int64_t H) {
+        const uint32_t mask = side_mask(depth);
+        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
+        {
+            ProfScope prof("points_block_brute", s);
+            hipLaunchKernelGGL((k_block_brute<1, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
+                               dim3(256), 0, s, SL, SW[depth], (void *)acc, (void *)P, n, 1,
+                               mask);
+        }
+        MECDF_LAUNCH_CHECK();
+        for (int64_t h = kBlockT; h < H; h *= 2) {
+            {
+                ProfScope prof("points_merge_count", s);
+                hipLaunchKernelGGL((k_merge_path<1, kW, true>), dim3(nbp), dim3(256), 0, s, SL,
+                                   SW[depth], TL, TW[depth], (Item<1> *)nullptr, nullptr,
+                                   (const void *)P, (void *)P2, (void *)acc, n, h, 1, mask);
+            }
+            MECDF_LAUNCH_CHECK();
+            std::swap(P, P2);
+            std::swap(SL, TL);
+            std::swap(SW[depth], TW[depth]);
         }
         return MECDF_OK;
     }
@@ -902,8 +869,13 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     if (kW)
         pl.add<double>((size_t)n2);
     for (int q = 0; q < depths; ++q) {
-        pl.add<Item<NC>>((size_t)n2);
-        pl.add<Item<NC>>((size_t)n2);
+        if (NC > 1 && q + 1 == d - 1) {  // compact items at the last depth
+            pl.add<Item<1>>((size_t)n2);
+            pl.add<Item<1>>((size_t)n2);
+        } else {
+            pl.add<Item<NC>>((size_t)n2);
+            pl.add<Item<NC>>((size_t)n2);
+        }
         if (kW) {
             pl.add<double>((size_t)n2);
             pl.add<double>((size_t)n2);
@@ -939,8 +911,14 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     dnc.d = d;
     dnc.s = s;
     for (int q = 0; q < depths; ++q) {
-        dnc.S[q + 1] = a.take<Item<NC>>((size_t)n2);
-        dnc.T[q + 1] = a.take<Item<NC>>((size_t)n2);
+        const bool compact = NC > 1 && q + 1 == d - 1;
+        if (compact) {
+            dnc.SL = a.take<Item<1>>((size_t)n2);
+            dnc.TL = a.take<Item<1>>((size_t)n2);
+        } else {
+            dnc.S[q + 1] = a.take<Item<NC>>((size_t)n2);
+            dnc.T[q + 1] = a.take<Item<NC>>((size_t)n2);
+        }
         dnc.SW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
         dnc.TW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
     }
