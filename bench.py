@@ -34,9 +34,9 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "da9da8e53cae686e63f4284498da187e09817cbe6653564273bec6701137b441",
+        "sha256": "9673db4abf69fda83e5195a46cb348e47f042b67eccdc93de89d20f3b245a834",
         "prec": "f64",
-        "fetch_kib": 131121.7, "fetch_factor": 2.0,
+        "fetch_kib": 131121.0, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
@@ -44,7 +44,7 @@ TRAFFIC = {
         "sha256": "304ea30b51ac835c160e645c3f8729daa746bb6ddb31bb07918d70e969be742d",
         "prec": "f64",
         "fetch_kib": 102452.6, "fetch_factor": 2.0,
-        "write_kib": 225440.3, "write_factor": 1.0,
+        "write_kib": 225432.5, "write_factor": 1.0,
     },
 }
 
