@@ -187,8 +187,9 @@ def secondary():
     x3 = torch.from_numpy(datagen.config3()).cuda()
     n3 = x3.shape[1]
     ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
-    # merge levels of the last coordinate: per item, the 8-byte compact item
-    # (last coordinate, id and side bits) and the 8-byte prefix value read
+    # merge levels of the last coordinate (all but the last level of each
+    # sub-problem): per item, the 8-byte compact item (last coordinate, id and
+    # side bits) and the 8-byte pair of 32-bit prefix and carried count, read
     # and written once
     torch.cuda.synchronize()
     mecdf.profile_reset()

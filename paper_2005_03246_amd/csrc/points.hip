@@ -20,17 +20,20 @@
 //   order      items sorted by (coordinate 0, type) with data before queries,
 //              so "i before q" encodes coordinate 0 (ties included).
 //   recursion  level-synchronous, one coordinate per depth m = 1..d-1:
-//              * pairs inside blocks of kBlockT items are counted by brute
-//                force in LDS, which also sorts each block by coordinate m;
-//              * then sorted blocks of size h = kBlockT, 2 kBlockT, ... are
-//                merged pairwise by coordinate m.  Below the last coordinate
-//                each merged block becomes a sub-problem of depth m+1, with a
-//                bit recording whether the item came from the left or right
-//                half; at the last coordinate the merge itself counts, for
-//                every query of the right half, the weight of the left-half
-//                data that precede it (a prefix sum carried over the left
-//                half).  A pair is counted at one depth only, by the items
-//                being data-left / query-right at every enclosing split.
+//              * below the last coordinate, pairs inside blocks of kBlockT
+//                items are counted by brute force in LDS, which also sorts
+//                each block by coordinate m; then sorted blocks of size
+//                h = kBlockT, 2 kBlockT, ... are merged pairwise by
+//                coordinate m, and each merged block becomes a sub-problem
+//                of depth m+1, with a bit recording whether the item came
+//                from the left or right half;
+//              * at the last coordinate every merge level counts, for each
+//                query of the right half, the weight of the left-half data at
+//                or below it (a prefix sum carried over the merged runs):
+//                levels up to kBlockT in LDS, the others one per launch; the
+//                count travels with the item and reaches the result once.
+//              A pair is counted at one depth only, by the items being
+//              data-left / query-right at every enclosing split.
 // Counts are exact int64; weighted sums accumulate in float64 in a fixed
 // order, so results are deterministic.
 #include <cstdlib>
@@ -193,13 +196,11 @@ inline uint32_t side_mask(int m) { return ((1u << (m - 1)) - 1u) << 1; }
 // m..d-1 are all <= its own (the active data are first compacted in LDS, in
 // block order, so each query scans only them).  The block is then sorted by
 // (coordinate m, type, position) with a bitonic network in LDS and written
-// back; at the last coordinate (P != nullptr) the inclusive prefix of active
-// data weight in the sorted block is written to P for the merges above.
+// back.  (The last coordinate has its own kernel, k_block_count.)
 template <int NC, bool kW>
 __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
                                                      double *__restrict__ W,
-                                                     void *__restrict__ acc_raw,
-                                                     void *__restrict__ P_raw, int64_t n,
+                                                     void *__restrict__ acc_raw, int64_t n,
                                                      int m, uint32_t mask) {
     using AccT = typename std::conditional<kW, double, int64_t>::type;
     constexpr int T = kBlockT;
@@ -209,7 +210,6 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
     __shared__ uint64_t sk[T];
     __shared__ uint32_t dIdx[T];
     __shared__ uint32_t wt[4];
-    __shared__ AccT wtA[4];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * T;
     const int cnt = (int)((n - base) < T ? (n - base) : T);
@@ -286,48 +286,28 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
             __syncthreads();
         }
     }
-    // write back in sorted order; prefix of active data for the merges
-    AccT pv[2];
+    // write back in sorted order
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         int r = 2 * tid + u;
-        pv[u] = AccT(0);
         if (r < cnt) {
             int li = (int)(sk[r] & 1023ull);
             S[base + r] = sI[li];
             if constexpr (kW)
                 W[base + r] = sW[li];
-            if (active_data(sI[li].idt, mask)) {
-                if constexpr (kW)
-                    pv[u] = sW[li];
-                else
-                    pv[u] = 1;
-            }
         }
-    }
-    if (P_raw) {
-        AccT ex = block_exclusive_scan256<AccT>(pv[0] + pv[1], wtA, nullptr);
-        AccT *P = reinterpret_cast<AccT *>(P_raw);
-        if (2 * tid < cnt)
-            P[base + 2 * tid] = ex + pv[0];
-        if (2 * tid + 1 < cnt)
-            P[base + 2 * tid + 1] = ex + pv[0] + pv[1];
     }
 }
 
 // Merge of aligned sorted blocks of size h into blocks of size 2h by the
-// depth-m key (A = left block first on equal keys).  kCount (the last
-// coordinate): right-half active queries add the left-half prefix P of active
-// data weight ahead of them, and the merged prefix is written to Pout.
-// Otherwise the side bit of depth m is set and a copy is written for depth
-// m + 1 (with only the last coordinate when NCC == 1).  Each workgroup
-// produces kMpT consecutive outputs of one merged block (h >= kMpT / 2).  Two
-// binary searches on the merge diagonal give the A and B ranges feeding the
-// tile, which are staged in LDS (items, keys, weights, prefix values); each
-// thread finds its own diagonal in LDS and merges four outputs, recording
-// where each output comes from; the workgroup then writes the tile with
-// coalesced stores.  An output's count of items from the other side before it
-// is its merge position.
+// depth-m key (A = left block first on equal keys).  The side bit of depth m
+// is set on every output and a copy is written for depth m + 1 (with only the
+// last coordinate when NCC == 1).  Each workgroup produces kMpT consecutive
+// outputs of one merged block (h >= kMpT / 2).  Two searches on the merge
+// diagonal give the A and B ranges feeding the tile, which are staged in LDS;
+// each thread finds its own diagonal in LDS and merges four outputs,
+// recording where each output comes from; the workgroup then writes the tile
+// with coalesced stores.
 constexpr int kMpT = 1024;
 
 template <int NC>
@@ -339,70 +319,105 @@ __device__ __forceinline__ uint64_t item_key_sel(const Item<NC> &it, int m) {
     return ((uint64_t)c << 1) | (uint64_t)(it.idt & 1u);
 }
 
-template <int NC, bool kW, bool kCount, int NCC = NC>
+// Wave 0 of a merge workgroup: lanes 0..31 search diagonal k0 and lanes
+// 32..63 diagonal k1 of the merge of A[0, ha) and B[0, hb), each for the
+// smallest i with A[i] ordered after B[k - i - 1] (32 probes per step); the
+// A index of each split goes to split[0] / split[1].
+template <int NC>
+__device__ __forceinline__ void merge_split(const Item<NC> *A, const Item<NC> *B,
+                                            int64_t ha, int64_t hb, int64_t k0, int64_t k1,
+                                            int m, int64_t *split) {
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5, l = lane & 31;
+    const int64_t k = half ? k1 : k0;
+    int64_t lo = k - hb > 0 ? k - hb : 0;
+    int64_t hi = k < ha ? k : ha;
+    const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+    for (;;) {
+        const int64_t span = hi - lo;
+        const bool go = span > 0;  // uniform over the half wave
+        int64_t step = (span + 31) / 32;
+        int64_t q = lo + (int64_t)(l + 1) * step - 1;
+        const bool probe = go && q < hi;
+        bool after = false;
+        if (probe)
+            after = item_key_sel(A[q], m) > item_key_sel(B[k - q - 1], m);
+        const uint64_t bal = __ballot(probe && after) & hmask;
+        const uint64_t any = __ballot(go) & hmask;
+        if (any == 0ull)
+            break;
+        if (go) {
+            if (bal) {
+                const int f = (__ffsll((unsigned long long)bal) - 1) & 31;
+                const int64_t qf = lo + (int64_t)(f + 1) * step - 1;
+                hi = qf;
+                lo = f == 0 ? lo : lo + (int64_t)f * step;
+            } else {
+                // every probe below hi said "before": past the last one
+                const int64_t nvalid = span / step < 32 ? span / step : 32;
+                lo += nvalid * step;
+            }
+        }
+    }
+    if (l == 0)
+        split[half] = lo;
+}
+
+// Each thread merges outputs 4t .. 4t+3 of the tile from the staged keys
+// (sk[0, na) the A range, sk[na, na + nb) the B range); src[q] receives the
+// staging slot of output q.
+__device__ __forceinline__ void merge_local(const uint32_t *sk, int na, int nb,
+                                            uint16_t *src) {
+    const int tot = na + nb;
+    const int dl = 4 * (int)threadIdx.x;
+    if (dl >= tot)
+        return;
+    const uint32_t *ska = sk;
+    const uint32_t *skb = sk + na;
+    int lo = dl - nb > 0 ? dl - nb : 0;
+    int hi = dl < na ? dl : na;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ska[mid] <= skb[dl - mid - 1])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int i = lo, j = dl - lo;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (dl + u >= tot)
+            break;
+        const bool takeA = (j >= nb) || (i < na && ska[i] <= skb[j]);
+        src[dl + u] = (uint16_t)(takeA ? i : na + j);
+        if (takeA)
+            ++i;
+        else
+            ++j;
+    }
+}
+
+template <int NC, bool kW, int NCC = NC>
 __global__ __launch_bounds__(256) void k_merge_path(
     const Item<NC> *__restrict__ in, const double *__restrict__ win,
     Item<NC> *__restrict__ out, double *__restrict__ wout,
-    Item<NCC> *__restrict__ copy, double *__restrict__ wcopy,
-    const void *__restrict__ Pin_raw, void *__restrict__ Pout_raw,
-    void *__restrict__ acc_raw, int64_t n, int64_t h, int m, uint32_t mask) {
-    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    Item<NCC> *__restrict__ copy, double *__restrict__ wcopy, int64_t n, int64_t h,
+    int m) {
     constexpr int kWn = kW ? kMpT : 1;
-    constexpr int kCn = kCount ? kMpT : 1;
     __shared__ Item<NC> sI[kMpT];     // A range, then B range
     __shared__ uint32_t sk[kMpT];     // their keys (ranks < 2^31)
     __shared__ double sW[kWn];        // their weights
-    __shared__ AccT sP[kCn];          // their prefix values
     __shared__ uint16_t sSrc[kMpT];   // per output: source slot in sI
     __shared__ int64_t sspl[2];
-    __shared__ AccT sPrev[2];         // prefix just before the A and the B range
     const int tid = threadIdx.x;
-    const AccT *Pin = reinterpret_cast<const AccT *>(Pin_raw);
     const int64_t o0 = (int64_t)blockIdx.x * kMpT;
     const int64_t s = (o0 / (2 * h)) * (2 * h);
     const int64_t ha = (n - s) < h ? (n - s) : h;
     const int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
-    const Item<NC> *A = in + s;
-    const Item<NC> *B = A + ha;
     const int64_t k0 = o0 - s;
     const int64_t k1 = k0 + kMpT < ha + hb ? k0 + kMpT : ha + hb;
-    if (tid < 64) {
-        // wave 0: lanes 0..31 search diagonal k0, lanes 32..63 diagonal k1,
-        // for the smallest i with A[i] after B[k-i-1] (32 probes per step)
-        const int half = tid >> 5, l = tid & 31;
-        const int64_t k = half ? k1 : k0;
-        int64_t lo = k - hb > 0 ? k - hb : 0;
-        int64_t hi = k < ha ? k : ha;
-        const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
-        for (;;) {
-            const int64_t span = hi - lo;
-            const bool go = span > 0;  // uniform over the half wave
-            int64_t step = (span + 31) / 32;
-            int64_t q = lo + (int64_t)(l + 1) * step - 1;
-            const bool probe = go && q < hi;
-            bool after = false;
-            if (probe)
-                after = item_key_sel(A[q], m) > item_key_sel(B[k - q - 1], m);
-            const uint64_t bal = __ballot(probe && after) & hmask;
-            const uint64_t any = __ballot(go) & hmask;
-            if (any == 0ull)
-                break;
-            if (go) {
-                if (bal) {
-                    const int f = (__ffsll((unsigned long long)bal) - 1) & 31;
-                    const int64_t qf = lo + (int64_t)(f + 1) * step - 1;
-                    hi = qf;
-                    lo = f == 0 ? lo : lo + (int64_t)f * step;
-                } else {
-                    // every probe below hi said "before": past the last one
-                    const int64_t nvalid = span / step < 32 ? span / step : 32;
-                    lo += nvalid * step;
-                }
-            }
-        }
-        if (l == 0)
-            sspl[half] = lo;
-    }
+    if (tid < 64)
+        merge_split<NC>(in + s, in + s + ha, ha, hb, k0, k1, m, sspl);
     __syncthreads();
     const int64_t ia0 = sspl[0], ia1 = sspl[1];
     const int64_t jb0 = k0 - ia0, jb1 = k1 - ia1;
@@ -415,79 +430,214 @@ __global__ __launch_bounds__(256) void k_merge_path(
         sk[t] = (uint32_t)item_key_sel(it, m);
         if constexpr (kW)
             sW[t] = win[g];
-        if constexpr (kCount)
-            sP[t] = Pin[g];
-    }
-    if constexpr (kCount) {
-        if (tid == 0)
-            sPrev[0] = ia0 > 0 ? Pin[s + ia0 - 1] : AccT(0);
-        if (tid == 1)
-            sPrev[1] = jb0 > 0 ? Pin[s + ha + jb0 - 1] : AccT(0);
     }
     __syncthreads();
-    const int dl = 4 * tid;
-    if (dl < tot) {
-        const uint32_t *ska = sk;
-        const uint32_t *skb = sk + na;
-        int lo = dl - nb > 0 ? dl - nb : 0;
-        int hi = dl < na ? dl : na;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ska[mid] <= skb[dl - mid - 1])
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        int i = lo, j = dl - lo;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (dl + u >= tot)
-                break;
-            const bool takeA = (j >= nb) || (i < na && ska[i] <= skb[j]);
-            sSrc[dl + u] = (uint16_t)(takeA ? i : na + j);
-            if (takeA)
-                ++i;
-            else
-                ++j;
-        }
-    }
+    merge_local(sk, na, nb, sSrc);
     __syncthreads();
     const uint32_t bit = 1u << m;
     for (int q = tid; q < tot; q += 256) {
         const int src = sSrc[q];
         const int64_t o = o0 + q;
         Item<NC> it = sI[src];
-        if constexpr (kCount) {
-            // the output at tile position q takes src; the items of the other
-            // side before it in the tile number q - (its index in its range)
-            AccT other;
-            if (src < na) {
-                const int jb = q - src;  // B items before it: jb0 + jb
-                other = jb > 0 ? sP[na + jb - 1] : sPrev[1];
-            } else {
-                const int ia = q - (src - na);  // A items before it: ia0 + ia
-                other = ia > 0 ? sP[ia - 1] : sPrev[0];
-                if (other != AccT(0) && active_query(it.idt, mask))
-                    reinterpret_cast<AccT *>(acc_raw)[it.idt >> kIdShift] += other;
-            }
-            reinterpret_cast<AccT *>(Pout_raw)[o] = sP[src] + other;
+        it.idt = src < na ? (it.idt & ~bit) : (it.idt | bit);
+        if constexpr (NCC == NC) {
+            copy[o] = it;
         } else {
-            it.idt = src < na ? (it.idt & ~bit) : (it.idt | bit);
-            if constexpr (NCC == NC) {
-                copy[o] = it;
-            } else {
-                static_assert(NCC == 1, "compact copies keep the last coordinate");
-                Item<1> c1;
-                c1.c[0] = it.c[NC - 1];
-                c1.idt = it.idt;
-                copy[o] = c1;
-            }
-            if constexpr (kW)
-                wcopy[o] = sW[src];
+            static_assert(NCC == 1, "compact copies keep the last coordinate");
+            Item<1> c1;
+            c1.c[0] = it.c[NC - 1];
+            c1.idt = it.idt;
+            copy[o] = c1;
         }
         out[o] = it;
-        if constexpr (kW)
+        if constexpr (kW) {
             wout[o] = sW[src];
+            wcopy[o] = sW[src];
+        }
+    }
+}
+
+// ---- the last coordinate --------------------------------------------------
+// Per item, in merged order: p, the prefix of active data weight up to and
+// including the item in its merged block, and c, the weight counted so far
+// for the item as an active query.  c travels with the item through the
+// merges and is added to the result once, at the last merge (ids are below
+// 2^26, so counts fit 32 bits).
+template <bool kW> struct PCnt;
+template <> struct PCnt<false> {
+    uint32_t p, c;
+};
+template <> struct PCnt<true> {
+    double p, c;
+};
+template <bool kW> using PVal = typename std::conditional<kW, double, uint32_t>::type;
+template <bool kW> using AccOf = typename std::conditional<kW, double, int64_t>::type;
+
+// The merge levels of runs of 1, 2, ..., kBlockT/2 items inside each block of
+// kBlockT items, in LDS.  Each item finds its rank in the other run by binary
+// search (left run first on equal keys); an active query of a right run adds
+// the left run's active data weight at or below its key, which is the left
+// run's prefix at that rank; every item's prefix grows by the other run's
+// prefix at its rank.  The sorted block is written back with its p and c
+// (kFlush: the block is the whole sub-problem, and c goes to the result).
+template <bool kW, bool kFlush>
+__global__ __launch_bounds__(256) void k_block_count(Item<1> *__restrict__ S,
+                                                     const double *__restrict__ W,
+                                                     PCnt<kW> *__restrict__ PC,
+                                                     AccOf<kW> *__restrict__ acc, int64_t n,
+                                                     uint32_t mask) {
+    using PV = PVal<kW>;
+    constexpr int T = kBlockT;
+    static_assert(T == 512, "two items per thread");
+    __shared__ Item<1> sI[T];
+    __shared__ uint32_t sk[2][T];   // keys in run order
+    __shared__ uint16_t sx[2][T];   // item slot of each run position
+    __shared__ PV sp[2][T];         // prefix of active data weight in the run
+    __shared__ PV sc[T];            // count per item slot
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * T;
+    const int cnt = (int)((n - base) < T ? (n - base) : T);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = tid + u * 256;
+        uint32_t key = 0xffffffffu;  // padding sorts last (keys are below 2^28)
+        PV w = PV(0);
+        if (t < cnt) {
+            const Item<1> it = S[base + t];
+            sI[t] = it;
+            key = (it.c[0] << 1) | (it.idt & 1u);
+            if (active_data(it.idt, mask)) {
+                if constexpr (kW)
+                    w = W[base + t];
+                else
+                    w = 1u;
+            }
+        }
+        sk[0][t] = key;
+        sx[0][t] = (uint16_t)t;
+        sp[0][t] = w;
+        sc[t] = PV(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int len = 1; len < T; len <<= 1) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int r = tid + u * 256;
+            const int b0 = r & ~(2 * len - 1);
+            const bool inA = (r & len) == 0;
+            const int ob = inA ? b0 + len : b0;
+            const uint32_t key = sk[cur][r];
+            // A items count B keys below theirs, B items A keys at or below
+            int lo = 0, hi = len;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const uint32_t k2 = sk[cur][ob + mid];
+                if (inA ? (k2 < key) : (k2 <= key))
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            const int slot = sx[cur][r];
+            const PV other = lo > 0 ? sp[cur][ob + lo - 1] : PV(0);
+            if (!inA && slot < cnt && active_query(sI[slot].idt, mask))
+                sc[slot] += other;
+            const int dst = b0 + (r & (len - 1)) + lo;
+            sk[cur ^ 1][dst] = key;
+            sx[cur ^ 1][dst] = (uint16_t)slot;
+            sp[cur ^ 1][dst] = sp[cur][r] + other;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int r = tid + u * 256;
+        if (r >= cnt)
+            continue;
+        if constexpr (kFlush) {
+            if (sc[r] != PV(0))
+                acc[sI[r].idt >> kIdShift] += (AccOf<kW>)sc[r];
+        } else {
+            const int slot = sx[cur][r];
+            S[base + r] = sI[slot];
+            PCnt<kW> v;
+            v.p = sp[cur][r];
+            v.c = sc[slot];
+            PC[base + r] = v;
+        }
+    }
+}
+
+// A merge level of the last coordinate above the LDS blocks (h >= kBlockT):
+// the merge of k_merge_path on compact items, carrying p and c.  An output
+// from one side has, before it in the merged block, the items of the other
+// side up to its tile position minus its index in its range; the other
+// side's prefix there is added to its p, and to its c when it is an active
+// query from the right side.  kFlush (the last level of the sub-problem):
+// nothing is written back and every nonzero c goes to the result.
+template <bool kW, bool kFlush>
+__global__ __launch_bounds__(256) void k_merge_count(
+    const Item<1> *__restrict__ in, const PCnt<kW> *__restrict__ pcin,
+    Item<1> *__restrict__ out, PCnt<kW> *__restrict__ pcout, AccOf<kW> *__restrict__ acc,
+    int64_t n, int64_t h, uint32_t mask) {
+    using PV = PVal<kW>;
+    __shared__ Item<1> sI[kMpT];      // A range, then B range
+    __shared__ uint32_t sk[kMpT];     // their keys
+    __shared__ PCnt<kW> sPC[kMpT];    // their p and c
+    __shared__ uint16_t sSrc[kMpT];   // per output: source slot
+    __shared__ int64_t sspl[2];
+    __shared__ PV sPrev[2];           // p just before the A and the B range
+    const int tid = threadIdx.x;
+    const int64_t o0 = (int64_t)blockIdx.x * kMpT;
+    const int64_t s = (o0 / (2 * h)) * (2 * h);
+    const int64_t ha = (n - s) < h ? (n - s) : h;
+    const int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
+    const int64_t k0 = o0 - s;
+    const int64_t k1 = k0 + kMpT < ha + hb ? k0 + kMpT : ha + hb;
+    if (tid < 64)
+        merge_split<1>(in + s, in + s + ha, ha, hb, k0, k1, 1, sspl);
+    __syncthreads();
+    const int64_t ia0 = sspl[0], ia1 = sspl[1];
+    const int64_t jb0 = k0 - ia0, jb1 = k1 - ia1;
+    const int na = (int)(ia1 - ia0), nb = (int)(jb1 - jb0);
+    const int tot = na + nb;
+    for (int t = tid; t < tot; t += 256) {
+        const int64_t g = t < na ? s + ia0 + t : s + ha + jb0 + (t - na);
+        const Item<1> it = in[g];
+        sI[t] = it;
+        sk[t] = (it.c[0] << 1) | (it.idt & 1u);
+        sPC[t] = pcin[g];
+    }
+    if (tid == 0)
+        sPrev[0] = ia0 > 0 ? pcin[s + ia0 - 1].p : PV(0);
+    if (tid == 1)
+        sPrev[1] = jb0 > 0 ? pcin[s + ha + jb0 - 1].p : PV(0);
+    __syncthreads();
+    merge_local(sk, na, nb, sSrc);
+    __syncthreads();
+    for (int q = tid; q < tot; q += 256) {
+        const int src = sSrc[q];
+        const Item<1> it = sI[src];
+        PCnt<kW> v = sPC[src];
+        PV other;
+        if (src < na) {
+            const int jb = q - src;  // B items before it: jb0 + jb
+            other = jb > 0 ? sPC[na + jb - 1].p : sPrev[1];
+        } else {
+            const int ia = q - (src - na);  // A items before it: ia0 + ia
+            other = ia > 0 ? sPC[ia - 1].p : sPrev[0];
+            if (active_query(it.idt, mask))
+                v.c += other;
+        }
+        if constexpr (kFlush) {
+            if (v.c != PV(0))
+                acc[it.idt >> kIdShift] += (AccOf<kW>)v.c;
+        } else {
+            v.p += other;
+            out[o0 + q] = it;
+            pcout[o0 + q] = v;
+        }
     }
 }
 
@@ -737,7 +887,7 @@ __global__ void k_zero_f64(double *a, int64_t n) {
 
 // ----------------------------------------------------------- host driver
 template <int NC, bool kW> struct Dnc {
-    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    using AccT = AccOf<kW>;
     int d;
     int64_t n;
     hipStream_t s;
@@ -747,7 +897,8 @@ template <int NC, bool kW> struct Dnc {
     double *TW[MECDF_MAX_DIM];
     AccT *acc;
     AccT *P;
-    AccT *P2;
+    PCnt<kW> *PCa;
+    PCnt<kW> *PCb;
     AccT *tagg;
     uint32_t *thead;
 
@@ -765,76 +916,85 @@ template <int NC, bool kW> struct Dnc {
     }
 
     // The last depth works on compact items (its coordinate and the id/side
-    // word) when NC > 1: SL / TL with the weights of SW / TW at that depth.
+    // word) when NC > 1: SL / TL with the weights of SW at that depth.
     Item<1> *SL = nullptr, *TL = nullptr;
 
     // solves depth `depth` inside aligned blocks of size H of S[depth]
     int solve(int depth, int64_t H) {
-        const uint32_t mask = side_mask(depth);
-        const bool last = depth == d - 1;
-        if (last && NC > 1)
+        if (depth == d - 1)
             return solve_last(depth, H);
+        const uint32_t mask = side_mask(depth);
         static_assert(2 * kBlockT >= kMpT, "every merge uses the merge-path kernel");
         const unsigned nbp = (unsigned)ceil_div(n, kMpT);
         {
             ProfScope prof("points_block_brute", s);
             hipLaunchKernelGGL((k_block_brute<NC, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
-                               dim3(256), 0, s, S[depth], SW[depth], (void *)acc,
-                               last ? (void *)P : nullptr, n, depth, mask);
-        }
-        MECDF_LAUNCH_CHECK();
-        for (int64_t h = kBlockT; h < H; h *= 2) {
-            if (last) {
-                ProfScope prof("points_merge_count", s);
-                hipLaunchKernelGGL((k_merge_path<NC, kW, true>), dim3(nbp), dim3(256), 0, s,
-                                   S[depth], SW[depth], T[depth], TW[depth],
-                                   (Item<NC> *)nullptr, nullptr, (const void *)P, (void *)P2,
-                                   (void *)acc, n, h, depth, mask);
-                std::swap(P, P2);
-            } else if (depth + 1 == d - 1 && NC > 1) {
-                ProfScope prof("points_merge", s);
-                hipLaunchKernelGGL((k_merge_path<NC, kW, false, 1>), dim3(nbp), dim3(256), 0, s,
-                                   S[depth], SW[depth], T[depth], TW[depth], SL, SW[depth + 1],
-                                   nullptr, nullptr, nullptr, n, h, depth, mask);
-            } else {
-                ProfScope prof("points_merge", s);
-                hipLaunchKernelGGL((k_merge_path<NC, kW, false>), dim3(nbp), dim3(256), 0, s,
-                                   S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
-                                   SW[depth + 1], nullptr, nullptr, nullptr, n, h, depth,
-                                   mask);
-            }
-            MECDF_LAUNCH_CHECK();
-            std::swap(S[depth], T[depth]);
-            std::swap(SW[depth], TW[depth]);
-            if (!last)
-                MECDF_TRY(solve(depth + 1, 2 * h));
-        }
-        return MECDF_OK;
-    }
-
-    // the last depth on compact items: coordinate index 1 of Item<1>, the
-    // side mask of the real depth
-    int solve_last(int depth, int64_t H) {
-        const uint32_t mask = side_mask(depth);
-        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
-        {
-            ProfScope prof("points_block_brute", s);
-            hipLaunchKernelGGL((k_block_brute<1, kW>), dim3((unsigned)ceil_div(n, kBlockT)),
-                               dim3(256), 0, s, SL, SW[depth], (void *)acc, (void *)P, n, 1,
+                               dim3(256), 0, s, S[depth], SW[depth], (void *)acc, n, depth,
                                mask);
         }
         MECDF_LAUNCH_CHECK();
         for (int64_t h = kBlockT; h < H; h *= 2) {
-            {
-                ProfScope prof("points_merge_count", s);
-                hipLaunchKernelGGL((k_merge_path<1, kW, true>), dim3(nbp), dim3(256), 0, s, SL,
-                                   SW[depth], TL, TW[depth], (Item<1> *)nullptr, nullptr,
-                                   (const void *)P, (void *)P2, (void *)acc, n, h, 1, mask);
+            if (depth + 1 == d - 1 && NC > 1) {
+                ProfScope prof("points_merge", s);
+                hipLaunchKernelGGL((k_merge_path<NC, kW, 1>), dim3(nbp), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], SL, SW[depth + 1],
+                                   n, h, depth);
+            } else {
+                ProfScope prof("points_merge", s);
+                hipLaunchKernelGGL((k_merge_path<NC, kW>), dim3(nbp), dim3(256), 0, s,
+                                   S[depth], SW[depth], T[depth], TW[depth], S[depth + 1],
+                                   SW[depth + 1], n, h, depth);
             }
             MECDF_LAUNCH_CHECK();
-            std::swap(P, P2);
-            std::swap(SL, TL);
+            std::swap(S[depth], T[depth]);
             std::swap(SW[depth], TW[depth]);
+            MECDF_TRY(solve(depth + 1, 2 * h));
+        }
+        return MECDF_OK;
+    }
+
+    // the last depth on Item<1> (the compact items, or the items themselves
+    // when NC == 1): LDS merges up to kBlockT, then one merge level per launch;
+    // the counts reach the result at the last level
+    int solve_last(int depth, int64_t H) {
+        const uint32_t mask = side_mask(depth);
+        Item<1> **L, **Lt;
+        if constexpr (NC > 1) {
+            L = &SL;
+            Lt = &TL;
+        } else {
+            L = &S[depth];
+            Lt = &T[depth];
+        }
+        const unsigned nbb = (unsigned)ceil_div(n, kBlockT);
+        const unsigned nbp = (unsigned)ceil_div(n, kMpT);
+        if (H <= kBlockT) {
+            ProfScope prof("points_block_count", s);
+            hipLaunchKernelGGL((k_block_count<kW, true>), dim3(nbb), dim3(256), 0, s, *L,
+                               SW[depth], PCa, acc, n, mask);
+            MECDF_LAUNCH_CHECK();
+            return MECDF_OK;
+        }
+        {
+            ProfScope prof("points_block_count", s);
+            hipLaunchKernelGGL((k_block_count<kW, false>), dim3(nbb), dim3(256), 0, s, *L,
+                               SW[depth], PCa, acc, n, mask);
+        }
+        MECDF_LAUNCH_CHECK();
+        for (int64_t h = kBlockT; h < H; h *= 2) {
+            if (2 * h >= H) {
+                ProfScope prof("points_merge_flush", s);
+                hipLaunchKernelGGL((k_merge_count<kW, true>), dim3(nbp), dim3(256), 0, s, *L,
+                                   PCa, (Item<1> *)nullptr, (PCnt<kW> *)nullptr, acc, n, h,
+                                   mask);
+            } else {
+                ProfScope prof("points_merge_count", s);
+                hipLaunchKernelGGL((k_merge_count<kW, false>), dim3(nbp), dim3(256), 0, s, *L,
+                                   PCa, *Lt, PCb, acc, n, h, mask);
+                std::swap(*L, *Lt);
+                std::swap(PCa, PCb);
+            }
+            MECDF_LAUNCH_CHECK();
         }
         return MECDF_OK;
     }
@@ -843,7 +1003,7 @@ template <int NC, bool kW> struct Dnc {
 template <int NC, bool kW, typename YT, typename OutT>
 static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
                         int survival, hipStream_t s) {
-    using AccT = typename std::conditional<kW, double, int64_t>::type;
+    using AccT = AccOf<kW>;
     const int64_t n2 = 2 * N;
     const int depths = d > 1 ? d - 1 : 1;
     ArenaPlan pl;
@@ -883,7 +1043,8 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     }
     pl.add<AccT>((size_t)N);               // acc
     pl.add<AccT>((size_t)n2);              // P
-    pl.add<AccT>((size_t)n2);              // P2
+    pl.add<PCnt<kW>>((size_t)n2);          // p and c at the last depth, x2
+    pl.add<PCnt<kW>>((size_t)n2);
     pl.add<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
     pl.add<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
     radix_plan(pl, n2);
@@ -924,7 +1085,8 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     }
     dnc.acc = a.take<AccT>((size_t)N);
     dnc.P = a.take<AccT>((size_t)n2);
-    dnc.P2 = a.take<AccT>((size_t)n2);
+    dnc.PCa = a.take<PCnt<kW>>((size_t)n2);
+    dnc.PCb = a.take<PCnt<kW>>((size_t)n2);
     dnc.tagg = a.take<AccT>((size_t)ceil_div(n2, kSegTile) + 1);
     dnc.thead = a.take<uint32_t>((size_t)ceil_div(n2, kSegTile) + 1);
     RadixScratch rs = radix_take(a, n2);
