@@ -76,10 +76,13 @@ static __global__ __launch_bounds__(256) void k_off_chunks(const uint32_t *__res
 // Per digit: exclusive scan of the chunk sums (in place), and the digit
 // bases B[d] = number of keys with a smaller digit.  One block of 512 threads;
 // loads are issued 16 at a time so that they overlap.
+template <typename T, int kW>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *wtot /*[kW]*/, T *total);
+
 static __global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ S,
                                                   int64_t nch, int R,
                                                   uint32_t *__restrict__ B) {
-    __shared__ uint32_t tot[kRadixMaxDigits];
+    __shared__ uint32_t wt[8];
     const int d = threadIdx.x;
     uint32_t run = 0;
     if (d < R) {
@@ -96,19 +99,9 @@ static __global__ __launch_bounds__(512) void k_off_scan(uint32_t *__restrict__ 
             }
         }
     }
-    tot[d] = d < R ? run : 0u;
-    __syncthreads();
-    if (d == 0) {
-        uint32_t acc = 0;
-        for (int q = 0; q < R; ++q) {
-            uint32_t v = tot[q];
-            tot[q] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
+    const uint32_t base = block_exclusive_scan<uint32_t, 8>(d < R ? run : 0u, wt, nullptr);
     if (d < R)
-        B[d] = tot[d];
+        B[d] = base;
 }
 
 // H[t*R + d] <- offset of digit d in tile t (in place)
