@@ -395,23 +395,55 @@ __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb
     }
 }
 
+// The 256 thread maps sit in LDS field by field (element f of thread t at
+// f * 256 + t), so that a wavefront's accesses to one field are consecutive.
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ void aff_put(Aff<T, CH, NSD> *buf, int t,
+                                        const Aff<T, CH, NSD> &a) {
+    T *q = reinterpret_cast<T *>(buf);
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        q[b * 256 + t] = a.m[b];
+#pragma unroll
+        for (int s = 0; s < NSD; ++s)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                q[(kKB + (b * NSD + s) * CH + c) * 256 + t] = a.l[b][s][c];
+    }
+}
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ Aff<T, CH, NSD> aff_get(const Aff<T, CH, NSD> *buf, int t) {
+    const T *q = reinterpret_cast<const T *>(buf);
+    Aff<T, CH, NSD> a;
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        a.m[b] = q[b * 256 + t];
+#pragma unroll
+        for (int s = 0; s < NSD; ++s)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                a.l[b][s][c] = q[(kKB + (b * NSD + s) * CH + c) * 256 + t];
+    }
+    return a;
+}
+
 // Inclusive tree scan of the 256 thread maps in LDS: forward (dir = 0, thread
 // t composes threads 0..t) or backward (dir = 1, threads 255..t).
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> block_aff_scan(Aff<T, CH, NSD> v,
                                                           Aff<T, CH, NSD> *buf, int dir) {
     const int t = threadIdx.x;
-    buf[t] = v;
+    aff_put(buf, t, v);
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
         Aff<T, CH, NSD> r = v;
         if (dir == 0 && t >= off)
-            r = aff_then(buf[t - off], v);
+            r = aff_then(aff_get(buf, t - off), v);
         if (dir == 1 && t + off < 256)
-            r = aff_then(buf[t + off], v);
+            r = aff_then(aff_get(buf, t + off), v);
         __syncthreads();
         v = r;
-        buf[t] = v;
+        aff_put(buf, t, v);
         __syncthreads();
     }
     return v;
@@ -436,77 +468,68 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
         agg[blockIdx.x].bwd = bi;
 }
 
-// Tile carries: one block of kCarryT threads, each owning a contiguous chunk
-// of tiles; tree scans over the chunk maps.
-constexpr int kCarryT = 256;
+// Tile carries in two steps.  k_kcarry_local: per group of 256 consecutive
+// tiles, the exclusive tree scans of the tile maps inside the group (forward:
+// tiles in ascending order; backward: descending), written over the tile
+// aggregates, and the group totals.  k_kcarry_final: per tile, the maps of
+// the groups before it (forward) or after it (backward) composed in order,
+// then the tile's own exclusive map: the state entering the tile.
 template <typename T, int CH, int NSD>
-__global__ __launch_bounds__(kCarryT) void k_kcarry(const KTileAgg<T, CH, NSD> *__restrict__ agg,
-                                                    int64_t nt,
-                                                    KCarry<T, CH, NSD> *__restrict__ car) {
-    __shared__ Aff<T, CH, NSD> buf[kCarryT];
+__global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__restrict__ agg,
+                                                      int64_t nt,
+                                                      KTileAgg<T, CH, NSD> *__restrict__ grp) {
+    __shared__ Aff<T, CH, NSD> buf[256];
     const int t = threadIdx.x;
-    const int64_t ch = ceil_div_dev(nt, kCarryT);
-    const int64_t t0 = (int64_t)t * ch;
-    const int64_t t1 = t0 + ch < nt ? t0 + ch : nt;
-    Aff<T, CH, NSD> v;
-    aff_identity(v);
-    for (int64_t q = t0; q < t1; ++q)
-        v = aff_then(v, agg[q].fwd);
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kCarryT; off <<= 1) {
-        Aff<T, CH, NSD> r = v;
-        if (t >= off)
-            r = aff_then(buf[t - off], v);
-        __syncthreads();
-        v = r;
-        buf[t] = v;
-        __syncthreads();
+    const int64_t q = (int64_t)blockIdx.x * 256 + t;
+    Aff<T, CH, NSD> fa, ba, id;
+    aff_identity(id);
+    fa = id;
+    ba = id;
+    if (q < nt) {
+        fa = agg[q].fwd;
+        ba = agg[q].bwd;
     }
-    Aff<T, CH, NSD> ex;
+    Aff<T, CH, NSD> fi = block_aff_scan<T, CH, NSD>(fa, buf, 0);
+    Aff<T, CH, NSD> fex = t == 0 ? id : aff_get(buf, t - 1);
+    if (t == 255)
+        grp[blockIdx.x].fwd = fi;
+    __syncthreads();
+    Aff<T, CH, NSD> bi = block_aff_scan<T, CH, NSD>(ba, buf, 1);
+    Aff<T, CH, NSD> bex = t == 255 ? id : aff_get(buf, t + 1);
     if (t == 0)
-        aff_identity(ex);
-    else
-        ex = buf[t - 1];
-    __syncthreads();
-    for (int64_t q = t0; q < t1; ++q) {
-#pragma unroll
-        for (int b = 0; b < kKB; ++b)
-#pragma unroll
-            for (int s = 0; s < NSD; ++s)
-#pragma unroll
-                for (int c = 0; c < CH; ++c)
-                    car[q].F[b][s][c] = ex.l[b][s][c];
-        ex = aff_then(ex, agg[q].fwd);
+        grp[blockIdx.x].bwd = bi;
+    if (q < nt) {
+        agg[q].fwd = fex;
+        agg[q].bwd = bex;
     }
-    aff_identity(v);
-    for (int64_t q = t1 - 1; q >= t0; --q)
-        v = aff_then(v, agg[q].bwd);
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kCarryT; off <<= 1) {
-        Aff<T, CH, NSD> r = v;
-        if (t + off < kCarryT)
-            r = aff_then(buf[t + off], v);
-        __syncthreads();
-        v = r;
-        buf[t] = v;
-        __syncthreads();
-    }
-    if (t == kCarryT - 1)
-        aff_identity(ex);
-    else
-        ex = buf[t + 1];
-    for (int64_t q = t1 - 1; q >= t0; --q) {
+}
+
+template <typename T, int CH, int NSD>
+__global__ __launch_bounds__(256) void k_kcarry_final(const KTileAgg<T, CH, NSD> *__restrict__ loc,
+                                                      int64_t nt,
+                                                      const KTileAgg<T, CH, NSD> *__restrict__ grp,
+                                                      KCarry<T, CH, NSD> *__restrict__ car) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nt)
+        return;
+    const int64_t g = q / 256, ng = ceil_div_dev(nt, (int64_t)256);
+    Aff<T, CH, NSD> cf, cb;
+    aff_identity(cf);
+    aff_identity(cb);
+    for (int64_t j = 0; j < g; ++j)
+        cf = aff_then(cf, grp[j].fwd);
+    for (int64_t j = ng - 1; j > g; --j)
+        cb = aff_then(cb, grp[j].bwd);
+    const Aff<T, CH, NSD> ef = loc[q].fwd, eb = loc[q].bwd;
 #pragma unroll
-        for (int b = 0; b < kKB; ++b)
+    for (int b = 0; b < kKB; ++b)
 #pragma unroll
-            for (int s = 0; s < NSD; ++s)
+        for (int s = 0; s < NSD; ++s)
 #pragma unroll
-                for (int c = 0; c < CH; ++c)
-                    car[q].B[b][s][c] = ex.l[b][s][c];
-        ex = aff_then(ex, agg[q].bwd);
-    }
+            for (int c = 0; c < CH; ++c) {
+                car[q].F[b][s][c] = ef.m[b] * cf.l[b][s][c] + ef.l[b][s][c];
+                car[q].B[b][s][c] = eb.m[b] * cb.l[b][s][c] + eb.l[b][s][c];
+            }
 }
 
 template <typename T, int CH, int NSD>
@@ -527,14 +550,14 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
     if (tid == 0)
         aff_identity(fex);
     else
-        fex = buf[tid - 1];
+        fex = aff_get(buf, tid - 1);
     __syncthreads();
     (void)block_aff_scan<T, CH, NSD>(bw, buf, 1);
     Aff<T, CH, NSD> bex;
     if (tid == 255)
         aff_identity(bex);
     else
-        bex = buf[tid + 1];
+        bex = aff_get(buf, tid + 1);
     const KCarry<T, CH, NSD> &cr = car[blockIdx.x];
     T recv[kKItems][kKB][CH];
 #pragma unroll
@@ -781,13 +804,17 @@ static void plan_state(ArenaPlan &pl, int64_t n) {
 
 template <typename T, int CH, int NSD>
 static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *agg_raw,
-                    void *car_raw, double *acc, hipStream_t s) {
+                    void *grp_raw, void *car_raw, double *acc, hipStream_t s) {
     auto *agg = reinterpret_cast<KTileAgg<T, CH, NSD> *>(agg_raw);
+    auto *grp = reinterpret_cast<KTileAgg<T, CH, NSD> *>(grp_raw);
     auto *car = reinterpret_cast<KCarry<T, CH, NSD> *>(car_raw);
     ProfScope prof("kde_scan", s);
+    const unsigned ng = (unsigned)ceil_div(nt, (int64_t)256);
     hipLaunchKernelGGL((k_ktile_agg<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb,
                        agg);
-    hipLaunchKernelGGL((k_kcarry<T, CH, NSD>), dim3(1), dim3(kCarryT), 0, s, agg, nt, car);
+    hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp);
+    hipLaunchKernelGGL((k_kcarry_final<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp,
+                       car);
     hipLaunchKernelGGL((k_kapply<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb, car,
                        acc);
     MECDF_LAUNCH_CHECK();
@@ -836,6 +863,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         pl.add<double>((size_t)nacc);
     pl.add<double>((size_t)n * kKB);
     pl.add<KTileAgg<T, CH, 4>>((size_t)nt + 1);
+    pl.add<KTileAgg<T, CH, 4>>((size_t)ceil_div(nt, (int64_t)256) + 1);  // tile groups
     pl.add<KCarry<T, CH, 4>>((size_t)nt + 1);
     pl.add<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
     radix_plan(pl, n);
@@ -862,6 +890,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         acc[q] = a.take<double>((size_t)nacc);
     double *terms = a.take<double>((size_t)n * kKB);
     void *agg = a.take<KTileAgg<T, CH, 4>>((size_t)nt + 1);
+    void *grp = a.take<KTileAgg<T, CH, 4>>((size_t)ceil_div(nt, (int64_t)256) + 1);
     void *car = a.take<KCarry<T, CH, 4>>((size_t)nt + 1);
     double *mpart = a.take<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
     RadixScratch rs = radix_take(a, n);
@@ -941,14 +970,14 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         if (d == 1) {
             KLevelArgs la{S0.x[0], 0, nullptr, nullptr, 1, nullptr, nullptr, 1,
                           S0.w0, S0.w1, S0.bits, n, (int64_t)1 << 40, 1};
-            MECDF_TRY((run_scan<T, CH, 1>(la, kb, nt, agg, car, ao, s)));
+            MECDF_TRY((run_scan<T, CH, 1>(la, kb, nt, agg, grp, car, ao, s)));
         } else {
             for (int q = L - 1; q >= 0; --q) {
                 const KState &M = So[q + 1];  // blocks of 2 hs[q] sorted by x2, bit 0 = side
                 if (d == 2) {
                     KLevelArgs la{M.x[1], 1, M.x[0], S0.x[0], hs[q], nullptr, nullptr, 1,
                                   M.w0, M.w1, M.bits, n, hs[q], 0};
-                    MECDF_TRY((run_scan<T, CH, 2>(la, kb, nt, agg, car, ao, s)));
+                    MECDF_TRY((run_scan<T, CH, 2>(la, kb, nt, agg, grp, car, ao, s)));
                 } else {
                     std::vector<KState> &I = Si[q];
                     double *ai = acc[2], *aj = acc[3];
@@ -959,7 +988,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                         const KState &Mi = I[r];
                         KLevelArgs la{Mi.x[2], 2, Mi.x[0], S0.x[0], hs[q], Mi.x[1], M.x[1], h2,
                                       Mi.w0, Mi.w1, Mi.bits, n, h2, 0};
-                        MECDF_TRY((run_scan<T, CH, 4>(la, kb, nt, agg, car, ai, s)));
+                        MECDF_TRY((run_scan<T, CH, 4>(la, kb, nt, agg, grp, car, ai, s)));
                         hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ai,
                                            I[r - 1].map, n, aj, 0);
                         std::swap(ai, aj);
