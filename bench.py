@@ -36,15 +36,15 @@ TRAFFIC = {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
         "sha256": "9673db4abf69fda83e5195a46cb348e47f042b67eccdc93de89d20f3b245a834",
         "prec": "f64",
-        "fetch_kib": 131121.0, "fetch_factor": 2.0,
+        "fetch_kib": 131117.0, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
         "source": "paper_2005_03246_amd/csrc/radix.hpp",
-        "sha256": "304ea30b51ac835c160e645c3f8729daa746bb6ddb31bb07918d70e969be742d",
+        "sha256": "f9754c33fa54a1abb6764c46b72814a7e1059147050d289374d33af86e60e554",
         "prec": "f64",
         "fetch_kib": 102452.6, "fetch_factor": 2.0,
-        "write_kib": 225432.5, "write_factor": 1.0,
+        "write_kib": 225443.9, "write_factor": 1.0,
     },
 }
 

@@ -535,7 +535,9 @@ __global__ __launch_bounds__(256) void k_kcarry_final(const KTileAgg<T, CH, NSD>
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
                                                 const KCarry<T, CH, NSD> *__restrict__ car,
-                                                double *__restrict__ acc) {
+                                                const double *hi,
+                                                const uint32_t *__restrict__ hmap,
+                                                double *lo) {
     __shared__ Aff<T, CH, NSD> buf[256];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)tid * kKItems;
@@ -608,17 +610,30 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
             add_side<T, CH, NSD>(st, sd[u], add);
         }
     }
+    // lo[p] = hi[hmap[p]] + this level's sums (hi == nullptr: zero; hmap ==
+    // nullptr: hi[p], which may be lo itself).  All loads come before the
+    // stores, which may overwrite them.
+    constexpr int W = kKB * CH;
+    double hv[kKItems][W];
 #pragma unroll
     for (int u = 0; u < kKItems; ++u) {
-        int64_t p = base + u;
+        const int64_t p = base + u;
+        const int64_t src = (hi && val[u]) ? (hmap ? (int64_t)hmap[p] : p) : -1;
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+            hv[u][i] = src >= 0 ? hi[src * W + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kKItems; ++u) {
+        const int64_t p = base + u;
         if (!val[u])
             continue;
-        double *a = acc + p * (kKB * CH);
+        double *a = lo + p * W;
 #pragma unroll
         for (int b = 0; b < kKB; ++b)
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                a[b * CH + c] += (double)recv[u][b][c];
+                a[b * CH + c] = hv[u][b * CH + c] + (double)recv[u][b][c];
     }
 }
 
@@ -804,7 +819,8 @@ static void plan_state(ArenaPlan &pl, int64_t n) {
 
 template <typename T, int CH, int NSD>
 static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *agg_raw,
-                    void *grp_raw, void *car_raw, double *acc, hipStream_t s) {
+                    void *grp_raw, void *car_raw, const double *hi, const uint32_t *hmap,
+                    double *lo, hipStream_t s) {
     auto *agg = reinterpret_cast<KTileAgg<T, CH, NSD> *>(agg_raw);
     auto *grp = reinterpret_cast<KTileAgg<T, CH, NSD> *>(grp_raw);
     auto *car = reinterpret_cast<KCarry<T, CH, NSD> *>(car_raw);
@@ -816,7 +832,7 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
     hipLaunchKernelGGL((k_kcarry_final<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp,
                        car);
     hipLaunchKernelGGL((k_kapply<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb, car,
-                       acc);
+                       hi, hmap, lo);
     MECDF_LAUNCH_CHECK();
     return MECDF_OK;
 }
@@ -966,18 +982,33 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
             kb.norm_loo[b] = 1.0 / ((double)(1 << d) * (double)(n - 1) * prod);
         }
         double *ao = acc[0], *an = acc[1];  // outer accumulator ping-pong
-        hipLaunchKernelGGL(k_kzero, dim3(nba), dim3(256), 0, s, ao, nacc);
+        // the levels of d = 1, and of d = 2 when there are any, write every
+        // accumulator record themselves
+        if (d == 3 || (d == 2 && L == 0))
+            hipLaunchKernelGGL(k_kzero, dim3(nba), dim3(256), 0, s, ao, nacc);
         if (d == 1) {
             KLevelArgs la{S0.x[0], 0, nullptr, nullptr, 1, nullptr, nullptr, 1,
                           S0.w0, S0.w1, S0.bits, n, (int64_t)1 << 40, 1};
-            MECDF_TRY((run_scan<T, CH, 1>(la, kb, nt, agg, grp, car, ao, s)));
+            MECDF_TRY((run_scan<T, CH, 1>(la, kb, nt, agg, grp, car, nullptr, nullptr, ao, s)));
         } else {
             for (int q = L - 1; q >= 0; --q) {
                 const KState &M = So[q + 1];  // blocks of 2 hs[q] sorted by x2, bit 0 = side
                 if (d == 2) {
+                    // the level above's accumulator comes in through its merge
+                    // map (none above the top level)
                     KLevelArgs la{M.x[1], 1, M.x[0], S0.x[0], hs[q], nullptr, nullptr, 1,
                                   M.w0, M.w1, M.bits, n, hs[q], 0};
-                    MECDF_TRY((run_scan<T, CH, 2>(la, kb, nt, agg, grp, car, ao, s)));
+                    const bool top = q == L - 1;
+                    MECDF_TRY((run_scan<T, CH, 2>(la, kb, nt, agg, grp, car, top ? nullptr : ao,
+                                                  top ? nullptr : So[q + 1].map, an, s)));
+                    std::swap(ao, an);
+                    if (q == 0) {
+                        ProfScope prof2("kde_down", s);
+                        hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ao,
+                                           So[0].map, n, an, 0);
+                        std::swap(ao, an);
+                    }
+                    continue;
                 } else {
                     std::vector<KState> &I = Si[q];
                     double *ai = acc[2], *aj = acc[3];
@@ -988,7 +1019,8 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                         const KState &Mi = I[r];
                         KLevelArgs la{Mi.x[2], 2, Mi.x[0], S0.x[0], hs[q], Mi.x[1], M.x[1], h2,
                                       Mi.w0, Mi.w1, Mi.bits, n, h2, 0};
-                        MECDF_TRY((run_scan<T, CH, 4>(la, kb, nt, agg, grp, car, ai, s)));
+                        MECDF_TRY((run_scan<T, CH, 4>(la, kb, nt, agg, grp, car, ai, nullptr,
+                                                      ai, s)));
                         hipLaunchKernelGGL((k_kacc_down<CH>), dim3(nba), dim3(256), 0, s, ai,
                                            I[r - 1].map, n, aj, 0);
                         std::swap(ai, aj);
