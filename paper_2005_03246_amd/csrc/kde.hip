@@ -275,7 +275,7 @@ __device__ __forceinline__ double split_point(const double *src, int64_t p, int6
 
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int64_t p,
-                                      T alpha[kKB], T beta[kKB], T f[kKB], int &sd,
+                                      T alpha[kKB], T *beta, T f[kKB], int &sd,
                                       T wv[CH]) {
     const int64_t seg = 2 * L.hin;
     const int64_t s = (p / seg) * seg;
@@ -298,7 +298,8 @@ __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int
     for (int b = 0; b < kKB; ++b) {
         double ihs = kb.ih[b][L.sc];
         alpha[b] = start ? T(0) : kexp<T>((T)(-(x - xp) * ihs));
-        beta[b] = last ? T(0) : kexp<T>((T)(-(xn - x) * ihs));
+        if (beta)
+            beta[b] = last ? T(0) : kexp<T>((T)(-(xn - x) * ihs));
         f[b] = L.oneside ? T(1) : kexp<T>((T)(-(da * kb.ih[b][0] + db * kb.ih[b][1])));
     }
 }
@@ -323,71 +324,63 @@ __device__ __forceinline__ T get_side(const T (&l)[NSD][CH], int sd, int c) {
     return r;
 }
 
+// The maps of the thread's items composed in order: forward (dir = 0, items
+// ascending) or backward (dir = 1, descending).
 template <typename T, int CH, int NSD>
-__device__ __forceinline__ void thread_affs(const T alpha[kKItems][kKB],
-                                            const T beta[kKItems][kKB],
-                                            const T f[kKItems][kKB], const int sd[kKItems],
-                                            const T wv[kKItems][CH], const bool val[kKItems],
-                                            Aff<T, CH, NSD> &fw, Aff<T, CH, NSD> &bw) {
-    aff_identity(fw);
-    aff_identity(bw);
+__device__ __forceinline__ Aff<T, CH, NSD> thread_aff(const T alpha[kKItems + 1][kKB],
+                                                      const T f[kKItems][kKB],
+                                                      const int sd[kKItems],
+                                                      const T wv[kKItems][CH],
+                                                      const bool val[kKItems], int dir) {
+    Aff<T, CH, NSD> a;
+    aff_identity(a);
 #pragma unroll
-    for (int u = 0; u < kKItems; ++u) {
+    for (int k = 0; k < kKItems; ++k) {
+        const int u = dir ? kKItems - 1 - k : k;
         if (!val[u])
             continue;
 #pragma unroll
         for (int b = 0; b < kKB; ++b) {
-            fw.m[b] *= alpha[u][b];
+            const T dec = dir ? alpha[u + 1][b] : alpha[u][b];
+            a.m[b] *= dec;
 #pragma unroll
             for (int s = 0; s < NSD; ++s)
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
-                    fw.l[b][s][c] *= alpha[u][b];
+                    a.l[b][s][c] *= dec;
             T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 add[c] = f[u][b] * wv[u][c];
-            add_side<T, CH, NSD>(fw.l[b], sd[u], add);
+            add_side<T, CH, NSD>(a.l[b], sd[u], add);
         }
     }
-#pragma unroll
-    for (int u = kKItems - 1; u >= 0; --u) {
-        if (!val[u])
-            continue;
-#pragma unroll
-        for (int b = 0; b < kKB; ++b) {
-            bw.m[b] *= beta[u][b];
-#pragma unroll
-            for (int s = 0; s < NSD; ++s)
-#pragma unroll
-                for (int c = 0; c < CH; ++c)
-                    bw.l[b][s][c] *= beta[u][b];
-            T add[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-                add[c] = f[u][b] * wv[u][c];
-            add_side<T, CH, NSD>(bw.l[b], sd[u], add);
-        }
-    }
+    return a;
 }
 
+// alpha[u] for the thread's items u; alpha[kKItems] is the last item's beta.
+// The beta of item u < kKItems - 1 is alpha[u + 1]: both are the decay across
+// the same pair of neighbours (0 at a segment boundary or past the end).
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb,
-                                           int64_t base, T alpha[kKItems][kKB],
-                                           T beta[kKItems][kKB], T f[kKItems][kKB],
-                                           int sd[kKItems], T wv[kKItems][CH],
-                                           bool val[kKItems]) {
+                                           int64_t base, T alpha[kKItems + 1][kKB],
+                                           T f[kKItems][kKB], int sd[kKItems],
+                                           T wv[kKItems][CH], bool val[kKItems]) {
+#pragma unroll
+    for (int b = 0; b < kKB; ++b)
+        alpha[kKItems][b] = T(0);
 #pragma unroll
     for (int u = 0; u < kKItems; ++u) {
         int64_t p = base + u;
         val[u] = p < L.n;
         if (val[u]) {
-            kitem<T, CH, NSD>(L, kb, p, alpha[u], beta[u], f[u], sd[u], wv[u]);
+            kitem<T, CH, NSD>(L, kb, p, alpha[u], u == kKItems - 1 ? alpha[kKItems] : nullptr,
+                              f[u], sd[u], wv[u]);
         } else {
             sd[u] = 0;
 #pragma unroll
             for (int b = 0; b < kKB; ++b)
-                alpha[u][b] = beta[u][b] = f[u][b] = T(0);
+                alpha[u][b] = f[u][b] = T(0);
 #pragma unroll
             for (int c = 0; c < CH; ++c)
                 wv[u][c] = T(0);
@@ -454,16 +447,16 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
                                                    KTileAgg<T, CH, NSD> *__restrict__ agg) {
     __shared__ Aff<T, CH, NSD> buf[256];
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)threadIdx.x * kKItems;
-    T alpha[kKItems][kKB], beta[kKItems][kKB], f[kKItems][kKB], wv[kKItems][CH];
+    T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
-    load_items<T, CH, NSD>(L, kb, base, alpha, beta, f, sd, wv, val);
-    Aff<T, CH, NSD> fw, bw;
-    thread_affs<T, CH, NSD>(alpha, beta, f, sd, wv, val, fw, bw);
-    Aff<T, CH, NSD> fi = block_aff_scan<T, CH, NSD>(fw, buf, 0);
+    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
+    Aff<T, CH, NSD> fi =
+        block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
     if (threadIdx.x == 255)
         agg[blockIdx.x].fwd = fi;
-    Aff<T, CH, NSD> bi = block_aff_scan<T, CH, NSD>(bw, buf, 1);
+    Aff<T, CH, NSD> bi =
+        block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
     if (threadIdx.x == 0)
         agg[blockIdx.x].bwd = bi;
 }
@@ -541,20 +534,18 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
     __shared__ Aff<T, CH, NSD> buf[256];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)tid * kKItems;
-    T alpha[kKItems][kKB], beta[kKItems][kKB], f[kKItems][kKB], wv[kKItems][CH];
+    T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
-    load_items<T, CH, NSD>(L, kb, base, alpha, beta, f, sd, wv, val);
-    Aff<T, CH, NSD> fw, bw;
-    thread_affs<T, CH, NSD>(alpha, beta, f, sd, wv, val, fw, bw);
-    (void)block_aff_scan<T, CH, NSD>(fw, buf, 0);
+    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
+    (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
     Aff<T, CH, NSD> fex;
     if (tid == 0)
         aff_identity(fex);
     else
         fex = aff_get(buf, tid - 1);
     __syncthreads();
-    (void)block_aff_scan<T, CH, NSD>(bw, buf, 1);
+    (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
     Aff<T, CH, NSD> bex;
     if (tid == 255)
         aff_identity(bex);
@@ -600,7 +591,7 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
             for (int s = 0; s < NSD; ++s)
 #pragma unroll
                 for (int c = 0; c < CH; ++c)
-                    st[s][c] *= beta[u][b];
+                    st[s][c] *= alpha[u + 1][b];
             T add[CH];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
