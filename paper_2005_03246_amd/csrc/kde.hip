@@ -464,13 +464,15 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
 // Tile carries in two steps.  k_kcarry_local: per group of 256 consecutive
 // tiles, the exclusive tree scans of the tile maps inside the group (forward:
 // tiles in ascending order; backward: descending), written over the tile
-// aggregates, and the group totals.  k_kcarry_final: per tile, the maps of
+// aggregates, and the group totals; with one group (car != null) it writes
+// the carries itself.  k_kcarry_final: per tile, the maps of
 // the groups before it (forward) or after it (backward) composed in order,
 // then the tile's own exclusive map: the state entering the tile.
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__restrict__ agg,
                                                       int64_t nt,
-                                                      KTileAgg<T, CH, NSD> *__restrict__ grp) {
+                                                      KTileAgg<T, CH, NSD> *__restrict__ grp,
+                                                      KCarry<T, CH, NSD> *__restrict__ car) {
     __shared__ Aff<T, CH, NSD> buf[256];
     const int t = threadIdx.x;
     const int64_t q = (int64_t)blockIdx.x * 256 + t;
@@ -491,7 +493,21 @@ __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__re
     Aff<T, CH, NSD> bex = t == 255 ? id : aff_get(buf, t + 1);
     if (t == 0)
         grp[blockIdx.x].bwd = bi;
-    if (q < nt) {
+    if (q >= nt)
+        return;
+    if (car) {
+        // a single group: the states entering the tiles are the exclusive
+        // maps applied to the zero state
+#pragma unroll
+        for (int b = 0; b < kKB; ++b)
+#pragma unroll
+            for (int s = 0; s < NSD; ++s)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    car[q].F[b][s][c] = fex.l[b][s][c];
+                    car[q].B[b][s][c] = bex.l[b][s][c];
+                }
+    } else {
         agg[q].fwd = fex;
         agg[q].bwd = bex;
     }
@@ -819,9 +835,15 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
     const unsigned ng = (unsigned)ceil_div(nt, (int64_t)256);
     hipLaunchKernelGGL((k_ktile_agg<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb,
                        agg);
-    hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp);
-    hipLaunchKernelGGL((k_kcarry_final<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp,
-                       car);
+    if (ng == 1) {
+        hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(1), dim3(256), 0, s, agg, nt, grp,
+                           car);
+    } else {
+        hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp,
+                           (KCarry<T, CH, NSD> *)nullptr);
+        hipLaunchKernelGGL((k_kcarry_final<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt,
+                           grp, car);
+    }
     hipLaunchKernelGGL((k_kapply<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb, car,
                        hi, hmap, lo);
     MECDF_LAUNCH_CHECK();
