@@ -290,10 +290,31 @@ def bandwidth_judge(train_count):
     }
 
 
-def cpu_baseline(x, y, nodes, target_s):
+def gpu_sample(xt, y, nodes, count=64):
+    """ECDF and ESF of the library at `count` seeded random grid nodes, float64
+    and compensated float32 weights (for the error report of the oracle leg)."""
+    import numpy as np
+    import torch
+
+    from paper_2005_03246_amd import mecdf
+
+    g = np.random.default_rng(7)
+    idx = np.stack([g.integers(0, M_NODES, size=count) for _ in range(3)], 1)
+    it = torch.from_numpy(idx).cuda()
+    out = {"idx": idx}
+    for prec, dt in (("f64", np.float64), ("f32c", np.float32)):
+        F, Fb = mecdf.ecdf_esf_grid(xt, nodes, torch.from_numpy(y.astype(dt)).cuda(), prec=prec)
+        out[prec] = tuple(A[it[:, 0], it[:, 1], it[:, 2]].double().cpu().numpy() for A in (F, Fb))
+        del F, Fb
+    return out
+
+
+def cpu_baseline(x, y, nodes, target_s, sample=None):
     """The brute-force oracle on a bounded sample of grid nodes (ECDF and ESF
     at each sampled node, full N), scaled to Gpoint-evals/s, on all host
-    cores and on one core."""
+    cores and on one core.  With `sample` (from gpu_sample) it also reports
+    the library's largest error at those nodes against the oracle, divided by
+    the same functional over |y| at the node."""
     import numpy as np
 
     import oracle
@@ -318,7 +339,7 @@ def cpu_baseline(x, y, nodes, target_s):
     t1 = run(4, 1)
     c1 = int(max(4, min(4096, 4 * (target_s / 20.0) / max(t1, 1e-3))))
     t1 = run(c1, 1)
-    return {
+    res = {
         "value": 2 * count / t / 1e9,
         "unit": "Gpoint-evals/s",
         "cores": cores,
@@ -328,6 +349,29 @@ def cpu_baseline(x, y, nodes, target_s):
         "single_core": {"value": 2 * c1 / t1 / 1e9, "sample_nodes": c1,
                         "seconds": t1},
     }
+    if sample is not None:
+        z = oracle.grid_points(nodes, sample["idx"])
+        fo, fa = oracle.ecdf(x, z, y)
+        go, ga = oracle.esf(x, z, y)
+        # the float32 path is judged on the float32-rounded weights it receives
+        y32 = y.astype(np.float32).astype(np.float64)
+        fo32, fa32 = oracle.ecdf(x, z, y32)
+        go32, ga32 = oracle.esf(x, z, y32)
+
+        def worst(got, want, scale):
+            err = np.abs(got - want)
+            if np.any((scale == 0) & (err != 0)):
+                return float("inf")
+            return float(np.max(np.where(scale > 0, err / np.where(scale > 0, scale, 1), 0)))
+
+        res["gpu_error_vs_oracle"] = {
+            "nodes": int(len(sample["idx"])),
+            "norm": "|library - oracle| / (same functional over |y|), per node",
+            "f64_max": max(worst(sample["f64"][0], fo, fa), worst(sample["f64"][1], go, ga)),
+            "f32c_max": max(worst(sample["f32c"][0], fo32, fa32),
+                            worst(sample["f32c"][1], go32, ga32)),
+        }
+    return res
 
 
 def main():
@@ -441,13 +485,14 @@ def main():
         "ms_per_step_profiled": ms_step_prof,
         "wall_s_timed": wall,
     }
+    del F, Fb
+    sample = None if args.no_cpu_baseline else gpu_sample(xt, y, nodes)
     if not args.no_secondary:
-        del F, Fb
         out["secondary"] = secondary()
     if not args.no_bandwidth:
         out["bandwidth"] = bandwidth_judge(args.bw_train)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds, sample)
     print(json.dumps(out), flush=True)
 
 
