@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the timings of the other workloads")
     ap.add_argument("--no-bandwidth", action="store_true",
-                    help="skip the learned-bandwidth judge")
+                    help="skip the learned-bandwidth evaluation against the grid search")
     ap.add_argument("--bw-train", type=int, default=2048,
                     help="training datasets of the bandwidth network")
     ap.add_argument("--secondary-only", action="store_true",
@@ -224,7 +224,7 @@ def secondary():
     return out
 
 
-def bandwidth_judge(train_count):
+def bandwidth_eval(train_count):
     """The learned bandwidth proposal against the plain 64-bandwidth grid
     search on the 512 mixture datasets (N log-uniform in 2^10..2^18, d in
     {1,2,3}): both return exact LCV scores over the same grid; the learned one
@@ -353,7 +353,7 @@ def cpu_baseline(x, y, nodes, target_s, sample=None):
         z = oracle.grid_points(nodes, sample["idx"])
         fo, fa = oracle.ecdf(x, z, y)
         go, ga = oracle.esf(x, z, y)
-        # the float32 path is judged on the float32-rounded weights it receives
+        # the float32 path is compared on the float32-rounded weights it receives
         y32 = y.astype(np.float32).astype(np.float64)
         fo32, fa32 = oracle.ecdf(x, z, y32)
         go32, ga32 = oracle.esf(x, z, y32)
@@ -490,7 +490,7 @@ def main():
     if not args.no_secondary:
         out["secondary"] = secondary()
     if not args.no_bandwidth:
-        out["bandwidth"] = bandwidth_judge(args.bw_train)
+        out["bandwidth"] = bandwidth_eval(args.bw_train)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds, sample)
     print(json.dumps(out), flush=True)
