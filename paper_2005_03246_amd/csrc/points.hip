@@ -1158,13 +1158,16 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
 }
 
 // ---- direct evaluation for small samples --------------------------------
-// eq. (ECDF) / (ESF) as written: every (query, point) pair.  64 queries per
-// block, one per lane; wave w of 16 takes the w-th sixteenth of the points, 64
-// at a time through its own LDS slice (broadcast reads), then the
-// partial results are combined in wave order.  Counts are exact; float64
+// eq. (ECDF) / (ESF) as written: every (query, point) pair.  16 queries per
+// block; the points are cut into 64 slices, and lane l of wave w takes query
+// l mod 16 over slice 4 w + l / 16, 16 points at a time through the wave's
+// LDS (each group of 16 lanes reads one address).  The 64 partial results of
+// a query are then combined in slice order.  Counts are exact; float64
 // weights are summed with Neumaier compensation and float32 weights with
 // Kahan compensation, in a fixed order.
 constexpr int kDirectWaves = 16;
+constexpr int kDirectQ = 16;                      // queries per block
+constexpr int kDirectSlices = kDirectWaves * 4;   // point slices per block
 
 template <typename P> struct DirectAcc;
 template <> struct DirectAcc<NoPayload> {
@@ -1200,53 +1203,75 @@ __global__ __launch_bounds__(kDirectWaves * 64) void k_points_direct(
     constexpr bool kW = !std::is_same<P, NoPayload>::value;
     __shared__ double sx[kDirectWaves][D][64];
     __shared__ typename std::conditional<kW, P, int>::type sy[kDirectWaves][64];
-    __shared__ __attribute__((aligned(16))) char part_raw[sizeof(DirectAcc<P>) * kDirectWaves * 64];
+    __shared__ __attribute__((aligned(16))) char
+        part_raw[sizeof(DirectAcc<P>) * kDirectSlices * kDirectQ];
     DirectAcc<P> *part = reinterpret_cast<DirectAcc<P> *>(part_raw);
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int qi = lane & (kDirectQ - 1);
+    const int sl = lane >> 4;                 // this lane's slice within the wave
+    const int g = w * 4 + sl;                 // slice index 0..63
+    const int64_t i = (int64_t)blockIdx.x * kDirectQ + qi;
     double q[D];
 #pragma unroll
     for (int k = 0; k < D; ++k)
         q[k] = i < n ? x[(int64_t)k * n + i] : 0.0;
-    // this wave's share of the points
-    const int64_t per = (n + kDirectWaves - 1) / kDirectWaves;
-    const int64_t j0 = (int64_t)w * per;
+    const int64_t per = (n + kDirectSlices - 1) / kDirectSlices;
+    const int64_t j0 = (int64_t)g * per < n ? (int64_t)g * per : n;
     const int64_t j1 = j0 + per < n ? j0 + per : n;
+    // the four slices of a wave have the same length except at the end
+    const int64_t len = j1 - j0;
     DirectAcc<P> acc;
-    for (int64_t t0 = j0; t0 < j1; t0 += 64) {
-        const int64_t j = t0 + lane;
-        if (j < j1) {
+    // the next 16 points of the slice are loaded while the current ones are
+    // compared
+    double nx[D];
+    typename std::conditional<kW, P, int>::type ny{};
+    auto load = [&](int64_t t0) {
+        const bool v = t0 + qi < len;
+        const int64_t j = j0 + t0 + qi;
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                sx[w][k][lane] = x[(int64_t)k * n + j];
-            if constexpr (kW)
-                sy[w][lane] = y[j];
-        }
+        for (int k = 0; k < D; ++k)
+            nx[k] = v ? x[(int64_t)k * n + j] : 0.0;
+        if constexpr (kW)
+            ny = v ? y[j] : P(0);
+    };
+    load(0);
+    for (int64_t t0 = 0; t0 < per; t0 += 16) {  // uniform over the wave
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            sx[w][k][lane] = nx[k];
+        if constexpr (kW)
+            sy[w][lane] = ny;
         wave_lds_fence();
-        const int cnt = j1 - t0 < 64 ? (int)(j1 - t0) : 64;
-        for (int t = 0; t < cnt; ++t) {
-            bool dom = true;
+        if (t0 + 16 < per)
+            load(t0 + 16);
+        const int64_t rem = len - t0;
+        const int cnt = rem <= 0 ? 0 : (rem < 16 ? (int)rem : 16);
+        const int b = sl * 16;
 #pragma unroll
-            for (int k = 0; k < D; ++k)
-                dom = dom && (survival ? (sx[w][k][t] > q[k]) : (sx[w][k][t] <= q[k]));
-            if (dom) {
-                if constexpr (kW)
-                    acc.add(sy[w][t]);
-                else
-                    acc.add(NoPayload{});
+        for (int t = 0; t < 16; ++t) {
+            if (t < cnt) {
+                bool dom = true;
+#pragma unroll
+                for (int k = 0; k < D; ++k)
+                    dom = dom && (survival ? (sx[w][k][b + t] > q[k]) : (sx[w][k][b + t] <= q[k]));
+                if (dom) {
+                    if constexpr (kW)
+                        acc.add(sy[w][b + t]);
+                    else
+                        acc.add(NoPayload{});
+                }
             }
         }
         wave_lds_fence();
     }
-    part[w * 64 + lane] = acc;
+    part[g * kDirectQ + qi] = acc;
     __syncthreads();
-    if (w != 0 || i >= n)
+    if (threadIdx.x >= kDirectQ || i >= n)
         return;
-    DirectAcc<P> r = part[lane];
-#pragma unroll
-    for (int q2 = 1; q2 < kDirectWaves; ++q2)
-        r.merge(part[q2 * 64 + lane]);
+    DirectAcc<P> r = part[qi];
+    for (int q2 = 1; q2 < kDirectSlices; ++q2)
+        r.merge(part[q2 * kDirectQ + qi]);
     if constexpr (kW) {
         if constexpr (std::is_same<P, double>::value)
             F[i] = (OutT)((r.s + r.c) / (double)n);
@@ -1260,7 +1285,7 @@ __global__ __launch_bounds__(kDirectWaves * 64) void k_points_direct(
 template <int D>
 static int points_direct_d(int64_t N, const double *x, const void *y, void *F, int survival,
                            int prec, hipStream_t s) {
-    const unsigned nb = (unsigned)ceil_div(N, 64);
+    const unsigned nb = (unsigned)ceil_div(N, kDirectQ);
     ProfScope prof("points_direct", s);
     if (y == nullptr)
         hipLaunchKernelGGL((k_points_direct<D, NoPayload, int64_t>), dim3(nb),
