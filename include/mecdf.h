@@ -243,8 +243,8 @@ int mecdf_mlp_train(int B, const float *feat, const float *target, float *params
  * isotropic bandwidths (hgrid, host).  The network proposes
  * log h = feat[12] + net(feat); the exact LOO likelihood score is evaluated
  * at the four grid bandwidths around the proposal (grid indices
- * round(j) - 1 .. round(j) + 2 for the proposal's fractional index j,
- * clamped to the grid).  With mode MECDF_BW_EXTEND the evaluated window is
+ * round(j) - 2 .. round(j) + 1 for the proposal's fractional index j, a
+ * window centred within half a step of j, clamped to the grid).  With mode MECDF_BW_EXTEND the evaluated window is
  * then extended by four grid points at a time towards the best score until
  * the best score is interior to it (or at the grid's end); with
  * MECDF_BW_WINDOW the four-point window is the answer.  Each dataset's

@@ -319,7 +319,8 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
         double lh = (double)hf[(size_t)i * 32 + 12] + (double)hp[i];
         double jf = std::isfinite(lh) ? (lh - l0) / dl : 0.0;
         jf = jf < -1e6 ? -1e6 : (jf > 1e6 ? 1e6 : jf);
-        int j0 = (int)std::lround(jf) - 1;
+        // the four grid points nearest the proposal: round(jf) - 2 .. round(jf) + 1
+        int j0 = (int)std::lround(jf) - 2;
         if (j0 > nhg - w)
             j0 = nhg - w;
         if (j0 < 0)
