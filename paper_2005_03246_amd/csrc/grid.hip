@@ -832,17 +832,26 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
             hipLaunchKernelGGL((k_line<T, P, kHeavyWaves>), dim3((unsigned)nblk),
                                dim3(kHeavyWaves * 64), lb_bytes, s, ks, ps, lbnd, lst, hcount,
                                g, F, Fbar, d == 1 ? 1 : 0, (double)N);
-        } else {
+        } else if (line_lds_bytes<4>(Cl) <= 160 * 1024) {
             lb_bytes = line_lds_bytes<4>(Cl);
-            if (lb_bytes > 160 * 1024) {
-                set_error("last grid axis too large for the line kernel");
-                return MECDF_EUNSUPPORTED;
-            }
             if (lb_bytes > 64 * 1024)
                 MECDF_TRY_HIP(hipFuncSetAttribute((const void *)k_line<T, P, 4>,
                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                                   (int)lb_bytes));
             hipLaunchKernelGGL((k_line<T, P, 4>), dim3((unsigned)nblk), dim3(256), lb_bytes,
+                               s, ks, ps, lbnd, lst, hcount, g, F, Fbar, d == 1 ? 1 : 0,
+                               (double)N);
+        } else {
+            // the longest last axes (up to 5119 cells): two wavefronts per line
+            lb_bytes = line_lds_bytes<2>(Cl);
+            if (lb_bytes > 160 * 1024) {
+                set_error("last grid axis too large for the line kernel");
+                return MECDF_EUNSUPPORTED;
+            }
+            MECDF_TRY_HIP(hipFuncSetAttribute((const void *)k_line<T, P, 2>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)lb_bytes));
+            hipLaunchKernelGGL((k_line<T, P, 2>), dim3((unsigned)nblk), dim3(128), lb_bytes,
                                s, ks, ps, lbnd, lst, hcount, g, F, Fbar, d == 1 ? 1 : 0,
                                (double)N);
         }

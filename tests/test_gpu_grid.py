@@ -60,6 +60,10 @@ CASES = [
     (4, 6000, [6, 7, 5, 9], False, True),
     (5, 3000, [3, 4, 2, 5, 6], True, False),
     (6, 2000, [2, 3, 2, 3, 2, 4], False, True),
+    # long last axes: line workgroups of four, then two wavefronts
+    (1, 5000, [1500], False, True),
+    (1, 20000, [4000], False, True),
+    (2, 8000, [3, 4000], True, False),
 ]
 
 
