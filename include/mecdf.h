@@ -124,6 +124,8 @@ int ecdf_esf_grid(int d, int64_t N, const double *x, const void *y,
  *
  *   x   device, d*N doubles;  y  device N weights or NULL (int64 counts)
  *   F   device, N results in input order
+ *
+ * Limits: N <= 2^26 (MECDF_EUNSUPPORTED above).  Results are deterministic.
  */
 int ecdf_points(int d, int64_t N, const double *x, const void *y, void *F,
                 int prec, void *stream);
