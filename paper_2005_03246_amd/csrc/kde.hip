@@ -669,7 +669,10 @@ __global__ void k_kzero(double *a, int64_t n) {
 
 // Direct sums inside each 64-item block of a state (one wavefront per block):
 // acc[p] += sum over the block's items j != p (with a different bit-0 side
-// when need_diff) of w_j exp(-sum_k |x_k,p - x_k,j| / h_k).
+// when need_diff) of w_j exp(-sum_k |x_k,p - x_k,j| / h_k).  Each unordered
+// pair is evaluated once: for offsets o = 1..32, lane l pairs with lane
+// (l + o) mod 64 (at o = 32 only lanes below 32 do), keeps its own share and
+// hands the partner's share to it by a shuffle; sums are taken in o order.
 template <typename T, int CH>
 __global__ __launch_bounds__(256) void k_kblock_pairs(KState st, int d, int64_t n, KBatch kb,
                                                       int need_diff, double *__restrict__ acc) {
@@ -678,7 +681,8 @@ __global__ __launch_bounds__(256) void k_kblock_pairs(KState st, int d, int64_t 
     const int64_t p = blk * 64 + lane;
     if (blk * 64 >= n)
         return;
-    const bool v = p < n;
+    const int cnt = (int)((n - blk * 64) < 64 ? (n - blk * 64) : 64);
+    const bool v = lane < cnt;
     double xx[3], w0 = 0.0, w1 = 0.0;
     int side = 0;
     for (int k = 0; k < 3; ++k)
@@ -694,23 +698,34 @@ __global__ __launch_bounds__(256) void k_kblock_pairs(KState st, int d, int64_t 
 #pragma unroll
         for (int c = 0; c < CH; ++c)
             sum[b][c] = 0.0;
-    const int64_t bstart = blk * 64;
-    const int cnt = (int)((n - bstart) < 64 ? (n - bstart) : 64);
-    for (int j = 0; j < cnt; ++j) {
-        double y0 = shfl(xx[0], j), y1 = shfl(xx[1], j), y2 = shfl(xx[2], j);
-        double u0 = shfl(w0, j), u1 = shfl(w1, j);
-        int sj = __shfl(side, j, 64);
-        if (!v || j == lane || (need_diff && sj == side))
-            continue;
-        double e0 = fabs(xx[0] - y0), e1 = d > 1 ? fabs(xx[1] - y1) : 0.0,
-               e2 = d > 2 ? fabs(xx[2] - y2) : 0.0;
+    for (int o = 1; o <= 32; ++o) {
+        const int q = (lane + o) & 63;
+        const double y0 = shfl(xx[0], q), y1 = shfl(xx[1], q), y2 = shfl(xx[2], q);
+        const double u0 = shfl(w0, q), u1 = shfl(w1, q);
+        const int sq = __shfl(side, q, 64);
+        const bool pair = v && q < cnt && !(need_diff && sq == side) && (o < 32 || lane < 32);
+        double give[kKB][CH];
+        const double e0 = fabs(xx[0] - y0), e1 = d > 1 ? fabs(xx[1] - y1) : 0.0,
+                     e2 = d > 2 ? fabs(xx[2] - y2) : 0.0;
 #pragma unroll
         for (int b = 0; b < kKB; ++b) {
-            T kv = kexp<T>((T)(-(e0 * kb.ih[b][0] + e1 * kb.ih[b][1] + e2 * kb.ih[b][2])));
+            const T kv =
+                pair ? kexp<T>((T)(-(e0 * kb.ih[b][0] + e1 * kb.ih[b][1] + e2 * kb.ih[b][2])))
+                     : T(0);
             sum[b][0] += (double)((T)u0 * kv);
-            if (CH > 1)
+            give[b][0] = (double)((T)w0 * kv);
+            if (CH > 1) {
                 sum[b][CH - 1] += (double)((T)u1 * kv);
+                give[b][CH - 1] = (double)((T)w1 * kv);
+            }
         }
+        // the share of lane (lane - o) mod 64, whose partner this lane is
+        const int from = (lane - o) & 63;
+#pragma unroll
+        for (int b = 0; b < kKB; ++b)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                sum[b][c] += shfl(give[b][c], from);
     }
     if (!v)
         return;
