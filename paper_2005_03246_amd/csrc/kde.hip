@@ -739,32 +739,67 @@ __global__ __launch_bounds__(256) void k_kblock_pairs(KState st, int d, int64_t 
 
 // Outputs and per-point score terms from the leave-one-out sums (x1 order).
 // mode 0: KDE (channel 0 = w); mode 1: NW (channel 0 = 1, channel 1 = y).
-template <int CH, typename OutT>
+// Per item (x1-sorted order) and bandwidth of the batch: the LOO score term,
+// log fhat_{-j} (mode 0) or the squared LOO residual (mode 1).
+template <int CH>
 __global__ __launch_bounds__(256) void k_kfinish(const double *__restrict__ acc, KState st,
-                                                 const uint32_t *__restrict__ ids, int64_t n,
-                                                 KBatch kb, int b0, int mode,
-                                                 OutT *__restrict__ out,
+                                                 int64_t n, KBatch kb, int mode,
                                                  double *__restrict__ terms) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n)
         return;
     const double *a = acc + p * (kKB * CH);
-    const double w0 = st.w0[p], w1 = st.w1[p];
-    const uint32_t id = ids[p];
+    const double w1 = st.w1[p];
     for (int b = 0; b < kb.nb; ++b) {
-        double o, t;
+        double t;
         if (mode == 0) {
-            o = (a[b * CH] + w0) * kb.norm_full[b];
             t = log(a[b * CH] * kb.norm_loo[b]);
         } else {
             double num = a[b * CH + CH - 1], den = a[b * CH];
-            o = (num + w1) / (den + 1.0);
             double e = w1 - num / den;
             t = e * e;
         }
-        if (out)
-            out[(int64_t)(b0 + b) * n + id] = (OutT)o;
         terms[(int64_t)b * n + p] = t;
+    }
+}
+
+// inv[ids[p]] = p: position of input point i in the x1-sorted order
+__global__ __launch_bounds__(256) void k_kinv(const uint32_t *__restrict__ ids, int64_t n,
+                                              uint32_t *__restrict__ inv) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n)
+        inv[ids[p]] = (uint32_t)p;
+}
+
+// The full estimates in input order: point i reads its accumulator record
+// (all bandwidths of the batch at once) from its sorted position, and each
+// bandwidth's row is written coalesced: the density with the point itself
+// (mode 0) or the regression ratio with it (mode 1).
+template <int CH, typename OutT>
+__global__ __launch_bounds__(256) void k_kout(const double *__restrict__ acc, KState st,
+                                              const uint32_t *__restrict__ inv, int64_t n,
+                                              KBatch kb, int b0, int mode,
+                                              OutT *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t p = inv[i];
+    const double *a = acc + p * (kKB * CH);
+    double r[kKB * CH];
+#pragma unroll
+    for (int q = 0; q < kKB * CH; ++q)
+        r[q] = a[q];
+    const double w0 = st.w0[p], w1 = st.w1[p];
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        if (b >= kb.nb)
+            break;
+        double o;
+        if (mode == 0)
+            o = (r[b * CH] + w0) * kb.norm_full[b];
+        else
+            o = (r[b * CH + CH - 1] + w1) / (r[b * CH] + 1.0);
+        out[(int64_t)(b0 + b) * n + i] = (OutT)o;
     }
 }
 
@@ -901,6 +936,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     for (int q = 0; q < 3; ++q)
         pl.add<uint32_t>((size_t)n);
     pl.add<uint32_t>((size_t)n);  // ids
+    pl.add<uint32_t>((size_t)n);  // inv
     for (int q = 0; q < nstates; ++q)
         plan_state(pl, n);
     for (int q = 0; q < 4; ++q)
@@ -918,6 +954,7 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     uint64_t *k0 = a.take<uint64_t>(n), *k1 = a.take<uint64_t>(n), *k2 = a.take<uint64_t>(n);
     uint32_t *i0 = a.take<uint32_t>(n), *i1 = a.take<uint32_t>(n), *i2 = a.take<uint32_t>(n);
     uint32_t *ids = a.take<uint32_t>(n);
+    uint32_t *inv = a.take<uint32_t>(n);
     KState S0 = take_state(a, n);
     std::vector<KState> So(d >= 2 ? L + 1 : 0);  // So[0]: 64-blocks by x2; So[q+1]: merged 2 hs[q]
     for (auto &st : So)
@@ -955,6 +992,8 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         uint32_t *idx = which == 1 ? i1 : (which == 2 ? i2 : i0);
         hipLaunchKernelGGL((k_kgather0<WT>), dim3(nb), dim3(256), 0, s, idx, n, d, x, w0in, w1in,
                            S0, ids);
+        if (out)
+            hipLaunchKernelGGL(k_kinv, dim3(nb), dim3(256), 0, s, ids, n, inv);
         if (d >= 2) {
             hipLaunchKernelGGL(k_kblocksort, dim3(nbw), dim3(256), 0, s, S0, 1, n, So[0], S0.map);
             for (int q = 0; q < L; ++q)
@@ -1077,8 +1116,12 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         }
         {
             ProfScope prof("kde_finish", s);
-            hipLaunchKernelGGL((k_kfinish<CH, OutT>), dim3(nb), dim3(256), 0, s, ao, S0, ids, n,
-                               kb, b0, mode, out, terms);
+            if (score)
+                hipLaunchKernelGGL((k_kfinish<CH>), dim3(nb), dim3(256), 0, s, ao, S0, n, kb,
+                                   mode, terms);
+            if (out)
+                hipLaunchKernelGGL((k_kout<CH, OutT>), dim3(nb), dim3(256), 0, s, ao, S0, inv,
+                                   n, kb, b0, mode, out);
             if (score)
                 launch_mean(terms, n, kb.nb, b0, mpart, score, s);
         }
