@@ -161,6 +161,8 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
  *   h     host, nh*d positive finite doubles, h[b*d + k]
  *   f     device nh*N results (double, or float with MECDF_F32C) or NULL
  *   lcv   device nh doubles or NULL
+ *
+ * Limits: N <= 2^28, and N <= 2^24 for d = 3 (MECDF_EUNSUPPORTED above).
  */
 int kde_laplace(int d, int64_t N, const double *x, const void *w, int nh,
                 const double *h, void *f, double *lcv, int prec, void *stream);
