@@ -34,9 +34,9 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "9673db4abf69fda83e5195a46cb348e47f042b67eccdc93de89d20f3b245a834",
+        "sha256": "0f98b647bc2aaa115163bed8d0a2f2020e038cd1e3755a788fa4ab3e27b7e829",
         "prec": "f64",
-        "fetch_kib": 131117.0, "fetch_factor": 2.0,
+        "fetch_kib": 131122.9, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
@@ -44,7 +44,7 @@ TRAFFIC = {
         "sha256": "f9754c33fa54a1abb6764c46b72814a7e1059147050d289374d33af86e60e554",
         "prec": "f64",
         "fetch_kib": 102452.6, "fetch_factor": 2.0,
-        "write_kib": 225443.9, "write_factor": 1.0,
+        "write_kib": 225439.0, "write_factor": 1.0,
     },
 }
 
