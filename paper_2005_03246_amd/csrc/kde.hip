@@ -315,12 +315,26 @@ __device__ __forceinline__ void add_side(T (&l)[NSD][CH], int sd, const T (&v)[C
         for (int c = 0; c < CH; ++c)
             l[s][c] += (s == sd) ? v[c] : T(0);
 }
+// a or b by an integer mask on the bits (the compiler keeps this a register
+// operation; a select between array elements can become an indexed load
+// from scratch memory)
+__device__ __forceinline__ double mask_pick(bool take_b, double a, double b) {
+    const uint64_t m = take_b ? ~0ull : 0ull;
+    const uint64_t r = ((uint64_t)__double_as_longlong(a) & ~m) |
+                       ((uint64_t)__double_as_longlong(b) & m);
+    return __longlong_as_double((long long)r);
+}
+__device__ __forceinline__ float mask_pick(bool take_b, float a, float b) {
+    const uint32_t m = take_b ? ~0u : 0u;
+    return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+}
+
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ T get_side(const T (&l)[NSD][CH], int sd, int c) {
     T r = l[0][c];
 #pragma unroll
     for (int s = 1; s < NSD; ++s)
-        r = (s == sd) ? l[s][c] : r;
+        r = mask_pick(s == sd, r, l[s][c]);
     return r;
 }
 
