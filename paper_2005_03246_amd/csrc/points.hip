@@ -312,10 +312,14 @@ constexpr int kMpT = 1024;
 
 template <int NC>
 __device__ __forceinline__ uint64_t item_key_sel(const Item<NC> &it, int m) {
+    // the coordinate m - 1 by bit masks (a chain of selects between the
+    // item's fields would be turned into an indexed load from scratch memory)
     uint32_t c = it.c[0];
 #pragma unroll
-    for (int k = 1; k < NC; ++k)
-        c = (k == m - 1) ? it.c[k] : c;
+    for (int k = 1; k < NC; ++k) {
+        const uint32_t sel = (k == m - 1) ? ~0u : 0u;
+        c = (it.c[k] & sel) | (c & ~sel);
+    }
     return ((uint64_t)c << 1) | (uint64_t)(it.idt & 1u);
 }
 
