@@ -456,23 +456,92 @@ __device__ __forceinline__ Aff<T, CH, NSD> block_aff_scan(Aff<T, CH, NSD> v,
     return v;
 }
 
+// The same scans by shuffles inside each wavefront and one exchange of the
+// four wavefront totals through LDS (wt, 4 entries): inc is the thread's inclusive
+// composition (dir 0: threads 0..t in order; dir 1: threads 255..t), exc the
+// exclusive one (identity for the first thread in scan order).
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ Aff<T, CH, NSD> aff_shfl(const Aff<T, CH, NSD> &a, int src) {
+    Aff<T, CH, NSD> r;
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        r.m[b] = shfl(a.m[b], src);
+#pragma unroll
+        for (int s = 0; s < NSD; ++s)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                r.l[b][s][c] = shfl(a.l[b][s][c], src);
+    }
+    return r;
+}
+
+template <typename T, int CH, int NSD>
+__device__ __forceinline__ void block_aff_scan2(const Aff<T, CH, NSD> &v, Aff<T, CH, NSD> *wt,
+                                                int dir, Aff<T, CH, NSD> &inc,
+                                                Aff<T, CH, NSD> &exc) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    Aff<T, CH, NSD> x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const Aff<T, CH, NSD> o = aff_shfl(x, dir ? ((lane + off) & 63) : ((lane - off) & 63));
+        if (dir ? (lane + off < 64) : (lane >= off))
+            x = aff_then(o, x);
+    }
+    __syncthreads();  // the totals of an earlier scan have been read
+    if (lane == (dir ? 0 : 63))
+        wt[w] = x;
+    __syncthreads();
+    Aff<T, CH, NSD> pre;
+    aff_identity(pre);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = dir ? 3 - k : k;
+        if (dir ? (q > w) : (q < w))
+            pre = aff_then(pre, wt[q]);
+    }
+    inc = aff_then(pre, x);
+    const Aff<T, CH, NSD> nb = aff_shfl(x, dir ? ((lane + 1) & 63) : ((lane - 1) & 63));
+    exc = (dir ? lane == 63 : lane == 0) ? pre : aff_then(pre, nb);
+}
+
+// Which block scan a kernel uses: the LDS tree keeps fewer values in
+// registers, which is what float64 density sums (one channel) need to keep
+// three wavefronts per SIMD; the shuffle scan needs almost no LDS and fewer
+// barriers, which wins for two channels and for float32.
+template <typename T, int CH> constexpr bool shfl_scan() {
+    return !(std::is_same<T, double>::value && CH == 1);
+}
+
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
                                                    KTileAgg<T, CH, NSD> *__restrict__ agg) {
-    __shared__ Aff<T, CH, NSD> buf[256];
+    __shared__ Aff<T, CH, NSD> buf[shfl_scan<T, CH>() ? 4 : 256];
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)threadIdx.x * kKItems;
     T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
     load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
-    Aff<T, CH, NSD> fi =
-        block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
-    if (threadIdx.x == 255)
-        agg[blockIdx.x].fwd = fi;
-    Aff<T, CH, NSD> bi =
-        block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
-    if (threadIdx.x == 0)
-        agg[blockIdx.x].bwd = bi;
+    if constexpr (shfl_scan<T, CH>()) {
+        Aff<T, CH, NSD> fi, fe, bi, be;
+        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0,
+                                    fi, fe);
+        if (threadIdx.x == 255)
+            agg[blockIdx.x].fwd = fi;
+        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1,
+                                    bi, be);
+        if (threadIdx.x == 0)
+            agg[blockIdx.x].bwd = bi;
+    } else {
+        Aff<T, CH, NSD> fi =
+            block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
+        if (threadIdx.x == 255)
+            agg[blockIdx.x].fwd = fi;
+        Aff<T, CH, NSD> bi =
+            block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
+        if (threadIdx.x == 0)
+            agg[blockIdx.x].bwd = bi;
+    }
 }
 
 // Tile carries in two steps.  k_kcarry_local: per group of 256 consecutive
@@ -561,26 +630,35 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
                                                 const double *hi,
                                                 const uint32_t *__restrict__ hmap,
                                                 double *lo) {
-    __shared__ Aff<T, CH, NSD> buf[256];
+    __shared__ Aff<T, CH, NSD> buf[shfl_scan<T, CH>() ? 4 : 256];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)tid * kKItems;
     T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
     load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
-    (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
-    Aff<T, CH, NSD> fex;
-    if (tid == 0)
-        aff_identity(fex);
-    else
-        fex = aff_get(buf, tid - 1);
-    __syncthreads();
-    (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
-    Aff<T, CH, NSD> bex;
-    if (tid == 255)
-        aff_identity(bex);
-    else
-        bex = aff_get(buf, tid + 1);
+    Aff<T, CH, NSD> fex, bex;
+    if constexpr (shfl_scan<T, CH>()) {
+        Aff<T, CH, NSD> fin, bin;
+        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0,
+                                    fin, fex);
+        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1,
+                                    bin, bex);
+    } else {
+        (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf,
+                                         0);
+        if (tid == 0)
+            aff_identity(fex);
+        else
+            fex = aff_get(buf, tid - 1);
+        __syncthreads();
+        (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf,
+                                         1);
+        if (tid == 255)
+            aff_identity(bex);
+        else
+            bex = aff_get(buf, tid + 1);
+    }
     const KCarry<T, CH, NSD> &cr = car[blockIdx.x];
     T recv[kKItems][kKB][CH];
 #pragma unroll
