@@ -813,7 +813,9 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
     const bool wave_path = L >= 1024 && Cl <= kWaveLineMaxCells && wave_bytes <= 64 * 1024;
     if (wave_path) {
         ProfScope prof3("grid_line", s);
-        const int64_t nblk = std::min<int64_t>(ceil_div(L, kLineWaves), 2048);
+        // one line per wavefront: the workgroup dispatcher then balances
+        // lines of very different lengths, and more lines are in flight
+        const int64_t nblk = std::min<int64_t>(ceil_div(L, kLineWaves), 1 << 20);
         hipLaunchKernelGGL((k_line_wave<T, P>), dim3((unsigned)nblk), dim3(256), wave_bytes, s,
                            ks, ps, lbnd, hlist, hcount, g, F, Fbar, d == 1 ? 1 : 0,
                            (double)N);

@@ -64,6 +64,11 @@ CASES = [
     (1, 5000, [1500], False, True),
     (1, 20000, [4000], False, True),
     (2, 8000, [3, 4000], True, False),
+    # longer inner axes: axis 1 of 300 and 600 nodes, d = 4 with 45 nodes on
+    # axis 0
+    (3, 3000, [70, 300, 20], True, False),
+    (3, 2000, [40, 600, 3], False, True),
+    (4, 3000, [45, 20, 6, 7], True, False),
 ]
 
 
