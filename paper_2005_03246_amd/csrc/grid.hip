@@ -205,24 +205,42 @@ static void launch_cellkey(bool lds, int64_t nb, hipStream_t s, const double *x,
 
 // Sorted range [lbnd[2l], lbnd[2l+1]) of every non-empty line l; the entries
 // of empty lines keep the marker kNoLine (set before the sort).  A line starts
-// where the bits above the last-axis cell change; one key per thread, keys
-// read coalesced.
+// where the bits above the last-axis cell change.  Four consecutive keys per
+// thread (one 16-byte load; keys is 16-byte aligned) and the key before them.
 constexpr uint32_t kNoLine = 0xffffffffu;
 
 __global__ __launch_bounds__(256) void k_line_bounds(const uint32_t *__restrict__ keys,
                                                      int64_t n, GridInfo g,
                                                      uint32_t *__restrict__ lbnd) {
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * 256) {
-        const uint32_t k = keys[p];
-        const uint32_t pk = p > 0 ? keys[p - 1] : 0u;
-        if (p == 0 || (k >> g.bd) != (pk >> g.bd)) {
-            lbnd[2 * (int64_t)key_line(k, g)] = (uint32_t)p;
+    const int64_t p0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (p0 >= n)
+        return;
+    uint32_t k[4];
+    if (p0 + 4 <= n) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(keys + p0);
+        k[0] = q.x;
+        k[1] = q.y;
+        k[2] = q.z;
+        k[3] = q.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            k[u] = p0 + u < n ? keys[p0 + u] : 0u;
+    }
+    uint32_t pk = p0 > 0 ? keys[p0 - 1] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t p = p0 + u;
+        if (p >= n)
+            break;
+        if (p == 0 || (k[u] >> g.bd) != (pk >> g.bd)) {
+            lbnd[2 * (int64_t)key_line(k[u], g)] = (uint32_t)p;
             if (p > 0)
                 lbnd[2 * (int64_t)key_line(pk, g) + 1] = (uint32_t)p;
         }
         if (p == n - 1)
-            lbnd[2 * (int64_t)key_line(k, g) + 1] = (uint32_t)n;
+            lbnd[2 * (int64_t)key_line(k[u], g) + 1] = (uint32_t)n;
+        pk = k[u];
     }
 }
 
@@ -796,9 +814,8 @@ static int grid_run_t(int d, int64_t N, const double *x, const P *y,
         ks = which == 0 ? k0 : (which == 1 ? k1 : k2);
         ps = which == 0 ? y : (which == 1 ? p1 : p2);
         ProfScope prof2("grid_line_bounds", s);
-        hipLaunchKernelGGL(k_line_bounds,
-                           dim3((unsigned)std::min<int64_t>(ceil_div(N, 256), 4096)),
-                           dim3(256), 0, s, ks, N, g, lbnd);
+        hipLaunchKernelGGL(k_line_bounds, dim3((unsigned)ceil_div(N, 1024)), dim3(256), 0, s,
+                           ks, N, g, lbnd);
         MECDF_LAUNCH_CHECK();
     } else {
         hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)ceil_div(2 * (L + 1), 256)), dim3(256),
