@@ -34,17 +34,17 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "0f98b647bc2aaa115163bed8d0a2f2020e038cd1e3755a788fa4ab3e27b7e829",
+        "sha256": "e8dcd20fa04d4b9895b82f8c599a84f0a36cfc92a89ea8298021908a68d62af4",
         "prec": "f64",
-        "fetch_kib": 131122.9, "fetch_factor": 2.0,
+        "fetch_kib": 131125.6, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
         "source": "paper_2005_03246_amd/csrc/radix.hpp",
         "sha256": "f9754c33fa54a1abb6764c46b72814a7e1059147050d289374d33af86e60e554",
         "prec": "f64",
-        "fetch_kib": 102452.6, "fetch_factor": 2.0,
-        "write_kib": 225439.0, "write_factor": 1.0,
+        "fetch_kib": 102444.9, "fetch_factor": 2.0,
+        "write_kib": 225431.6, "write_factor": 1.0,
     },
 }
 
