@@ -193,8 +193,9 @@ inline uint32_t side_mask(int m) { return ((1u << (m - 1)) - 1u) << 1; }
 
 // Pairs inside each block of kBlockT items at depth m: every active query
 // adds the weight of the active data placed before it whose coordinates
-// m..d-1 are all <= its own (the active data are first compacted in LDS, in
-// block order, so each query scans only them).  The block is then sorted by
+// m..d-1 are all <= its own (the active data items and weights are first
+// compacted in LDS, in block order, so each query scans only them, and the
+// number of them before a query is its compaction offset).  The block is then sorted by
 // (coordinate m, type, position) with a bitonic network in LDS and written
 // back.  (The last coordinate has its own kernel, k_block_count.)
 template <int NC, bool kW>
@@ -208,7 +209,8 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
     __shared__ Item<NC> sI[T];
     __shared__ double sW[kW ? T : 1];
     __shared__ uint64_t sk[T];
-    __shared__ uint32_t dIdx[T];
+    __shared__ Item<NC> dI[T];
+    __shared__ double dW[kW ? T : 1];
     __shared__ uint32_t wt[4];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * T;
@@ -226,12 +228,17 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
         int li = 2 * tid + u;
         fd[u] = li < cnt && active_data(sI[li].idt, mask);
     }
-    uint32_t nd;
-    uint32_t off = block_exclusive_scan256<uint32_t>((uint32_t)fd[0] + (uint32_t)fd[1], wt, &nd);
-    if (fd[0])
-        dIdx[off++] = 2 * tid;
-    if (fd[1])
-        dIdx[off] = 2 * tid + 1;
+    const uint32_t off = block_exclusive_scan256<uint32_t>((uint32_t)fd[0] + (uint32_t)fd[1],
+                                                           wt, nullptr);
+    const uint32_t nbefore[2] = {off, off + (uint32_t)fd[0]};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (fd[u]) {
+            dI[nbefore[u]] = sI[2 * tid + u];
+            if constexpr (kW)
+                dW[nbefore[u]] = sW[2 * tid + u];
+        }
+    }
     __syncthreads();
     // active queries scan the active data before them
 #pragma unroll
@@ -240,24 +247,36 @@ __global__ __launch_bounds__(256) void k_block_brute(Item<NC> *__restrict__ S,
         if (li >= cnt || !active_query(sI[li].idt, mask))
             continue;
         const Item<NC> me = sI[li];
-        AccT sum = AccT(0);
-        for (uint32_t k = 0; k < nd; ++k) {
-            uint32_t j = dIdx[k];
-            if ((int)j >= li)
-                break;
-            const Item<NC> J = sI[j];
-            bool dom = true;
+        const uint32_t nb = nbefore[u];
+        auto dom = [&](const Item<NC> &J) {
+            bool r = true;
 #pragma unroll
             for (int q = 0; q < NC; ++q)
                 if (q >= m - 1)
-                    dom = dom && (J.c[q] <= me.c[q]);
-            if (dom) {
-                if constexpr (kW)
-                    sum += sW[j];
-                else
-                    sum += 1;
-            }
+                    r = r && (J.c[q] <= me.c[q]);
+            return r;
+        };
+        auto wgt = [&](uint32_t k) -> AccT {
+            if constexpr (kW)
+                return dW[k];
+            else
+                return AccT(1);
+        };
+        AccT sum = AccT(0);
+        uint32_t k = 0;
+        for (; k + 4 <= nb; k += 4) {
+            Item<NC> J[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                J[v] = dI[k + v];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (dom(J[v]))
+                    sum += wgt(k + v);
         }
+        for (; k < nb; ++k)
+            if (dom(dI[k]))
+                sum += wgt(k);
         if (sum != AccT(0))
             reinterpret_cast<AccT *>(acc_raw)[me.idt >> kIdShift] += sum;
     }
