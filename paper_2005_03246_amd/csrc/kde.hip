@@ -712,27 +712,32 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
     // lo[p] = hi[hmap[p]] + this level's sums (hi == nullptr: zero; hmap ==
     // nullptr: hi[p], which may be lo itself).  All loads come before the
     // stores, which may overwrite them.
+    // (a record of W doubles is 16-byte aligned: moved as double2)
     constexpr int W = kKB * CH;
-    double hv[kKItems][W];
+    static_assert(W % 2 == 0, "records of whole double2");
+    double2 hv[kKItems][W / 2];
 #pragma unroll
     for (int u = 0; u < kKItems; ++u) {
         const int64_t p = base + u;
         const int64_t src = (hi && val[u]) ? (hmap ? (int64_t)hmap[p] : p) : -1;
 #pragma unroll
-        for (int i = 0; i < W; ++i)
-            hv[u][i] = src >= 0 ? hi[src * W + i] : 0.0;
+        for (int i = 0; i < W / 2; ++i)
+            hv[u][i] = src >= 0 ? reinterpret_cast<const double2 *>(hi + src * W)[i]
+                                : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < kKItems; ++u) {
         const int64_t p = base + u;
         if (!val[u])
             continue;
-        double *a = lo + p * W;
+        double2 *a = reinterpret_cast<double2 *>(lo + p * W);
 #pragma unroll
-        for (int b = 0; b < kKB; ++b)
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-                a[b * CH + c] = hv[u][b * CH + c] + (double)recv[u][b][c];
+        for (int i = 0; i < W / 2; ++i) {
+            const int b0 = (2 * i) / CH, c0 = (2 * i) % CH;
+            const int b1 = (2 * i + 1) / CH, c1 = (2 * i + 1) % CH;
+            a[i] = make_double2(hv[u][i].x + (double)recv[u][b0][c0],
+                                hv[u][i].y + (double)recv[u][b1][c1]);
+        }
     }
 }
 
