@@ -273,27 +273,22 @@ __device__ __forceinline__ double split_point(const double *src, int64_t p, int6
     return (s + h < n) ? src[s + h] : src[n - 1];
 }
 
+// Item p's decays and weights from its loaded values: x, the scanned
+// coordinate of it (xp, xn: of its neighbours), da / db its distances to the
+// split points of the split coordinates, side bits sb, weights w0v, w1v.
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int64_t p,
-                                      T alpha[kKB], T *beta, T f[kKB], int &sd,
-                                      T wv[CH]) {
+                                      double x, double xp, double xn, double da, double db,
+                                      uint32_t sb, double w0v, double w1v, T alpha[kKB],
+                                      T *beta, T f[kKB], int &sd, T wv[CH]) {
     const int64_t seg = 2 * L.hin;
     const int64_t s = (p / seg) * seg;
     const bool start = (p == s);
     const bool last = (p + 1 >= L.n) || (p + 1 == s + seg);
-    double x = L.xs[p];
-    double xp = start ? x : L.xs[p - 1];
-    double xn = last ? x : L.xs[p + 1];
-    double da = 0.0, db = 0.0;
-    if (!L.oneside) {
-        da = fabs(L.xa[p] - split_point(L.ca, p, L.ha, L.n));
-        if (NSD == 4)
-            db = fabs(L.xb[p] - split_point(L.cb, p, L.hb, L.n));
-    }
-    sd = L.oneside ? 0 : (int)(L.bits[p] & (NSD - 1));
-    wv[0] = (T)L.w0[p];
+    sd = L.oneside ? 0 : (int)(sb & (NSD - 1));
+    wv[0] = (T)w0v;
     if (CH > 1)
-        wv[CH - 1] = (T)L.w1[p];
+        wv[CH - 1] = (T)w1v;
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
         double ihs = kb.ih[b][L.sc];
@@ -302,6 +297,16 @@ __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int
             beta[b] = last ? T(0) : kexp<T>((T)(-(xn - x) * ihs));
         f[b] = L.oneside ? T(1) : kexp<T>((T)(-(da * kb.ih[b][0] + db * kb.ih[b][1])));
     }
+}
+
+// the kKItems (= 4) doubles at q (32-byte aligned) as two 16-byte loads
+__device__ __forceinline__ void load4(const double *q, double v[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(q)[0];
+    const double2 b = reinterpret_cast<const double2 *>(q)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
 }
 
 // Side-indexed access to small per-thread arrays with the side as a select
@@ -374,12 +379,48 @@ __device__ __forceinline__ Aff<T, CH, NSD> thread_aff(const T alpha[kKItems + 1]
 
 // alpha[u] for the thread's items u; alpha[kKItems] is the last item's beta.
 // The beta of item u < kKItems - 1 is alpha[u + 1]: both are the decay across
-// the same pair of neighbours (0 at a segment boundary or past the end).
+// the same pair of neighbours (0 at a segment boundary or past the end).  The
+// items' arrays are read as whole records: base is a multiple of kKItems and
+// every array starts 256-byte aligned.
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb,
                                            int64_t base, T alpha[kKItems + 1][kKB],
                                            T f[kKItems][kKB], int sd[kKItems],
                                            T wv[kKItems][CH], bool val[kKItems]) {
+    static_assert(kKItems == 4, "items read as two 16-byte loads per array");
+    double xs[4], xa[4] = {0.0, 0.0, 0.0, 0.0}, xb[4] = {0.0, 0.0, 0.0, 0.0};
+    double w0[4], w1[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t bits4 = 0u;
+    if (base + 4 <= L.n) {
+        load4(L.xs + base, xs);
+        load4(L.w0 + base, w0);
+        if (CH > 1)
+            load4(L.w1 + base, w1);
+        if (!L.oneside) {
+            load4(L.xa + base, xa);
+            if (NSD == 4)
+                load4(L.xb + base, xb);
+            bits4 = *reinterpret_cast<const uint32_t *>(L.bits + base);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t p = base + u;
+            const bool v = p < L.n;
+            xs[u] = v ? L.xs[p] : 0.0;
+            w0[u] = v ? L.w0[p] : 0.0;
+            if (CH > 1)
+                w1[u] = v ? L.w1[p] : 0.0;
+            if (!L.oneside && v) {
+                xa[u] = L.xa[p];
+                if (NSD == 4)
+                    xb[u] = L.xb[p];
+                bits4 |= (uint32_t)L.bits[p] << (8 * u);
+            }
+        }
+    }
+    const double xprev = base > 0 && base - 1 < L.n ? L.xs[base - 1] : 0.0;
+    const double xnext = base + 4 < L.n ? L.xs[base + 4] : 0.0;
 #pragma unroll
     for (int b = 0; b < kKB; ++b)
         alpha[kKItems][b] = T(0);
@@ -388,8 +429,16 @@ __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb
         int64_t p = base + u;
         val[u] = p < L.n;
         if (val[u]) {
-            kitem<T, CH, NSD>(L, kb, p, alpha[u], u == kKItems - 1 ? alpha[kKItems] : nullptr,
-                              f[u], sd[u], wv[u]);
+            double da = 0.0, db = 0.0;
+            if (!L.oneside) {
+                da = fabs(xa[u] - split_point(L.ca, p, L.ha, L.n));
+                if (NSD == 4)
+                    db = fabs(xb[u] - split_point(L.cb, p, L.hb, L.n));
+            }
+            kitem<T, CH, NSD>(L, kb, p, xs[u], u > 0 ? xs[u - 1] : xprev,
+                              u < kKItems - 1 ? xs[u + 1] : xnext, da, db, bits4 >> (8 * u),
+                              w0[u], w1[u], alpha[u],
+                              u == kKItems - 1 ? alpha[kKItems] : nullptr, f[u], sd[u], wv[u]);
         } else {
             sd[u] = 0;
 #pragma unroll
