@@ -918,24 +918,34 @@ __global__ __launch_bounds__(256) void k_kinv(const uint32_t *__restrict__ ids, 
 }
 
 // The full estimates in input order: point i reads its accumulator record
-// (all bandwidths of the batch at once) from its sorted position, and each
-// bandwidth's row is written coalesced: the density with the point itself
-// (mode 0) or the regression ratio with it (mode 1).
-template <int CH, typename OutT>
-__global__ __launch_bounds__(256) void k_kout(const double *__restrict__ acc, KState st,
+// (all bandwidths of the batch at once, as 16-byte vectors) from its sorted
+// position and its own weights from the caller's arrays in input order (the
+// same values the sorted state holds at that position), and each bandwidth's
+// row is written coalesced: the density with the point itself (mode 0) or the
+// regression ratio with it (mode 1).
+template <int CH, typename OutT, typename WT>
+__global__ __launch_bounds__(256) void k_kout(const double *__restrict__ acc,
                                               const uint32_t *__restrict__ inv, int64_t n,
                                               KBatch kb, int b0, int mode,
+                                              const WT *__restrict__ w0in,
+                                              const WT *__restrict__ w1in,
                                               OutT *__restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n)
         return;
     const int64_t p = inv[i];
-    const double *a = acc + p * (kKB * CH);
-    double r[kKB * CH];
+    constexpr int W = kKB * CH;
+    static_assert(W % 2 == 0, "records of whole double2");
+    const double2 *a = reinterpret_cast<const double2 *>(acc + p * W);
+    double r[W];
 #pragma unroll
-    for (int q = 0; q < kKB * CH; ++q)
-        r[q] = a[q];
-    const double w0 = st.w0[p], w1 = st.w1[p];
+    for (int q = 0; q < W / 2; ++q) {
+        const double2 v = a[q];
+        r[2 * q] = v.x;
+        r[2 * q + 1] = v.y;
+    }
+    const double w0 = w0in ? (double)w0in[i] : 1.0;
+    const double w1 = w1in ? (double)w1in[i] : 0.0;
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
         if (b >= kb.nb)
@@ -1266,8 +1276,8 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
                 hipLaunchKernelGGL((k_kfinish<CH>), dim3(nb), dim3(256), 0, s, ao, S0, n, kb,
                                    mode, terms);
             if (out)
-                hipLaunchKernelGGL((k_kout<CH, OutT>), dim3(nb), dim3(256), 0, s, ao, S0, inv,
-                                   n, kb, b0, mode, out);
+                hipLaunchKernelGGL((k_kout<CH, OutT, WT>), dim3(nb), dim3(256), 0, s, ao, inv,
+                                   n, kb, b0, mode, w0in, w1in, out);
             if (score)
                 launch_mean(terms, n, kb.nb, b0, mpart, score, s);
         }
