@@ -147,15 +147,15 @@ __global__ __launch_bounds__(256) void k_kblocksort(KState in, int key, int64_t 
     }
 }
 
-// Merge of aligned blocks of size h sorted by coordinate `key` (A then B)
-// into 2h, one thread per item; sets bit `sbit` to the item's side and
-// records in.map[p] = new position.
+// Merge of aligned blocks of size h (a power of two) sorted by coordinate
+// `key` (A then B) into 2h, one thread per item; sets bit `sbit` to the item's
+// side and records in.map[p] = new position.
 __global__ __launch_bounds__(256) void k_kmerge(KState in, int key, int64_t n, int64_t h,
                                                 int sbit, KState o) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n)
         return;
-    int64_t s = (p / (2 * h)) * (2 * h);
+    int64_t s = p & ~(2 * h - 1);
     int64_t ha = (n - s) < h ? (n - s) : h;
     int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
     const double *K = in.x[key];
@@ -257,7 +257,7 @@ struct KLevelArgs {
     int sc;                 // its index (for the bandwidth)
     const double *xa;       // first split coordinate (x1)
     const double *ca;       // split points source for xa (x1-sorted sample)
-    int64_t ha;             // half size of the xa split blocks
+    int64_t ha;             // half size of the xa split blocks (ha, hb, hin: powers of two)
     const double *xb;       // second split coordinate (x2, d = 3) or nullptr
     const double *cb;       // split points source for xb
     int64_t hb;
@@ -267,9 +267,10 @@ struct KLevelArgs {
     int oneside;
 };
 
+// The split point of the block of 2h items holding p (h a power of two).
 __device__ __forceinline__ double split_point(const double *src, int64_t p, int64_t h,
                                               int64_t n) {
-    int64_t s = (p / (2 * h)) * (2 * h);
+    const int64_t s = p & ~(2 * h - 1);
     return (s + h < n) ? src[s + h] : src[n - 1];
 }
 
@@ -281,8 +282,8 @@ __device__ __forceinline__ void kitem(const KLevelArgs &L, const KBatch &kb, int
                                       double x, double xp, double xn, double da, double db,
                                       uint32_t sb, double w0v, double w1v, T alpha[kKB],
                                       T *beta, T f[kKB], int &sd, T wv[CH]) {
-    const int64_t seg = 2 * L.hin;
-    const int64_t s = (p / seg) * seg;
+    const int64_t seg = 2 * L.hin;  // a power of two
+    const int64_t s = p & ~(seg - 1);
     const bool start = (p == s);
     const bool last = (p + 1 >= L.n) || (p + 1 == s + seg);
     sd = L.oneside ? 0 : (int)(sb & (NSD - 1));
@@ -1037,6 +1038,12 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
     auto *agg = reinterpret_cast<KTileAgg<T, CH, NSD> *>(agg_raw);
     auto *grp = reinterpret_cast<KTileAgg<T, CH, NSD> *>(grp_raw);
     auto *car = reinterpret_cast<KCarry<T, CH, NSD> *>(car_raw);
+    // the kernels find an item's segment and split blocks with bit masks
+    auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (!pow2(la.ha) || !pow2(la.hb) || !pow2(la.hin)) {
+        set_error("kernel sums: block sizes must be powers of two");
+        return MECDF_EINVAL;
+    }
     ProfScope prof("kde_scan", s);
     const unsigned ng = (unsigned)ceil_div(nt, (int64_t)256);
     hipLaunchKernelGGL((k_ktile_agg<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb,
