@@ -59,6 +59,9 @@ def _load():
         lib.oracle_laplace_sums.argtypes = [I, I64, P, I, P, I64, P, I, P, P,
                                             P, P, I]
         lib.oracle_laplace_sums.restype = I
+        lib.oracle_laplace_loo_shifted.argtypes = [I, I64, P, I, P, I, P, P,
+                                                   P, P, I]
+        lib.oracle_laplace_loo_shifted.restype = I
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = I
         _lib = lib
@@ -225,12 +228,55 @@ def kde_laplace_loo(x, h, w=None, nthreads=0):
     return s[0] * c[:, None], a[0] * c[:, None]
 
 
+def laplace_loo_shifted(x, h, w=None, nthreads=0):
+    """Leave-one-out kernel sums at the sample points with the nearest term
+    factored out: returns (m, S, A) with m of shape (nh, N) the smallest
+    scaled distance min_{i != j} sum_k |x_ki - x_kj| / h_bk, and S, A of shape
+    (nw, nh, N) the sums of w_c,i exp(-(e_i - m)) (and of |w_c,i| ...) over
+    i != j.  The plain leave-one-out sum is exp(-m) * S."""
+    x = _as_2d(x)
+    d, n = x.shape
+    if n < 2:
+        raise ValueError("leave-one-out sums need N >= 2")
+    h = _f64(_hmat(h, d))
+    nh = h.shape[0]
+    if w is None:
+        wv, nw = None, 1
+    else:
+        wv = _f64(w)
+        if wv.ndim == 1:
+            wv = wv[None, :]
+        nw = wv.shape[0]
+        wv = _f64(wv)
+    m = np.zeros((nh, n))
+    s = np.zeros((nw, nh, n))
+    a = np.zeros((nw, nh, n))
+    rc = _load().oracle_laplace_loo_shifted(d, n, _ptr(x), nw, _ptr(wv), nh,
+                                            _ptr(h), _ptr(m), _ptr(s), _ptr(a),
+                                            int(nthreads))
+    if rc:
+        raise ValueError("oracle_laplace_loo_shifted rejected its arguments")
+    return m, s, a
+
+
+def log_kde_loo(x, h, nthreads=0):
+    """log fhat_{-j}(x_j) at every sample point, (nh, N): the leave-one-out
+    density of eq. (Laplacian_kde_nD) (sum over i != j, N - 1 normalisation)
+    through a max-shifted log-sum-exp, -m_j + log S_j + log(1 / (2^d (N-1)
+    prod_k h_k)), finite even where every kernel term underflows."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    m, s, _ = laplace_loo_shifted(x, hm, None, nthreads)
+    c = -np.log(2.0 ** d * (n - 1) * np.prod(hm, axis=1))
+    return -m + np.log(s[0]) + c[:, None]
+
+
 def lcv(x, h, nthreads=0):
     """Likelihood cross-validation score LCV(h) = (1/N) sum_j log fhat_{-j}(x_j)
-    for each bandwidth row of h.  Returns (nh,)."""
-    f, _ = kde_laplace_loo(x, h, None, nthreads)
-    with np.errstate(divide="ignore"):
-        return np.log(f).mean(axis=1)
+    for each bandwidth row of h (Section 3.2 names likelihood
+    cross-validation for infinite-support kernels).  Returns (nh,)."""
+    return log_kde_loo(x, h, nthreads).mean(axis=1)
 
 
 def nw_regression(x, y, z, h, nthreads=0):
@@ -246,13 +292,14 @@ def nw_regression(x, y, z, h, nthreads=0):
 
 def nw_loo(x, y, h, nthreads=0):
     """Leave-one-out NW estimate at the sample points and the |y| scale of its
-    numerator: (m_loo, num, den, num_abs), each (nh, N)."""
+    numerator: (m_loo, num, den, num_abs), each (nh, N).  num and den are the
+    kernel sums over i != j relative to the nearest term (both carry the same
+    factor exp(m_j), which cancels in the ratio), so the ratio is defined
+    wherever some other point exists."""
     x = _as_2d(x)
-    d, n = x.shape
-    hm = _hmat(h, d)
     y = _f64(y)
-    s, a = laplace_sums(x, x, hm, np.stack([np.ones_like(y), y]),
-                        np.arange(n), nthreads)
+    _, s, a = laplace_loo_shifted(x, h, np.stack([np.ones_like(y), y]),
+                                  nthreads)
     return s[1] / s[0], s[1], s[0], a[1]
 
 

@@ -190,3 +190,83 @@ int oracle_laplace_sums(int d, int64_t N, const double *x, int nw,
     }
     return 0;
 }
+
+/*
+ * Leave-one-out Laplacian kernel sums at the sample points with the largest
+ * term factored out (a max-shifted log-sum-exp), for the likelihood and
+ * squared-error cross-validation scores built on eq. (Laplacian_kde_nD).
+ *
+ * For query point j and bandwidth vector b, with e_i = sum_k |x_{k,i} - x_{k,j}| / h_{b,k}
+ * over the data points i != j:
+ *
+ *   out_min[b*N + j]          = m = min_{i != j} e_i
+ *   out_sum[(c*nh + b)*N + j] = sum_{i != j} w_c,i exp(-(e_i - m))
+ *   out_abs[(c*nh + b)*N + j] = same with |w_c,i|
+ *
+ * so that sum_{i != j} w_c,i exp(-e_i) = exp(-m) * out_sum, and the logarithm
+ * of the leave-one-out sum is -m + log(out_sum) even where every exp(-e_i)
+ * underflows.  The nearest point (e_i = m) contributes exp(0) = 1, so
+ * out_sum >= min_i w_0,i > 0 for positive weights.  N >= 2.
+ */
+int oracle_laplace_loo_shifted(int d, int64_t N, const double *x, int nw,
+                               const double *w, int nh, const double *h,
+                               double *out_min, double *out_sum,
+                               double *out_abs, int nthreads)
+{
+    if (d < 1 || N < 2 || nh < 1 || !x || !h || !out_min || !out_sum ||
+        !out_abs)
+        return -1;
+    if (w == NULL)
+        nw = 1;
+    if (nw < 1 || nw > 8)
+        return -1;
+    for (int b = 0; b < nh; ++b)
+        for (int k = 0; k < d; ++k)
+            if (!(h[b * d + k] > 0.0))
+                return -1;
+    set_threads(nthreads);
+
+#pragma omp parallel for schedule(dynamic, 8) collapse(2)
+    for (int b = 0; b < nh; ++b)
+        for (int64_t j = 0; j < N; ++j) {
+            /* first pass: the smallest scaled distance to another point */
+            double m = INFINITY;
+            for (int64_t i = 0; i < N; ++i) {
+                if (i == j)
+                    continue;
+                double e = 0.0;
+                for (int k = 0; k < d; ++k)
+                    e += fabs(x[(int64_t)k * N + i] - x[(int64_t)k * N + j]) /
+                         h[b * d + k];
+                if (e < m)
+                    m = e;
+            }
+            /* second pass: the sums relative to that term */
+            nsum_t s[8], a[8];
+            for (int c = 0; c < nw; ++c) {
+                s[c].s = s[c].c = 0.0;
+                a[c].s = a[c].c = 0.0;
+            }
+            for (int64_t i = 0; i < N; ++i) {
+                if (i == j)
+                    continue;
+                double e = 0.0;
+                for (int k = 0; k < d; ++k)
+                    e += fabs(x[(int64_t)k * N + i] - x[(int64_t)k * N + j]) /
+                         h[b * d + k];
+                double kv = exp(-(e - m));
+                for (int c = 0; c < nw; ++c) {
+                    double wc = w ? w[(int64_t)c * N + i] : 1.0;
+                    nsum_add(&s[c], wc * kv);
+                    nsum_add(&a[c], fabs(wc) * kv);
+                }
+            }
+            out_min[(int64_t)b * N + j] = m;
+            for (int c = 0; c < nw; ++c) {
+                int64_t o = ((int64_t)c * nh + b) * N + j;
+                out_sum[o] = nsum_get(&s[c]);
+                out_abs[o] = nsum_get(&a[c]);
+            }
+        }
+    return 0;
+}

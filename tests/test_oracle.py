@@ -240,3 +240,68 @@ def test_far_points_underflow_exactly():
     x = np.array([[7.0, -7.0], [7.0, -7.0]])
     s, _ = oracle.laplace_sums(x, x, 0.01)
     np.testing.assert_array_equal(s[0, 0], [1.0, 1.0])
+
+
+# ------------------------------------------- leave-one-out scores under underflow
+def test_lcv_two_far_points_closed_form():
+    """Two points 8 apart at h = 0.01: every leave-one-out kernel term is
+    exp(-800), which is 0 in FP64, yet log fhat_{-j} is finite:
+    log(exp(-800) / (2 h (N - 1))) = -800 - log(2 * 0.01)."""
+    x = np.array([[0.0, 8.0]])
+    want = -800.0 - math.log(2 * 0.01)
+    got = oracle.lcv(x, [0.01])[0]
+    assert got == pytest.approx(want, rel=1e-15)
+    # the plain (unshifted) sum does underflow here
+    floo, _ = oracle.kde_laplace_loo(x, 0.01)
+    assert np.all(floo == 0.0)
+
+
+def test_lcv_three_points_hand_values():
+    """x = (0, 1, 3) in d = 1, h = 0.5, N - 1 = 2: the leave-one-out density
+    at x_j is (1 / (2 h 2)) sum_{i != j} exp(-|x_i - x_j| / h)."""
+    x = np.array([[0.0, 1.0, 3.0]])
+    terms = [math.log((math.exp(-2) + math.exp(-6)) / 2.0),
+             math.log((math.exp(-2) + math.exp(-4)) / 2.0),
+             math.log((math.exp(-6) + math.exp(-4)) / 2.0)]
+    got = oracle.log_kde_loo(x, [0.5])[0]
+    np.testing.assert_allclose(got, terms, rtol=1e-15)
+    assert oracle.lcv(x, [0.5])[0] == pytest.approx(sum(terms) / 3, rel=1e-15)
+
+
+def test_lcv_brute_force_logsumexp_tiny():
+    """Tiny random samples at bandwidths from moderate down to where every
+    kernel term underflows, against scipy's logsumexp over i != j."""
+    from scipy.special import logsumexp
+
+    g = np.random.default_rng(12)
+    for d in (1, 2, 3):
+        x = g.normal(size=(d, 7)) * 3
+        hs = np.array([1.0, 0.05, 0.002])
+        got = oracle.log_kde_loo(x, hs)
+        for b, h in enumerate(hs):
+            for j in range(7):
+                e = np.sum(np.abs(x - x[:, j:j + 1]), axis=0) / h
+                e = np.delete(e, j)
+                want = logsumexp(-e) - math.log(2 ** d * 6 * h ** d)
+                assert got[b, j] == pytest.approx(want, rel=1e-13, abs=1e-12)
+    # where nothing underflows the shifted form equals the plain logarithm
+    x = g.normal(size=(2, 300))
+    floo, _ = oracle.kde_laplace_loo(x, [0.2, 0.9])
+    np.testing.assert_allclose(oracle.lcv(x, [0.2, 0.9]), np.log(floo).mean(axis=1),
+                               rtol=1e-14)
+
+
+def test_nw_loo_ratio_under_underflow():
+    """x = (0, 10, 10.5), y = (1, 2, 4), h = 0.01: at point 0 the other two
+    terms are exp(-1000) and exp(-1050) (both 0 in FP64); their ratio is
+    (2 + 4 e^-50) / (1 + e^-50).  At point 2 the terms are exp(-1050) and
+    exp(-50): m = (e^-1000 + 2) / (e^-1000 + 1) = 2 to double precision."""
+    x = np.array([[0.0, 10.0, 10.5]])
+    y = np.array([1.0, 2.0, 4.0])
+    m, _, _, _ = oracle.nw_loo(x, y, [0.01])
+    e = math.exp(-50)
+    assert m[0, 0] == pytest.approx((2 + 4 * e) / (1 + e), rel=1e-15)
+    assert m[0, 1] == pytest.approx(4.0, rel=1e-15)
+    assert m[0, 2] == pytest.approx(2.0, rel=1e-15)
+    cv = oracle.nw_cv(x, y, [0.01])[0]
+    assert cv == pytest.approx(((1 - m[0, 0]) ** 2 + 4 + 4) / 3, rel=1e-15)
