@@ -157,7 +157,7 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
 
 static int kde_check(int d, int64_t N, const double *x, int nh,
                      const double *h, void *out, double *score, int prec) {
-    MECDF_TRY(check_common(d, N, x, prec, 3));
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
     if (N < 2)
         return fail(MECDF_EINVAL, "kernel sums at the points need N >= 2");
     if (nh < 1 || nh > 256)

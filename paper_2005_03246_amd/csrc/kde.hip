@@ -50,6 +50,7 @@ constexpr int kKB = 4;     // bandwidths per batch
 constexpr int kKT = 64;    // bottom block: one wavefront
 constexpr int kKItems = 4;
 constexpr int kKTile = 256 * kKItems;
+constexpr int64_t kKdeDirectMaxN = int64_t(1) << 20;  // d >= 4: O(N^2) direct sums
 
 __device__ __forceinline__ uint64_t order_key_kde(double v) {
     if (v == 0.0)
@@ -208,13 +209,33 @@ __global__ __launch_bounds__(256) void k_kmerge(KState in, int key, int64_t n, i
 // 1-D case (oneside) there is one side and f = 1.  Both recurrences are affine
 // scans, state -> m * state + l, evaluated as tile aggregates, tile carries
 // and a final pass, with fixed-order tree scans inside each tile.
+//
+// The decay m of a run of items is the product of their decays,
+// exp(-(x_last - x_before) / h).  It is formed from those two coordinates
+// each time it is used, never multiplied out: a product of k rounded factors
+// carries k roundings (for float32 factors over 2^20 sorted normal points at
+// h = 1 that is a relative error of 2.5e-4), while each weight then passes
+// through O(log N) compositions.  A map stores lo, the scanned coordinate
+// before its run (-inf when a segment starts inside the run, so m = 0), and
+// hi, the coordinate of its last item; maps of the backward scan store both
+// negated, so that one rule serves both directions.  lo = NaN marks the
+// identity.
+//
+// Inside a tile of kKTile items float64 decays are also carried multiplied
+// out (m): at most kKTile roundings, a relative error below 1.2e-13, for one
+// multiplication per composition instead of an exponential.  Float32 decays
+// are always formed from the coordinates, and across tiles both are.
+template <typename T> constexpr bool tile_products() { return std::is_same<T, double>::value; }
+
 template <typename T, int CH, int NSD> struct Aff {
-    T m[kKB];
+    double lo, hi;
+    T m[kKB];  // the decay multiplied out (used when tile_products<T>())
     T l[kKB][NSD][CH];
 };
 
 template <typename T, int CH, int NSD>
 __device__ __forceinline__ void aff_identity(Aff<T, CH, NSD> &a) {
+    a.lo = a.hi = __builtin_nan("");
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
         a.m[b] = T(1);
@@ -226,21 +247,49 @@ __device__ __forceinline__ void aff_identity(Aff<T, CH, NSD> &a) {
     }
 }
 
-// first `x`, then `y`: state -> y.m (x.m state + x.l) + y.l
-template <typename T, int CH, int NSD>
+// The decay of map a for bandwidth b (ih: 1/h of the scanned coordinate),
+// from the coordinates (A) or as carried.
+template <bool A, typename T, int CH, int NSD>
+__device__ __forceinline__ T aff_m(const Aff<T, CH, NSD> &a, const double (&ih)[kKB], int b) {
+    if constexpr (!A)
+        return a.m[b];
+    return (a.lo != a.lo) ? T(1) : kexp<T>((T)(-(a.hi - a.lo) * ih[b]));
+}
+
+// first `x`, then `y` (y's run follows x's): state -> y.m (x.m state + x.l) + y.l
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> aff_then(const Aff<T, CH, NSD> &x,
-                                                    const Aff<T, CH, NSD> &y) {
+                                                    const Aff<T, CH, NSD> &y,
+                                                    const double (&ih)[kKB]) {
     Aff<T, CH, NSD> r;
+    if constexpr (A) {
+        const bool xid = x.lo != x.lo, yid = y.lo != y.lo;
+        r.lo = xid ? y.lo : (y.lo == -INFINITY ? -INFINITY : x.lo);
+        r.hi = yid ? x.hi : y.hi;
+    } else {
+        // the identity needs no special case here (m = 1, l = 0); the
+        // coordinates of a tile's total are set from the tile itself
+        r.lo = r.hi = 0.0;
+    }
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
-        r.m[b] = x.m[b] * y.m[b];
+        const T my = aff_m<A>(y, ih, b);
+        if constexpr (!A)
+            r.m[b] = x.m[b] * my;
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                r.l[b][s][c] = y.m[b] * x.l[b][s][c] + y.l[b][s][c];
+                r.l[b][s][c] = my * x.l[b][s][c] + y.l[b][s][c];
     }
     return r;
+}
+
+// 1/h of the scanned coordinate for each bandwidth of the batch
+__device__ __forceinline__ void scan_ih(const KBatch &kb, int sc, double (&ih)[kKB]) {
+#pragma unroll
+    for (int b = 0; b < kKB; ++b)
+        ih[b] = kb.ih[b][sc];
 }
 
 template <typename T, int CH, int NSD> struct KTileAgg {
@@ -344,6 +393,16 @@ __device__ __forceinline__ T get_side(const T (&l)[NSD][CH], int sd, int c) {
     return r;
 }
 
+// Where the thread's items sit on the scanned coordinate: the first and the
+// last valid item's value, the values just before and after the items, and
+// which items start or end a segment (bit u).  Kept as scalars: selecting
+// among array elements by a runtime condition can place the array in memory.
+struct ItemPos {
+    double xfirst, xlast;
+    double xprev, xnext;
+    uint32_t starts, lasts, vmask;
+};
+
 // The maps of the thread's items composed in order: forward (dir = 0, items
 // ascending) or backward (dir = 1, descending).
 template <typename T, int CH, int NSD>
@@ -351,9 +410,19 @@ __device__ __forceinline__ Aff<T, CH, NSD> thread_aff(const T alpha[kKItems + 1]
                                                       const T f[kKItems][kKB],
                                                       const int sd[kKItems],
                                                       const T wv[kKItems][CH],
-                                                      const bool val[kKItems], int dir) {
+                                                      const bool val[kKItems],
+                                                      const ItemPos &ps, int dir) {
     Aff<T, CH, NSD> a;
     aff_identity(a);
+    if (!tile_products<T>() && ps.vmask) {
+        if (dir == 0) {
+            a.lo = (ps.starts & ps.vmask) ? -INFINITY : ps.xprev;
+            a.hi = ps.xlast;
+        } else {
+            a.lo = (ps.lasts & ps.vmask) ? -INFINITY : -ps.xnext;
+            a.hi = -ps.xfirst;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kKItems; ++k) {
         const int u = dir ? kKItems - 1 - k : k;
@@ -362,7 +431,8 @@ __device__ __forceinline__ Aff<T, CH, NSD> thread_aff(const T alpha[kKItems + 1]
 #pragma unroll
         for (int b = 0; b < kKB; ++b) {
             const T dec = dir ? alpha[u + 1][b] : alpha[u][b];
-            a.m[b] *= dec;
+            if constexpr (tile_products<T>())
+                a.m[b] *= dec;
 #pragma unroll
             for (int s = 0; s < NSD; ++s)
 #pragma unroll
@@ -387,7 +457,8 @@ template <typename T, int CH, int NSD>
 __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb,
                                            int64_t base, T alpha[kKItems + 1][kKB],
                                            T f[kKItems][kKB], int sd[kKItems],
-                                           T wv[kKItems][CH], bool val[kKItems]) {
+                                           T wv[kKItems][CH], bool val[kKItems],
+                                           ItemPos &ps) {
     static_assert(kKItems == 4, "items read as two 16-byte loads per array");
     double xs[4], xa[4] = {0.0, 0.0, 0.0, 0.0}, xb[4] = {0.0, 0.0, 0.0, 0.0};
     double w0[4], w1[4] = {0.0, 0.0, 0.0, 0.0};
@@ -422,6 +493,27 @@ __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb
     }
     const double xprev = base > 0 && base - 1 < L.n ? L.xs[base - 1] : 0.0;
     const double xnext = base + 4 < L.n ? L.xs[base + 4] : 0.0;
+    ps.xprev = xprev;
+    ps.xnext = xnext;
+    ps.xfirst = xs[0];
+    ps.xlast = xs[0];
+    ps.starts = ps.lasts = ps.vmask = 0u;
+    {
+        const int64_t seg = 2 * L.hin;  // a power of two
+#pragma unroll
+        for (int u = 0; u < kKItems; ++u) {
+            const int64_t p = base + u;
+            if (p < L.n) {
+                ps.vmask |= 1u << u;
+                ps.xlast = xs[u];
+            }
+            const int64_t s0 = p & ~(seg - 1);
+            if (p == s0)
+                ps.starts |= 1u << u;
+            if (p + 1 >= L.n || p + 1 == s0 + seg)
+                ps.lasts |= 1u << u;
+        }
+    }
 #pragma unroll
     for (int b = 0; b < kKB; ++b)
         alpha[kKItems][b] = T(0);
@@ -454,13 +546,20 @@ __device__ __forceinline__ void load_items(const KLevelArgs &L, const KBatch &kb
 
 // The 256 thread maps sit in LDS field by field (element f of thread t at
 // f * 256 + t), so that a wavefront's accesses to one field are consecutive.
-template <typename T, int CH, int NSD>
+// (A: the map's coordinates are moved, else its multiplied-out decays)
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ void aff_put(Aff<T, CH, NSD> *buf, int t,
                                         const Aff<T, CH, NSD> &a) {
-    T *q = reinterpret_cast<T *>(buf);
+    double *qd = reinterpret_cast<double *>(buf);
+    if constexpr (A) {
+        qd[t] = a.lo;
+        qd[256 + t] = a.hi;
+    }
+    T *q = reinterpret_cast<T *>(qd + 512);
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
-        q[b * 256 + t] = a.m[b];
+        if constexpr (!A)
+            q[b * 256 + t] = a.m[b];
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
@@ -468,13 +567,16 @@ __device__ __forceinline__ void aff_put(Aff<T, CH, NSD> *buf, int t,
                 q[(kKB + (b * NSD + s) * CH + c) * 256 + t] = a.l[b][s][c];
     }
 }
-template <typename T, int CH, int NSD>
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> aff_get(const Aff<T, CH, NSD> *buf, int t) {
-    const T *q = reinterpret_cast<const T *>(buf);
+    const double *qd = reinterpret_cast<const double *>(buf);
     Aff<T, CH, NSD> a;
+    a.lo = A ? qd[t] : 0.0;
+    a.hi = A ? qd[256 + t] : 0.0;
+    const T *q = reinterpret_cast<const T *>(qd + 512);
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
-        a.m[b] = q[b * 256 + t];
+        a.m[b] = A ? T(1) : q[b * 256 + t];
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
@@ -486,21 +588,22 @@ __device__ __forceinline__ Aff<T, CH, NSD> aff_get(const Aff<T, CH, NSD> *buf, i
 
 // Inclusive tree scan of the 256 thread maps in LDS: forward (dir = 0, thread
 // t composes threads 0..t) or backward (dir = 1, threads 255..t).
-template <typename T, int CH, int NSD>
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> block_aff_scan(Aff<T, CH, NSD> v,
-                                                          Aff<T, CH, NSD> *buf, int dir) {
+                                                          Aff<T, CH, NSD> *buf, int dir,
+                                                          const double (&ih)[kKB]) {
     const int t = threadIdx.x;
-    aff_put(buf, t, v);
+    aff_put<A>(buf, t, v);
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
         Aff<T, CH, NSD> r = v;
         if (dir == 0 && t >= off)
-            r = aff_then(aff_get(buf, t - off), v);
+            r = aff_then<A>(aff_get<A>(buf, t - off), v, ih);
         if (dir == 1 && t + off < 256)
-            r = aff_then(aff_get(buf, t + off), v);
+            r = aff_then<A>(aff_get<A>(buf, t + off), v, ih);
         __syncthreads();
         v = r;
-        aff_put(buf, t, v);
+        aff_put<A>(buf, t, v);
         __syncthreads();
     }
     return v;
@@ -510,12 +613,14 @@ __device__ __forceinline__ Aff<T, CH, NSD> block_aff_scan(Aff<T, CH, NSD> v,
 // four wavefront totals through LDS (wt, 4 entries): inc is the thread's inclusive
 // composition (dir 0: threads 0..t in order; dir 1: threads 255..t), exc the
 // exclusive one (identity for the first thread in scan order).
-template <typename T, int CH, int NSD>
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> aff_shfl(const Aff<T, CH, NSD> &a, int src) {
     Aff<T, CH, NSD> r;
+    r.lo = A ? shfl(a.lo, src) : 0.0;
+    r.hi = A ? shfl(a.hi, src) : 0.0;
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
-        r.m[b] = shfl(a.m[b], src);
+        r.m[b] = A ? T(1) : shfl(a.m[b], src);
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
@@ -525,18 +630,18 @@ __device__ __forceinline__ Aff<T, CH, NSD> aff_shfl(const Aff<T, CH, NSD> &a, in
     return r;
 }
 
-template <typename T, int CH, int NSD>
+template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ void block_aff_scan2(const Aff<T, CH, NSD> &v, Aff<T, CH, NSD> *wt,
                                                 int dir, Aff<T, CH, NSD> &inc,
-                                                Aff<T, CH, NSD> &exc) {
+                                                Aff<T, CH, NSD> &exc, const double (&ih)[kKB]) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     Aff<T, CH, NSD> x = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const Aff<T, CH, NSD> o = aff_shfl(x, dir ? ((lane + off) & 63) : ((lane - off) & 63));
+        const Aff<T, CH, NSD> o = aff_shfl<A>(x, dir ? ((lane + off) & 63) : ((lane - off) & 63));
         if (dir ? (lane + off < 64) : (lane >= off))
-            x = aff_then(o, x);
+            x = aff_then<A>(o, x, ih);
     }
     __syncthreads();  // the totals of an earlier scan have been read
     if (lane == (dir ? 0 : 63))
@@ -548,11 +653,11 @@ __device__ __forceinline__ void block_aff_scan2(const Aff<T, CH, NSD> &v, Aff<T,
     for (int k = 0; k < 4; ++k) {
         const int q = dir ? 3 - k : k;
         if (dir ? (q > w) : (q < w))
-            pre = aff_then(pre, wt[q]);
+            pre = aff_then<A>(pre, wt[q], ih);
     }
-    inc = aff_then(pre, x);
-    const Aff<T, CH, NSD> nb = aff_shfl(x, dir ? ((lane + 1) & 63) : ((lane - 1) & 63));
-    exc = (dir ? lane == 63 : lane == 0) ? pre : aff_then(pre, nb);
+    inc = aff_then<A>(pre, x, ih);
+    const Aff<T, CH, NSD> nb = aff_shfl<A>(x, dir ? ((lane + 1) & 63) : ((lane - 1) & 63));
+    exc = (dir ? lane == 63 : lane == 0) ? pre : aff_then<A>(pre, nb, ih);
 }
 
 // Which block scan a kernel uses: the LDS tree keeps fewer values in
@@ -563,6 +668,24 @@ template <typename T, int CH> constexpr bool shfl_scan() {
     return !(std::is_same<T, double>::value && CH == 1);
 }
 
+// The coordinates of a whole tile's forward and backward maps, read from the
+// tile itself (maps inside a tile carry none when their decays are
+// multiplied out).  Segments are aligned blocks of 2 hin items and tiles
+// aligned blocks of kKTile, both powers of two, so a segment starts inside the
+// tile exactly when one starts at its first item, and one ends inside it
+// exactly when one ends at its last item or the sample does.
+__device__ __forceinline__ void tile_coords(const KLevelArgs &L, int64_t t0, double &flo,
+                                            double &fhi, double &blo, double &bhi) {
+    const int64_t seg = 2 * L.hin;
+    const int64_t t1 = t0 + kKTile < L.n ? t0 + kKTile : L.n;  // one past the last item
+    const bool start = (t0 & (seg - 1)) == 0;
+    const bool end = t1 >= L.n || (t1 & (seg - 1)) == 0;
+    flo = start ? -INFINITY : L.xs[t0 - 1];
+    fhi = L.xs[t1 - 1];
+    blo = end ? -INFINITY : -L.xs[t1];
+    bhi = -L.xs[t0];
+}
+
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
                                                    KTileAgg<T, CH, NSD> *__restrict__ agg) {
@@ -571,26 +694,42 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
     T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
-    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
+    ItemPos ps;
+    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val, ps);
+    double ih[kKB];
+    scan_ih(kb, L.sc, ih);
+    double fi_lo, fi_hi, bi_lo, bi_hi;  // the unused pair of tile_coords
     if constexpr (shfl_scan<T, CH>()) {
         Aff<T, CH, NSD> fi, fe, bi, be;
-        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0,
-                                    fi, fe);
-        if (threadIdx.x == 255)
+        block_aff_scan2<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 0), buf,
+                                    0, fi, fe, ih);
+        if (threadIdx.x == 255) {
+            if constexpr (tile_products<T>())
+                tile_coords(L, (int64_t)blockIdx.x * kKTile, fi.lo, fi.hi, bi_lo, bi_hi);
             agg[blockIdx.x].fwd = fi;
-        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1,
-                                    bi, be);
-        if (threadIdx.x == 0)
+        }
+        block_aff_scan2<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 1), buf,
+                                    1, bi, be, ih);
+        if (threadIdx.x == 0) {
+            if constexpr (tile_products<T>())
+                tile_coords(L, (int64_t)blockIdx.x * kKTile, fi_lo, fi_hi, bi.lo, bi.hi);
             agg[blockIdx.x].bwd = bi;
+        }
     } else {
-        Aff<T, CH, NSD> fi =
-            block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0);
-        if (threadIdx.x == 255)
+        Aff<T, CH, NSD> fi = block_aff_scan<!tile_products<T>(), T, CH, NSD>(
+            thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 0), buf, 0, ih);
+        if (threadIdx.x == 255) {
+            if constexpr (tile_products<T>())
+                tile_coords(L, (int64_t)blockIdx.x * kKTile, fi.lo, fi.hi, bi_lo, bi_hi);
             agg[blockIdx.x].fwd = fi;
-        Aff<T, CH, NSD> bi =
-            block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1);
-        if (threadIdx.x == 0)
+        }
+        Aff<T, CH, NSD> bi = block_aff_scan<!tile_products<T>(), T, CH, NSD>(
+            thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 1), buf, 1, ih);
+        if (threadIdx.x == 0) {
+            if constexpr (tile_products<T>())
+                tile_coords(L, (int64_t)blockIdx.x * kKTile, fi_lo, fi_hi, bi.lo, bi.hi);
             agg[blockIdx.x].bwd = bi;
+        }
     }
 }
 
@@ -605,9 +744,12 @@ template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__restrict__ agg,
                                                       int64_t nt,
                                                       KTileAgg<T, CH, NSD> *__restrict__ grp,
-                                                      KCarry<T, CH, NSD> *__restrict__ car) {
+                                                      KCarry<T, CH, NSD> *__restrict__ car,
+                                                      KBatch kb, int sc) {
     __shared__ Aff<T, CH, NSD> buf[256];
     const int t = threadIdx.x;
+    double ih[kKB];
+    scan_ih(kb, sc, ih);
     const int64_t q = (int64_t)blockIdx.x * 256 + t;
     Aff<T, CH, NSD> fa, ba, id;
     aff_identity(id);
@@ -617,13 +759,13 @@ __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__re
         fa = agg[q].fwd;
         ba = agg[q].bwd;
     }
-    Aff<T, CH, NSD> fi = block_aff_scan<T, CH, NSD>(fa, buf, 0);
-    Aff<T, CH, NSD> fex = t == 0 ? id : aff_get(buf, t - 1);
+    Aff<T, CH, NSD> fi = block_aff_scan<true, T, CH, NSD>(fa, buf, 0, ih);
+    Aff<T, CH, NSD> fex = t == 0 ? id : aff_get<true>(buf, t - 1);
     if (t == 255)
         grp[blockIdx.x].fwd = fi;
     __syncthreads();
-    Aff<T, CH, NSD> bi = block_aff_scan<T, CH, NSD>(ba, buf, 1);
-    Aff<T, CH, NSD> bex = t == 255 ? id : aff_get(buf, t + 1);
+    Aff<T, CH, NSD> bi = block_aff_scan<true, T, CH, NSD>(ba, buf, 1, ih);
+    Aff<T, CH, NSD> bex = t == 255 ? id : aff_get<true>(buf, t + 1);
     if (t == 0)
         grp[blockIdx.x].bwd = bi;
     if (q >= nt)
@@ -650,28 +792,33 @@ template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_kcarry_final(const KTileAgg<T, CH, NSD> *__restrict__ loc,
                                                       int64_t nt,
                                                       const KTileAgg<T, CH, NSD> *__restrict__ grp,
-                                                      KCarry<T, CH, NSD> *__restrict__ car) {
+                                                      KCarry<T, CH, NSD> *__restrict__ car,
+                                                      KBatch kb, int sc) {
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= nt)
         return;
+    double ih[kKB];
+    scan_ih(kb, sc, ih);
     const int64_t g = q / 256, ng = ceil_div_dev(nt, (int64_t)256);
     Aff<T, CH, NSD> cf, cb;
     aff_identity(cf);
     aff_identity(cb);
     for (int64_t j = 0; j < g; ++j)
-        cf = aff_then(cf, grp[j].fwd);
+        cf = aff_then<true>(cf, grp[j].fwd, ih);
     for (int64_t j = ng - 1; j > g; --j)
-        cb = aff_then(cb, grp[j].bwd);
+        cb = aff_then<true>(cb, grp[j].bwd, ih);
     const Aff<T, CH, NSD> ef = loc[q].fwd, eb = loc[q].bwd;
 #pragma unroll
-    for (int b = 0; b < kKB; ++b)
+    for (int b = 0; b < kKB; ++b) {
+        const T mf = aff_m<true>(ef, ih, b), mb = aff_m<true>(eb, ih, b);
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                car[q].F[b][s][c] = ef.m[b] * cf.l[b][s][c] + ef.l[b][s][c];
-                car[q].B[b][s][c] = eb.m[b] * cb.l[b][s][c] + eb.l[b][s][c];
+                car[q].F[b][s][c] = mf * cf.l[b][s][c] + ef.l[b][s][c];
+                car[q].B[b][s][c] = mb * cb.l[b][s][c] + eb.l[b][s][c];
             }
+    }
 }
 
 template <typename T, int CH, int NSD>
@@ -686,39 +833,43 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
     T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
     bool val[kKItems];
-    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val);
+    ItemPos ps;
+    load_items<T, CH, NSD>(L, kb, base, alpha, f, sd, wv, val, ps);
+    double ih[kKB];
+    scan_ih(kb, L.sc, ih);
     Aff<T, CH, NSD> fex, bex;
     if constexpr (shfl_scan<T, CH>()) {
         Aff<T, CH, NSD> fin, bin;
-        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf, 0,
-                                    fin, fex);
-        block_aff_scan2<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf, 1,
-                                    bin, bex);
+        block_aff_scan2<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 0), buf,
+                                    0, fin, fex, ih);
+        block_aff_scan2<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 1), buf,
+                                    1, bin, bex, ih);
     } else {
-        (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 0), buf,
-                                         0);
+        (void)block_aff_scan<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 0),
+                                         buf, 0, ih);
         if (tid == 0)
             aff_identity(fex);
         else
-            fex = aff_get(buf, tid - 1);
+            fex = aff_get<!tile_products<T>()>(buf, tid - 1);
         __syncthreads();
-        (void)block_aff_scan<T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, 1), buf,
-                                         1);
+        (void)block_aff_scan<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 1),
+                                         buf, 1, ih);
         if (tid == 255)
             aff_identity(bex);
         else
-            bex = aff_get(buf, tid + 1);
+            bex = aff_get<!tile_products<T>()>(buf, tid + 1);
     }
     const KCarry<T, CH, NSD> &cr = car[blockIdx.x];
     T recv[kKItems][kKB][CH];
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
         T st[NSD][CH];
+        const T mf = aff_m<!tile_products<T>()>(fex, ih, b);
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                st[s][c] = fex.m[b] * cr.F[b][s][c] + fex.l[b][s][c];
+                st[s][c] = mf * cr.F[b][s][c] + fex.l[b][s][c];
 #pragma unroll
         for (int u = 0; u < kKItems; ++u) {
             const int o = L.oneside ? 0 : (sd[u] ^ (NSD - 1));
@@ -735,11 +886,12 @@ __global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
             }
             add_side<T, CH, NSD>(st, sd[u], add);
         }
+        const T mb = aff_m<!tile_products<T>()>(bex, ih, b);
 #pragma unroll
         for (int s = 0; s < NSD; ++s)
 #pragma unroll
             for (int c = 0; c < CH; ++c)
-                st[s][c] = bex.m[b] * cr.B[b][s][c] + bex.l[b][s][c];
+                st[s][c] = mb * cr.B[b][s][c] + bex.l[b][s][c];
 #pragma unroll
         for (int u = kKItems - 1; u >= 0; --u) {
             const int o = L.oneside ? 0 : (sd[u] ^ (NSD - 1));
@@ -813,6 +965,23 @@ __global__ void k_kzero(double *a, int64_t n) {
     if (i < n)
         a[i] = 0.0;
 }
+
+__global__ void k_kzero_u32(uint32_t *a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        a[i] = 0u;
+}
+
+// Leave-one-out sums below this are re-evaluated exactly (k_kloo_exact): a
+// term lost in the scans is below the smallest normal number of the scan type
+// (2.2e-308 in float64, 1.2e-38 in float32), and at most N x (levels) of them
+// reach one item, so a sum above the threshold is within about 1e-18
+// (float64) / 1e-8 (float32) of its exact value relative to itself.
+template <typename T> constexpr double loo_tiny();
+template <> constexpr double loo_tiny<double>() { return 1e-280; }
+template <> constexpr double loo_tiny<float>() { return 1e-22; }
+constexpr int kLooExactGroups = 256;
+constexpr int kLooPartGroups = 2048;
 
 // Direct sums inside each 64-item block of a state (one wavefront per block):
 // acc[p] += sum over the block's items j != p (with a different bit-0 side
@@ -888,25 +1057,358 @@ __global__ __launch_bounds__(256) void k_kblock_pairs(KState st, int d, int64_t 
 // mode 0: KDE (channel 0 = w); mode 1: NW (channel 0 = 1, channel 1 = y).
 // Per item (x1-sorted order) and bandwidth of the batch: the LOO score term,
 // log fhat_{-j} (mode 0) or the squared LOO residual (mode 1).
+//
+// A leave-one-out sum of channel 0 (the density, or the regression
+// denominator) below `tiny` may have lost terms that fell below the smallest
+// normal number of the scan's type on the way (every stored factor is <= 1,
+// so a lost term is smaller than that number); such an item is appended to
+// `list` (entry p * kKB + b; cnt counts them, capacity n * kKB) and its score
+// term is left to k_kloo_exact.
 template <int CH>
 __global__ __launch_bounds__(256) void k_kfinish(const double *__restrict__ acc, KState st,
-                                                 int64_t n, KBatch kb, int mode,
-                                                 double *__restrict__ terms) {
+                                                 int64_t n, KBatch kb, int mode, double tiny,
+                                                 double *__restrict__ terms,
+                                                 uint32_t *__restrict__ cnt,
+                                                 uint32_t *__restrict__ list) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n)
         return;
     const double *a = acc + p * (kKB * CH);
     const double w1 = st.w1[p];
     for (int b = 0; b < kb.nb; ++b) {
+        const double den = a[b * CH];
+        if (!(den >= tiny)) {
+            const uint32_t slot = atomicAdd(cnt, 1u);
+            list[slot] = (uint32_t)p * kKB + (uint32_t)b;
+            continue;
+        }
         double t;
         if (mode == 0) {
-            t = log(a[b * CH] * kb.norm_loo[b]);
+            t = log(den * kb.norm_loo[b]);
         } else {
-            double num = a[b * CH + CH - 1], den = a[b * CH];
+            double num = a[b * CH + CH - 1];
             double e = w1 - num / den;
             t = e * e;
         }
         terms[(int64_t)b * n + p] = t;
+    }
+}
+
+// ------------------------------------------- sums relative to the nearest point
+// Leave-one-out kernel sums at a query j written relative to its nearest
+// other point, so that their logarithm exists even where every term
+// exp(-e_i) is below the float64 range:
+//   e_i = sum_k |x_k,i - x_k,j| / h_k,   m = min_{i != j} e_i,
+//   S_c = sum_{i != j} w_c,i exp(-(e_i - m)),   sum_{i != j} w_c,i exp(-e_i) = exp(-m) S_c.
+// Accumulated in one pass: a smaller e_i rescales the sums seen so far by
+// exp(-(m - e_i)) and becomes the new m.  Sums carry a Neumaier compensation
+// term (rescaled with them).
+template <int CH> struct LooAcc {
+    double m;
+    double s[CH], c[CH];
+};
+
+template <int CH> __device__ __forceinline__ void loo_init(LooAcc<CH> &a) {
+    a.m = INFINITY;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+        a.s[c] = a.c[c] = 0.0;
+}
+
+__device__ __forceinline__ void neum_add(double &s, double &c, double v) {
+    const double t = s + v;
+    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+}
+
+// one term: scaled distance e with factor t = exp(-|e - m|) already formed
+template <int CH>
+__device__ __forceinline__ void loo_add(LooAcc<CH> &a, double e, double t, const double (&w)[CH]) {
+    const bool lower = e < a.m;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        if (lower) {
+            a.s[c] *= t;
+            a.c[c] *= t;
+        }
+        neum_add(a.s[c], a.c[c], lower ? w[c] : w[c] * t);
+    }
+    a.m = lower ? e : a.m;
+}
+
+// b merged into a (a's terms first)
+template <int CH> __device__ __forceinline__ void loo_merge(LooAcc<CH> &a, const LooAcc<CH> &b) {
+    if (!(b.m < INFINITY))
+        return;
+    if (!(a.m < INFINITY)) {
+        a = b;
+        return;
+    }
+    const double m = a.m < b.m ? a.m : b.m;
+    const double fa = exp(-(a.m - m)), fb = exp(-(b.m - m));
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        double s = a.s[c] * fa, cc = a.c[c] * fa;
+        neum_add(s, cc, b.s[c] * fb);
+        neum_add(s, cc, b.c[c] * fb);
+        a.s[c] = s;
+        a.c[c] = cc;
+    }
+    a.m = m;
+}
+
+// The score term of an item from its sums relative to the nearest point.
+template <int CH>
+__device__ __forceinline__ double loo_term(const LooAcc<CH> &r, int mode, double norm_loo,
+                                           double yj) {
+    if (mode == 0)
+        return -r.m + log((r.s[0] + r.c[0]) * norm_loo);
+    const double ratio = (r.s[CH - 1] + r.c[CH - 1]) / (r.s[0] + r.c[0]);
+    const double er = yj - ratio;
+    return er * er;
+}
+
+// The score terms of the items k_kfinish set aside, by a sum over every other
+// point of the sample.  The first kLooCap items of the list: work units of
+// kLooQ items and one of nch chunks of the points (k_kloo_part), each chunk's
+// sums combined in a fixed tree of its workgroup, then the chunks of an item
+// in order (k_kloo_fin).  Items past kLooCap: one workgroup each, all points
+// (k_kloo_exact).  Workgroups step through the units; every one reads the
+// same count, so all of them leave the loop together.
+constexpr int kLooQ = 4;
+constexpr uint32_t kLooCap = 4096;
+constexpr int kLooMaxChunks = 64;
+
+template <int CH>
+__device__ __forceinline__ void loo_block_reduce(LooAcc<CH> a, LooAcc<CH> *buf, int t) {
+    buf[t] = a;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+            LooAcc<CH> x = buf[t];
+            loo_merge(x, buf[t + off]);
+            buf[t] = x;
+        }
+        __syncthreads();
+    }
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_kloo_part(KState st, int d, int64_t n, KBatch kb,
+                                                   const uint32_t *__restrict__ cnt,
+                                                   const uint32_t *__restrict__ list, int nch,
+                                                   int64_t chunk, LooAcc<CH> *__restrict__ part) {
+    __shared__ LooAcc<CH> buf[256];
+    const int t = threadIdx.x;
+    const uint32_t nf = *cnt < kLooCap ? *cnt : kLooCap;
+    const uint32_t units = ((nf + kLooQ - 1) / kLooQ) * (uint32_t)nch;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const uint32_t g = u / (uint32_t)nch;
+        const int c = (int)(u % (uint32_t)nch);
+        const uint32_t q0 = g * kLooQ;
+        int64_t qp[kLooQ];
+        double qx[kLooQ][3], qih[kLooQ][3];
+        LooAcc<CH> acc[kLooQ];
+#pragma unroll
+        for (int q = 0; q < kLooQ; ++q) {
+            const bool vq = q0 + q < nf;
+            const uint32_t e = vq ? list[q0 + q] : 0u;
+            qp[q] = vq ? (int64_t)(e / kKB) : -1;
+            const int b = (int)(e % kKB);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                qx[q][k] = (vq && k < d) ? st.x[k][qp[q]] : 0.0;
+                qih[q][k] = k < d ? kb.ih[b][k] : 0.0;
+            }
+            loo_init(acc[q]);
+        }
+        const int64_t i0 = (int64_t)c * chunk;
+        const int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+        for (int64_t i = i0 + t; i < i1; i += 256) {
+            double xi[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                xi[k] = k < d ? st.x[k][i] : 0.0;
+            double w[CH];
+            w[0] = st.w0[i];
+            if (CH > 1)
+                w[CH - 1] = st.w1[i];
+#pragma unroll
+            for (int q = 0; q < kLooQ; ++q) {
+                if (qp[q] < 0 || i == qp[q])
+                    continue;
+                double ei = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    ei += fabs(xi[k] - qx[q][k]) * qih[q][k];
+                loo_add(acc[q], ei, exp(-fabs(ei - acc[q].m)), w);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kLooQ; ++q) {
+            loo_block_reduce(acc[q], buf, t);
+            if (t == 0 && q0 + q < nf)
+                part[(int64_t)(q0 + q) * nch + c] = buf[0];
+            __syncthreads();  // buf is rewritten next
+        }
+    }
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_kloo_fin(KState st, int64_t n, KBatch kb, int mode,
+                                                  const uint32_t *__restrict__ cnt,
+                                                  const uint32_t *__restrict__ list, int nch,
+                                                  const LooAcc<CH> *__restrict__ part,
+                                                  double *__restrict__ terms) {
+    const uint32_t nf = *cnt < kLooCap ? *cnt : kLooCap;
+    const uint32_t f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= nf)
+        return;
+    const uint32_t e = list[f];
+    const int64_t p = e / kKB;
+    const int b = (int)(e % kKB);
+    LooAcc<CH> r = part[(int64_t)f * nch];
+    for (int c = 1; c < nch; ++c)
+        loo_merge(r, part[(int64_t)f * nch + c]);
+    terms[(int64_t)b * n + p] = loo_term(r, mode, kb.norm_loo[b], st.w1[p]);
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_kloo_exact(KState st, int d, int64_t n, KBatch kb,
+                                                    int mode, const uint32_t *__restrict__ cnt,
+                                                    const uint32_t *__restrict__ list,
+                                                    double *__restrict__ terms) {
+    __shared__ LooAcc<CH> part[256];
+    const int t = threadIdx.x;
+    const uint32_t nf = *cnt;
+    for (uint32_t u = kLooCap + blockIdx.x; u < nf; u += gridDim.x) {
+        const uint32_t e = list[u];
+        const int64_t p = e / kKB;
+        const int b = (int)(e % kKB);
+        double q[3], ih[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            q[k] = k < d ? st.x[k][p] : 0.0;
+            ih[k] = k < d ? kb.ih[b][k] : 0.0;
+        }
+        LooAcc<CH> a;
+        loo_init(a);
+        for (int64_t i = t; i < n; i += 256) {
+            if (i == p)
+                continue;
+            double ei = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < d)
+                    ei += fabs(st.x[k][i] - q[k]) * ih[k];
+            double w[CH];
+            w[0] = st.w0[i];
+            if (CH > 1)
+                w[CH - 1] = st.w1[i];
+            loo_add(a, ei, exp(-fabs(ei - a.m)), w);
+        }
+        loo_block_reduce(a, part, t);
+        if (t == 0)
+            terms[(int64_t)b * n + p] = loo_term(part[0], mode, kb.norm_loo[b], st.w1[p]);
+        __syncthreads();  // part[] is rewritten for the next item
+    }
+}
+
+// ------------------------------------------------ direct sums, d = 4 .. 6
+// For d >= 4 the orthant recursion would need one nested split per extra
+// coordinate (2^(d-1) running sums per item and O(N log^(d-1) N) work); the
+// sums are evaluated here directly, every (query, point) pair, relative to
+// the query's nearest point as above.  One thread per query (input order),
+// the points staged 256 at a time through LDS and read as broadcasts, every
+// bandwidth of the batch from the same staged distances.
+struct KBatchD {
+    double ih[kKB][MECDF_MAX_DIM];
+    double norm_full[kKB];
+    double norm_loo[kKB];
+    int nb;
+};
+
+template <typename T, int CH, typename WT, typename OutT>
+__global__ __launch_bounds__(256) void k_kdirect(const double *__restrict__ x, int d, int64_t n,
+                                                 const WT *__restrict__ w0in,
+                                                 const WT *__restrict__ w1in, KBatchD kb, int b0,
+                                                 int mode, OutT *__restrict__ out,
+                                                 double *__restrict__ terms) {
+    __shared__ double sx[MECDF_MAX_DIM][256];
+    __shared__ double sw[CH][256];
+    const int t = threadIdx.x;
+    const int64_t j = (int64_t)blockIdx.x * 256 + t;
+    const bool vq = j < n;
+    double q[MECDF_MAX_DIM];
+#pragma unroll
+    for (int k = 0; k < MECDF_MAX_DIM; ++k)
+        q[k] = (vq && k < d) ? x[(int64_t)k * n + j] : 0.0;
+    LooAcc<CH> acc[kKB];
+#pragma unroll
+    for (int b = 0; b < kKB; ++b)
+        loo_init(acc[b]);
+    for (int64_t t0 = 0; t0 < n; t0 += 256) {
+        const int64_t i = t0 + t;
+        __syncthreads();  // the previous tile has been read
+#pragma unroll
+        for (int k = 0; k < MECDF_MAX_DIM; ++k)
+            if (k < d)
+                sx[k][t] = i < n ? x[(int64_t)k * n + i] : 0.0;
+        sw[0][t] = i < n ? (w0in ? (double)w0in[i] : 1.0) : 0.0;
+        if (CH > 1)
+            sw[CH - 1][t] = i < n ? (double)w1in[i] : 0.0;
+        __syncthreads();
+        const int cnt = (n - t0) < 256 ? (int)(n - t0) : 256;
+        for (int u = 0; u < cnt; ++u) {
+            if (t0 + u == j)
+                continue;
+            double dk[MECDF_MAX_DIM];
+#pragma unroll
+            for (int k = 0; k < MECDF_MAX_DIM; ++k)
+                dk[k] = k < d ? fabs(sx[k][u] - q[k]) : 0.0;
+            double w[CH];
+            w[0] = sw[0][u];
+            if (CH > 1)
+                w[CH - 1] = sw[CH - 1][u];
+#pragma unroll
+            for (int b = 0; b < kKB; ++b) {
+                if (b >= kb.nb)
+                    break;
+                double e = 0.0;
+#pragma unroll
+                for (int k = 0; k < MECDF_MAX_DIM; ++k)
+                    e += dk[k] * kb.ih[b][k];
+                const T f = kexp<T>((T)(-fabs(e - acc[b].m)));
+                loo_add(acc[b], e, (double)f, w);
+            }
+        }
+    }
+    if (!vq)
+        return;
+    const double w0j = w0in ? (double)w0in[j] : 1.0;
+    const double w1j = w1in ? (double)w1in[j] : 0.0;
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        if (b >= kb.nb)
+            break;
+        const double s0 = acc[b].s[0] + acc[b].c[0];
+        const double s1 = acc[b].s[CH - 1] + acc[b].c[CH - 1];
+        const double em = exp(-acc[b].m);
+        if (out) {
+            const double o = mode == 0 ? (w0j + em * s0) * kb.norm_full[b]
+                                       : (w1j + em * s1) / (1.0 + em * s0);
+            out[(int64_t)(b0 + b) * n + j] = (OutT)o;
+        }
+        if (terms) {
+            double v;
+            if (mode == 0) {
+                v = -acc[b].m + log(s0 * kb.norm_loo[b]);
+            } else {
+                const double er = w1j - s1 / s0;
+                v = er * er;
+            }
+            terms[(int64_t)b * n + j] = v;
+        }
     }
 }
 
@@ -1044,19 +1546,25 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
         set_error("kernel sums: block sizes must be powers of two");
         return MECDF_EINVAL;
     }
-    ProfScope prof("kde_scan", s);
     const unsigned ng = (unsigned)ceil_div(nt, (int64_t)256);
-    hipLaunchKernelGGL((k_ktile_agg<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb,
-                       agg);
+    {
+        ProfScope prof("kde_tile_agg", s);
+        hipLaunchKernelGGL((k_ktile_agg<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la,
+                           kb, agg);
+    }
+    {
+    ProfScope prof("kde_carry", s);
     if (ng == 1) {
         hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(1), dim3(256), 0, s, agg, nt, grp,
-                           car);
+                           car, kb, la.sc);
     } else {
         hipLaunchKernelGGL((k_kcarry_local<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt, grp,
-                           (KCarry<T, CH, NSD> *)nullptr);
+                           (KCarry<T, CH, NSD> *)nullptr, kb, la.sc);
         hipLaunchKernelGGL((k_kcarry_final<T, CH, NSD>), dim3(ng), dim3(256), 0, s, agg, nt,
-                           grp, car);
+                           grp, car, kb, la.sc);
     }
+    }
+    ProfScope prof("kde_apply", s);
     hipLaunchKernelGGL((k_kapply<T, CH, NSD>), dim3((unsigned)nt), dim3(256), 0, s, la, kb, car,
                        hi, hmap, lo);
     MECDF_LAUNCH_CHECK();
@@ -1109,6 +1617,11 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     pl.add<KTileAgg<T, CH, 4>>((size_t)ceil_div(nt, (int64_t)256) + 1);  // tile groups
     pl.add<KCarry<T, CH, 4>>((size_t)nt + 1);
     pl.add<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
+    pl.add<uint32_t>(64);                 // count of items set aside
+    pl.add<uint32_t>((size_t)n * kKB);    // their list
+    const int loo_nch = (int)std::min<int64_t>(kLooMaxChunks, ceil_div(n, 4096));
+    const int64_t loo_chunk = ceil_div(n, loo_nch);
+    pl.add<LooAcc<CH>>((size_t)kLooCap * loo_nch);
     radix_plan(pl, n);
     void *wsb = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &wsb));
@@ -1137,6 +1650,9 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
     void *grp = a.take<KTileAgg<T, CH, 4>>((size_t)ceil_div(nt, (int64_t)256) + 1);
     void *car = a.take<KCarry<T, CH, 4>>((size_t)nt + 1);
     double *mpart = a.take<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
+    uint32_t *aside_cnt = a.take<uint32_t>(64);
+    uint32_t *aside = a.take<uint32_t>((size_t)n * kKB);
+    LooAcc<CH> *loo_part = a.take<LooAcc<CH>>((size_t)kLooCap * loo_nch);
     RadixScratch rs = radix_take(a, n);
     const unsigned nb = (unsigned)ceil_div(n, 256);
     const unsigned nbw = (unsigned)ceil_div(ceil_div(n, 64), 4);
@@ -1279,15 +1795,62 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         }
         {
             ProfScope prof("kde_finish", s);
-            if (score)
+            if (score) {
+                hipLaunchKernelGGL(k_kzero_u32, dim3(1), dim3(64), 0, s, aside_cnt, 1);
                 hipLaunchKernelGGL((k_kfinish<CH>), dim3(nb), dim3(256), 0, s, ao, S0, n, kb,
-                                   mode, terms);
+                                   mode, loo_tiny<T>(), terms, aside_cnt, aside);
+                ProfScope prof4("kde_loo_exact", s);
+                hipLaunchKernelGGL((k_kloo_part<CH>), dim3(kLooPartGroups), dim3(256), 0, s, S0,
+                                   d, n, kb, aside_cnt, aside, loo_nch, loo_chunk, loo_part);
+                hipLaunchKernelGGL((k_kloo_fin<CH>), dim3(kLooCap / 256), dim3(256), 0, s, S0, n,
+                                   kb, mode, aside_cnt, aside, loo_nch, loo_part, terms);
+                hipLaunchKernelGGL((k_kloo_exact<CH>), dim3(kLooExactGroups), dim3(256), 0, s,
+                                   S0, d, n, kb, mode, aside_cnt, aside, terms);
+            }
             if (out)
                 hipLaunchKernelGGL((k_kout<CH, OutT, WT>), dim3(nb), dim3(256), 0, s, ao, inv,
                                    n, kb, b0, mode, w0in, w1in, out);
             if (score)
                 launch_mean(terms, n, kb.nb, b0, mpart, score, s);
         }
+        MECDF_LAUNCH_CHECK();
+    }
+    return MECDF_OK;
+}
+
+template <typename T, int CH, typename WT, typename OutT>
+static int kde_direct_t(int d, int64_t n, const double *x, const WT *w0in, const WT *w1in,
+                        int nh, const double *h, OutT *out, double *score, int mode,
+                        hipStream_t s) {
+    ArenaPlan pl;
+    pl.add<double>((size_t)n * kKB);
+    pl.add<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
+    void *wsb = nullptr;
+    MECDF_TRY(workspace_reserve(pl.used, &wsb));
+    Arena a;
+    a.base = (char *)wsb;
+    double *terms = a.take<double>((size_t)n * kKB);
+    double *mpart = a.take<double>((size_t)(ceil_div(n, kMeanChunk) * kKB));
+    ProfScope prof("kde_direct", s);
+    for (int b0 = 0; b0 < nh; b0 += kKB) {
+        KBatchD kb{};
+        kb.nb = nh - b0 < kKB ? nh - b0 : kKB;
+        for (int b = 0; b < kKB; ++b) {
+            const int bb = b0 + (b < kb.nb ? b : 0);
+            double prod = 1.0;
+            for (int k = 0; k < MECDF_MAX_DIM; ++k) {
+                kb.ih[b][k] = k < d ? 1.0 / h[bb * d + k] : 0.0;
+                if (k < d)
+                    prod *= h[bb * d + k];
+            }
+            kb.norm_full[b] = 1.0 / ((double)(1 << d) * (double)n * prod);
+            kb.norm_loo[b] = 1.0 / ((double)(1 << d) * (double)(n - 1) * prod);
+        }
+        hipLaunchKernelGGL((k_kdirect<T, CH, WT, OutT>), dim3((unsigned)ceil_div(n, 256)),
+                           dim3(256), 0, s, x, d, n, w0in, w1in, kb, b0, mode, out,
+                           score ? terms : nullptr);
+        if (score)
+            launch_mean(terms, n, kb.nb, b0, mpart, score, s);
         MECDF_LAUNCH_CHECK();
     }
     return MECDF_OK;
@@ -1308,9 +1871,25 @@ int kde_lcv_select(int d, int64_t N, const double *x, int nh, const double *h, d
 
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh, const double *h,
             void *f, double *score, int regression, int prec, hipStream_t s) {
-    if (N > (int64_t(1) << 28) || (d == 3 && N > (int64_t(1) << 24))) {
-        set_error("kernel sums support N <= 2^28 (2^24 for d = 3)");
+    if (N > (int64_t(1) << 28) || (d == 3 && N > (int64_t(1) << 24)) ||
+        (d >= 4 && N > kKdeDirectMaxN)) {
+        set_error("kernel sums support N <= 2^28 (2^24 for d = 3, 2^20 for d >= 4)");
         return MECDF_EUNSUPPORTED;
+    }
+    if (d >= 4) {
+        if (!regression) {
+            if (prec == MECDF_F64)
+                return kde_direct_t<double, 1, double, double>(d, N, x, (const double *)w,
+                                                               nullptr, nh, h, (double *)f,
+                                                               score, 0, s);
+            return kde_direct_t<float, 1, float, float>(d, N, x, (const float *)w, nullptr, nh,
+                                                        h, (float *)f, score, 0, s);
+        }
+        if (prec == MECDF_F64)
+            return kde_direct_t<double, 2, double, double>(d, N, x, nullptr, (const double *)w,
+                                                           nh, h, (double *)f, score, 1, s);
+        return kde_direct_t<float, 2, float, float>(d, N, x, nullptr, (const float *)w, nh, h,
+                                                    (float *)f, score, 1, s);
     }
     if (!regression) {
         if (prec == MECDF_F64)

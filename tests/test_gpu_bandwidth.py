@@ -73,10 +73,24 @@ def test_mlp_forward_and_grad_vs_reference(lib, B):
     Gr, Lr = omlp.grad(X.astype(np.float64), T.astype(np.float64), p.astype(np.float64),
                        emulate=True)
     assert abs(float(loss.cpu()) - Lr) <= 1e-3 * max(Lr, 1e-6)
-    for a, b in [(omlp.OW1, omlp.OB1), (omlp.OB1, omlp.OW2), (omlp.OW2, omlp.OB2),
-                 (omlp.OB2, omlp.OW3), (omlp.OW3, omlp.OB3), (omlp.OB3, omlp.NPARAMS)]:
+    Gx, _ = omlp.grad(X.astype(np.float64), T.astype(np.float64), p.astype(np.float64),
+                      emulate=False)
+    blocks = [(omlp.OW1, omlp.OB1), (omlp.OB1, omlp.OW2), (omlp.OW2, omlp.OB2),
+              (omlp.OB2, omlp.OW3), (omlp.OW3, omlp.OB3), (omlp.OB3, omlp.NPARAMS)]
+    loose_exact = []
+    for a, b in blocks:
         s = np.max(np.abs(Gr[a:b])) + 1e-12
-        assert np.max(np.abs(G[a:b] - Gr[a:b])) <= 2e-2 * s, (a, b)
+        err = np.abs(G[a:b] - Gr[a:b]) / s
+        # most entries differ from the bf16-emulating reference only by the
+        # float32 accumulation order; an activation whose bf16 rounding falls
+        # the other way (an accumulation error straddling a rounding boundary)
+        # moves the entries it feeds by up to a bf16 step, hence the loose max
+        assert np.max(err) <= 2e-2, (a, b)
+        assert np.quantile(err, 0.99) <= 1e-4, (a, b)
+        loose_exact.append(np.quantile(np.abs(Gx[a:b] - Gr[a:b]) / s, 0.99))
+    # the bound above separates the emulation from plain float64: without
+    # the bf16 roundings the reference gradient misses it in the weight blocks
+    assert max(loose_exact[0], loose_exact[2]) > 1e-4
 
 
 def test_training_reduces_loss(lib):
@@ -148,3 +162,13 @@ def test_learned_selection_vs_grid_search(lib):
     assert np.all(wev == 4)
     # the extension only adds evaluations, so its choice is at least as good
     assert np.all(lcv >= wlcv - 1e-12)
+    # what the network adds: the same four-point window opened at the
+    # rule-of-thumb bandwidth alone (network output 0) lands further from the
+    # grid optimum, on average and in the share of datasets within 1 %
+    zero = torch.zeros_like(params)
+    ridx, rlcv, _ = bandwidth.select(test, zero, hgrid, lib.BW_WINDOW)
+    lim = np.log(1 / 0.99)
+    gap_learned = mat[rows, gidx] - wlcv
+    gap_rot = mat[rows, gidx] - rlcv
+    assert gap_learned.mean() < gap_rot.mean()
+    assert np.mean(gap_learned <= lim) >= np.mean(gap_rot <= lim)

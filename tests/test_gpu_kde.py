@@ -51,14 +51,15 @@ def test_kde_random(lib, case):
     assert rel_err(f0.cpu().numpy(), want0, scale0) <= 1e-12
     ref = oracle.lcv(x, hs)
     got = lcv0.cpu().numpy()
-    fin = np.isfinite(ref)
-    assert np.all(np.isfinite(got) == fin)
-    assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-12 * np.maximum(1.0, np.abs(ref[fin])))
-    # float32 path
+    assert np.all(np.isfinite(got))
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.maximum(1.0, np.abs(ref)))
+    # float32 path: densities and the LCV scores
     f32, _ = lib.kde_laplace(dev(x), hs, dev(w.astype(np.float32), torch.float32),
                              prec="f32c", want_lcv=False)
     want32, scale32 = oracle.kde_laplace(x, x, hs, w.astype(np.float32).astype(np.float64))
     assert rel_err(f32.cpu().numpy(), want32, scale32) <= 1e-5
+    _, l32 = lib.kde_laplace(dev(x), hs, prec="f32c", want_f=False)
+    assert np.all(np.abs(l32.cpu().numpy() - ref) <= 1e-5 * np.maximum(1.0, np.abs(ref)))
 
 
 @pytest.mark.parametrize("case", [(1, 800), (2, 70), (2, 2500), (3, 600), (3, 2100)])
@@ -74,10 +75,87 @@ def test_nw_random(lib, case):
     assert np.max(np.abs(m.cpu().numpy() - want)) <= 1e-12 * np.max(np.abs(y))
     ref = oracle.nw_cv(x, y, hs)
     assert np.all(np.abs(cv.cpu().numpy() - ref) <= 1e-12 * np.maximum(1.0, ref))
-    m32, _ = lib.kreg_laplace(dev(x), dev(y.astype(np.float32), torch.float32), hs,
-                              prec="f32c", want_cv=False)
-    want32 = oracle.nw_regression(x, y.astype(np.float32).astype(np.float64), x, hs)
+    m32, cv32 = lib.kreg_laplace(dev(x), dev(y.astype(np.float32), torch.float32), hs,
+                                 prec="f32c")
+    y32 = y.astype(np.float32).astype(np.float64)
+    want32 = oracle.nw_regression(x, y32, x, hs)
     assert np.max(np.abs(m32.cpu().numpy() - want32)) <= 1e-5 * np.max(np.abs(y))
+    ref32 = oracle.nw_cv(x, y32, hs)
+    assert np.all(np.abs(cv32.cpu().numpy() - ref32) <= 1e-5 * np.maximum(1.0, ref32))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_loo_sums_below_the_float_range(lib, d):
+    """Points far from every other one: at h = 0.01 their leave-one-out
+    kernel sums are below the float64 range (exp(-1000)) or the float32 range,
+    yet log fhat_{-j} and the NW leave-one-out ratio are finite and equal the
+    oracle's values (taken relative to the nearest point)."""
+    g = np.random.default_rng(40 + d)
+    n = 900
+    x = g.normal(size=(d, n)) * 0.3
+    x[:, 5] += 10.0          # 10 / 0.01 = 1000 from everything in axis 0 alone
+    x[:, 6] -= 9.0
+    x[:, 7] += 0.8           # e^-80: below the float32 range only
+    y = np.sin(x[0]) + 0.1 * g.normal(size=n)
+    hs = hmat([0.01, 0.02, 0.5], d)
+    ref = oracle.lcv(x, hs)
+    refcv = oracle.nw_cv(x, y, hs)
+    for prec, tol in (("f64", 1e-12), ("f32c", 1e-5)):
+        yy = dev(y) if prec == "f64" else dev(y.astype(np.float32), torch.float32)
+        _, lcv = lib.kde_laplace(dev(x), hs, prec=prec, want_f=False)
+        got = lcv.cpu().numpy()
+        assert np.all(np.isfinite(got)), prec
+        assert np.all(np.abs(got - ref) <= tol * np.maximum(1.0, np.abs(ref))), prec
+        _, cv = lib.kreg_laplace(dev(x), yy, hs, prec=prec, want_m=False)
+        r = refcv if prec == "f64" else oracle.nw_cv(x, y.astype(np.float32).astype(np.float64), hs)
+        assert np.all(np.abs(cv.cpu().numpy() - r) <= tol * np.maximum(1.0, r)), prec
+
+
+@pytest.mark.parametrize("case", [(4, 2), (4, 300), (5, 257), (6, 700)])
+def test_direct_sums_d4_to_d6(lib, case):
+    """d = 4..6 (direct evaluation of every pair): densities, NW estimates and
+    both scores against the oracle in float64 and float32."""
+    d, n = case
+    g = np.random.default_rng(70 + d + n)
+    x = g.normal(size=(d, n))
+    x[:, 0] += 6.0           # one far point: its sums are relative to its neighbour
+    w = g.uniform(0.2, 2.0, n)
+    y = np.cos(x[1]) + 0.1 * g.normal(size=n)
+    hs = hmat([0.05, 0.3, 1.0, 2.5, 0.7], d)
+    hs[2] = g.uniform(0.2, 1.5, d)
+    f, _ = lib.kde_laplace(dev(x), hs, dev(w), want_lcv=False)
+    want, scale = oracle.kde_laplace(x, x, hs, w)
+    assert rel_err(f.cpu().numpy(), want, scale) <= 1e-12
+    _, lcv = lib.kde_laplace(dev(x), hs, want_f=False)
+    ref = oracle.lcv(x, hs)
+    assert np.all(np.abs(lcv.cpu().numpy() - ref) <= 1e-12 * np.maximum(1.0, np.abs(ref)))
+    m, cv = lib.kreg_laplace(dev(x), dev(y), hs)
+    assert np.max(np.abs(m.cpu().numpy() - oracle.nw_regression(x, y, x, hs))) <= \
+        1e-12 * np.max(np.abs(y))
+    refcv = oracle.nw_cv(x, y, hs)
+    assert np.all(np.abs(cv.cpu().numpy() - refcv) <= 1e-12 * np.maximum(1.0, refcv))
+    f32, l32 = lib.kde_laplace(dev(x), hs, prec="f32c")
+    want1, scale1 = oracle.kde_laplace(x, x, hs)
+    assert rel_err(f32.cpu().numpy(), want1, scale1) <= 1e-5
+    assert np.all(np.abs(l32.cpu().numpy() - ref) <= 1e-5 * np.maximum(1.0, np.abs(ref)))
+    y32 = y.astype(np.float32)
+    m32, cv32 = lib.kreg_laplace(dev(x), dev(y32, torch.float32), hs, prec="f32c")
+    y32d = y32.astype(np.float64)
+    assert np.max(np.abs(m32.cpu().numpy() - oracle.nw_regression(x, y32d, x, hs))) <= \
+        1e-5 * np.max(np.abs(y))
+    r32 = oracle.nw_cv(x, y32d, hs)
+    assert np.all(np.abs(cv32.cpu().numpy() - r32) <= 1e-5 * np.maximum(1.0, r32))
+
+
+def test_paper_accuracy_claim_2d(lib):
+    """Section 4.2 reports the fast Laplacian KDE within 1e-14 (max absolute
+    difference) of the naive sum for X ~ N(0, I_2), h = 0.1: N = 20000 here,
+    every sample point, float64."""
+    g = np.random.default_rng(4_2)
+    x = g.normal(size=(2, 20000))
+    f, _ = lib.kde_laplace(dev(x), [0.1], want_lcv=False)
+    want, _ = oracle.kde_laplace(x, x, hmat([0.1], 2))
+    assert np.max(np.abs(f.cpu().numpy() - want)) < 1e-14
 
 
 def test_kde_hand_d1(lib, golden):
@@ -101,6 +179,18 @@ def test_kde_config4_lcv_full_small(lib):
     refcv = oracle.nw_cv(x, y, hs)
     assert np.all(np.abs(cv.cpu().numpy() - refcv) <= 1e-12 * refcv)
     assert int(np.argmin(cv.cpu().numpy())) == int(np.argmin(refcv))
+    # float32 path: all 64 scores within 1e-5, and the selected bandwidth's
+    # oracle score within that tolerance of the best one
+    _, l32 = lib.kde_laplace(dev(x), hs, prec="f32c", want_f=False)
+    g32 = l32.cpu().numpy()
+    assert np.all(np.abs(g32 - ref) <= 1e-5 * np.maximum(1.0, np.abs(ref)))
+    assert ref[int(np.argmax(g32))] >= ref.max() - 2e-5 * max(1.0, abs(ref.max()))
+    y32 = y.astype(np.float32)
+    _, c32 = lib.kreg_laplace(dev(x), dev(y32, torch.float32), hs, prec="f32c", want_m=False)
+    r32 = oracle.nw_cv(x, y32.astype(np.float64), hs)
+    c32 = c32.cpu().numpy()
+    assert np.all(np.abs(c32 - r32) <= 1e-5 * np.maximum(1.0, r32))
+    assert r32[int(np.argmin(c32))] <= r32.min() + 2e-5 * max(1.0, r32.min())
 
 
 def test_kde_config4_full_size_sampled(lib):
@@ -122,6 +212,19 @@ def test_kde_config4_full_size_sampled(lib):
     gotm = m.cpu().numpy()[pick][:, idx]
     assert np.max(np.abs(gotm - wantm)) <= 1e-12 * np.max(np.abs(y))
     assert np.all(np.isfinite(lcv.cpu().numpy())) and np.all(np.isfinite(cv.cpu().numpy()))
+    del f, m
+    # float32 path at the same points and bandwidths
+    f32, l32 = lib.kde_laplace(xt, hs, prec="f32c")
+    assert rel_err(f32.cpu().numpy()[pick][:, idx], want, scale) <= 1e-5
+    l32 = l32.cpu().numpy()
+    assert np.all(np.isfinite(l32))
+    assert np.all(np.abs(l32 - lcv.cpu().numpy()) <= 1e-5 * np.maximum(1.0, np.abs(l32)))
+    del f32
+    y32 = y.astype(np.float32)
+    m32, c32 = lib.kreg_laplace(xt, dev(y32, torch.float32), hs, prec="f32c")
+    want32 = oracle.nw_regression(x, y32.astype(np.float64), x[:, idx], hs[pick])
+    assert np.max(np.abs(m32.cpu().numpy()[pick][:, idx] - want32)) <= 1e-5 * np.max(np.abs(y))
+    assert np.all(np.isfinite(c32.cpu().numpy()))
 
 
 def test_kde_deterministic(lib):
