@@ -115,6 +115,28 @@ int ecdf_esf_grid(int d, int64_t N, const double *x, const void *y,
                   int prec, void *stream);
 
 /*
+ * ecdf_esf_grid_noalloc -- ecdf_esf_grid for callers that cannot allocate
+ * device memory (work recorded under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and argument
+ * errors as ecdf_esf_grid, but the call allocates nothing: its working memory
+ * is a fixed array of MECDF_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each device it runs on until the process ends, and the nodes z
+ * are copied from the caller's host array on the stream (read before the
+ * call returns).  A problem whose working memory exceeds the array returns
+ * MECDF_EUNSUPPORTED before anything is enqueued; it takes about 12 bytes
+ * per point for counts, 20 with float32 and 28 with float64 weights, plus
+ * 12 bytes per grid line (the product of M_k + 1 over all axes but the last)
+ * and the nodes, so about 2.3 million float64 points fit.  Every call on one
+ * device uses the same array and leaves its contents behind: calls that
+ * overlap in time on a device (other streams or threads) race; issue them on
+ * one stream.
+ */
+#define MECDF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ecdf_esf_grid_noalloc(int d, int64_t N, const double *x, const void *y,
+                          const int64_t *M, const double *z, void *F, void *Fbar,
+                          int prec, void *stream);
+
+/*
  * ecdf_points -- generalized ECDF at the sample points themselves
  * (Section 2.2): F[j] = F_N(x_j) = (1/N) sum_i y_i 1{x_i <= x_j componentwise}.
  * Unlike the recursion's own output in Section 2.2, which leaves the point

@@ -131,6 +131,16 @@ int ecdf_esf_grid(int d, int64_t N, const double *x, const void *y,
     return grid_entry(d, N, x, y, M, z, F, Fbar, prec, stream);
 }
 
+int ecdf_esf_grid_noalloc(int d, int64_t N, const double *x, const void *y,
+                          const int64_t *M, const double *z, void *F, void *Fbar,
+                          int prec, void *stream) {
+    void *ws = nullptr;
+    size_t cap = 0;
+    MECDF_TRY(noalloc_scratch(&ws, &cap));
+    FixedWorkspace fixed(ws, cap);
+    return grid_entry(d, N, x, y, M, z, F, Fbar, prec, stream);
+}
+
 int ecdf_points(int d, int64_t N, const double *x, const void *y, void *F,
                 int prec, void *stream) {
     MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));

@@ -55,6 +55,20 @@ struct Status {
 // in flight.
 int workspace_reserve(size_t bytes, void **base);
 void workspace_release_all();
+
+// While set (for the calling thread), workspace_reserve hands out this fixed
+// region instead of the growing buffer and fails with MECDF_EUNSUPPORTED when
+// a call needs more, and upload_small copies straight from the caller's host
+// array: nothing is allocated.  Used by the entry points that allocate
+// nothing.
+void set_fixed_workspace(void *base, size_t bytes);
+struct FixedWorkspace {
+    FixedWorkspace(void *base, size_t bytes) { set_fixed_workspace(base, bytes); }
+    ~FixedWorkspace() { set_fixed_workspace(nullptr, 0); }
+};
+// The library's fixed device scratch array on the current device, for the
+// entry points that allocate nothing.
+int noalloc_scratch(void **base, size_t *bytes);
 int upload_small(const void *host, size_t bytes, void *dev_dst,
                  hipStream_t stream);
 

@@ -49,7 +49,28 @@ size_t workspace_limit() {
 void set_error(const std::string &msg) { g_last_error = msg; }
 const char *last_error() { return g_last_error.c_str(); }
 
+namespace {
+thread_local void *t_fixed_ws = nullptr;
+thread_local size_t t_fixed_bytes = 0;
+}  // namespace
+
+void set_fixed_workspace(void *base, size_t bytes) {
+    t_fixed_ws = base;
+    t_fixed_bytes = bytes;
+}
+
 int workspace_reserve(size_t bytes, void **base) {
+    if (t_fixed_ws) {
+        if (bytes > t_fixed_bytes) {
+            set_error("this call needs " + std::to_string(bytes) +
+                      " bytes of working memory; the fixed scratch array of the "
+                      "no-allocation entry point holds " +
+                      std::to_string(t_fixed_bytes));
+            return MECDF_EUNSUPPORTED;
+        }
+        *base = t_fixed_ws;
+        return MECDF_OK;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     int dev = 0;
     MECDF_TRY_HIP(hipGetDevice(&dev));
@@ -92,6 +113,12 @@ int upload_small(const void *host, size_t bytes, void *dev_dst,
                  hipStream_t stream) {
     if (bytes == 0)
         return MECDF_OK;
+    if (t_fixed_ws) {
+        // no staging buffer: HIP stages a copy from pageable memory itself
+        // and has read the host array when the call returns
+        MECDF_TRY_HIP(hipMemcpyAsync(dev_dst, host, bytes, hipMemcpyHostToDevice, stream));
+        return MECDF_OK;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     int dev = 0;
     MECDF_TRY_HIP(hipGetDevice(&dev));

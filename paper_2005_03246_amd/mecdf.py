@@ -39,6 +39,7 @@ _SIGS = {
     "ecdf_grid": [_I, _I64, _P, _P, _P, _P, _P, _I, _P],
     "esf_grid": [_I, _I64, _P, _P, _P, _P, _P, _I, _P],
     "ecdf_esf_grid": [_I, _I64, _P, _P, _P, _P, _P, _P, _I, _P],
+    "ecdf_esf_grid_noalloc": [_I, _I64, _P, _P, _P, _P, _P, _P, _I, _P],
     "ecdf_points": [_I, _I64, _P, _P, _P, _I, _P],
     "esf_points": [_I, _I64, _P, _P, _P, _I, _P],
     "kde_laplace": [_I, _I64, _P, _P, _I, _P, _P, _P, _I, _P],
@@ -121,11 +122,17 @@ def _grid_args(nodes):
     return ms, zs, tuple(int(len(v)) for v in nodes)
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
 def ecdf_esf_grid(x: torch.Tensor, nodes, y=None, prec="f64", want_ecdf=True,
-                  want_esf=True, stream=None):
+                  want_esf=True, stream=None, out=None, noalloc=False):
     """ECDF and/or ESF at every node of the rectilinear grid given by the
     per-axis node lists ``nodes`` (C ABI ``ecdf_esf_grid``).  Returns
-    (F, Fbar), each of shape (M_1, ..., M_d) or None when not requested."""
+    (F, Fbar), each of shape (M_1, ..., M_d) or None when not requested.
+    ``out`` = (F, Fbar) writes into caller tensors; ``noalloc`` calls
+    ``ecdf_esf_grid_noalloc`` (working memory in the library's fixed scratch
+    array; with ``out`` given, nothing is allocated on the device)."""
     x = _x(x)
     d, n = x.shape
     if len(nodes) != d:
@@ -134,11 +141,18 @@ def ecdf_esf_grid(x: torch.Tensor, nodes, y=None, prec="f64", want_ecdf=True,
     y = _y(y, n, p, x)
     ms, zs, shape = _grid_args(nodes)
     dt = _out_dtype(y, p)
-    F = torch.empty(shape, dtype=dt, device=x.device) if want_ecdf else None
-    Fb = torch.empty(shape, dtype=dt, device=x.device) if want_esf else None
-    rc = _lib.ecdf_esf_grid(d, n, _ptr(x), _ptr(y), ms, zs, _ptr(F), _ptr(Fb),
-                            p, _stream_ptr(stream))
-    _check(rc, "ecdf_esf_grid")
+    if out is not None:
+        F, Fb = out
+        for t in (F, Fb):
+            if t is not None and (t.dtype != dt or tuple(t.shape) != shape or
+                                  not t.is_contiguous() or t.device != x.device):
+                raise ValueError("out tensors must be contiguous %s of shape %s" % (dt, shape))
+    else:
+        F = torch.empty(shape, dtype=dt, device=x.device) if want_ecdf else None
+        Fb = torch.empty(shape, dtype=dt, device=x.device) if want_esf else None
+    fn = _lib.ecdf_esf_grid_noalloc if noalloc else _lib.ecdf_esf_grid
+    rc = fn(d, n, _ptr(x), _ptr(y), ms, zs, _ptr(F), _ptr(Fb), p, _stream_ptr(stream))
+    _check(rc, "ecdf_esf_grid_noalloc" if noalloc else "ecdf_esf_grid")
     return F, Fb
 
 
