@@ -15,10 +15,16 @@
  *
  * Weights.  y (or w) is a device array of N values.  With prec == MECDF_F64
  * it holds doubles and results are doubles; with prec == MECDF_F32C it holds
- * floats and results are floats, accumulated with Kahan compensation.  Where
- * an entry point accepts y == NULL, y is taken as 1 and the result is the raw
- * integer count (int64, no 1/N factor): the classical ECDF of Section 1
- * times N.
+ * floats and results are floats.  What F32C computes in float32 differs by
+ * path: the grid path bins and scans in float32 with Kahan compensation; the
+ * points path sums float32 weights with Kahan compensation; the kernel-sum
+ * path forms its exponentials and runs its scans in float32 without
+ * compensation (each scan level's result is added into float64 sums, and the
+ * decay over a long run is formed from the float64 coordinates of its ends
+ * rather than multiplied out), and its leave-one-out scores are float64.
+ * Where an entry point accepts y == NULL, y is taken as 1 and the result is
+ * the raw integer count (int64, no 1/N factor): the classical ECDF of
+ * Section 1 times N.
  *
  * Ownership.  The caller owns every buffer.  Device pointers must point to
  * memory on the current HIP device; host pointers (grid sizes, nodes,
@@ -54,7 +60,8 @@ enum {
     MECDF_EINVAL = -1,       /* invalid argument                          */
     MECDF_ENOMEM = -2,       /* workspace allocation failed or over limit */
     MECDF_EDEVICE = -3,      /* HIP runtime error                         */
-    MECDF_EUNSUPPORTED = -4  /* valid but outside the supported sizes     */
+    MECDF_EUNSUPPORTED = -4, /* valid but outside the supported sizes     */
+    MECDF_EIO = -5           /* a checkpoint file could not be read/written */
 };
 
 enum {
@@ -179,7 +186,7 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
  *   lcv[b] = (1/N) sum_j log fhat_{-j}(x_j),
  *   fhat_{-j} = 1/(2^d (N-1) prod_k h_{b,k}) sum_{i != j} w_i exp(...).
  *
- *   d     1..3
+ *   d     1..MECDF_MAX_DIM
  *   N     >= 2
  *   x     device d*N doubles
  *   w     device N doubles (float with MECDF_F32C) or NULL for w = 1
@@ -188,7 +195,13 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
  *   f     device nh*N results (double, or float with MECDF_F32C) or NULL
  *   lcv   device nh doubles or NULL
  *
- * Limits: N <= 2^28, and N <= 2^24 for d = 3 (MECDF_EUNSUPPORTED above).
+ * The logarithm in lcv is taken of the leave-one-out sum relative to the
+ * nearest other point, so the score stays finite where every kernel term is
+ * below the float64 range.  d = 1..3 run the recursion (O(N log^(d-1) N) per
+ * bandwidth); d = 4..6 evaluate every pair directly (O(N^2 d)).
+ *
+ * Limits: N <= 2^28, N <= 2^24 for d = 3 and N <= 2^20 for d >= 4
+ * (MECDF_EUNSUPPORTED above).
  */
 int kde_laplace(int d, int64_t N, const double *x, const void *w, int nh,
                 const double *h, void *f, double *lcv, int prec, void *stream);
@@ -221,12 +234,16 @@ typedef struct {
  * mecdf_kde_lcv_batched -- the likelihood CV score of kde_laplace for many
  * datasets and isotropic bandwidths: for dataset s, the nh[s] bandwidths
  * h[off_s .. off_s + nh[s]) (off_s = nh[0] + ... + nh[s-1]), each used on
- * every axis, give lcv[off_s + b] (device doubles).  sets, nh and h are host
- * arrays.  Datasets are processed in order on the stream; same errors as
- * kde_laplace.
+ * every axis, give lcv[off_s + b] (device doubles).  best (device, nsets
+ * ints, or NULL) receives each dataset's index b of its largest score (the
+ * lowest such b on ties; -1 when nh[s] = 0): the grid-search choice, and the
+ * label mecdf_bw_train takes.  sets, nh and h are host arrays.  Every
+ * dataset is checked before the first is run; datasets are then processed in
+ * order on the stream; same errors as kde_laplace.
  */
 int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
-                          const double *h, double *lcv, int prec, void *stream);
+                          const double *h, double *lcv, int *best, int prec,
+                          void *stream);
 
 /*
  * mecdf_bw_features -- 32 summary statistics per dataset (device floats,
@@ -267,6 +284,40 @@ int mecdf_mlp_grad(int B, const float *feat, const float *target,
 int mecdf_mlp_train(int B, const float *feat, const float *target, float *params,
                     float *adam, int steps, float lr, float wd, float *losses,
                     void *stream);
+
+/*
+ * mecdf_bw_train -- trains the network of mecdf_bw_select on grid labels.
+ * The target of dataset r is log(hgrid[label[r]]) - feat[r*32 + 12] (the
+ * grid optimum relative to the rule-of-thumb bandwidth); training runs
+ * `steps` full-batch steps of mecdf_mlp_train's Adam with decoupled weight
+ * decay.
+ *
+ *   B, feat     B >= 1 datasets, device float[B*32] from mecdf_bw_features
+ *   label       device int[B], grid indices in [0, nhg) (the best output of
+ *               mecdf_kde_lcv_batched); checked on the host (one wait)
+ *   nhg, hgrid  host, the ascending bandwidth grid
+ *   seed        seeds fresh parameters (He-style normals from a counter-based
+ *               generator: the same seed gives the same parameters)
+ *   params      device float[MECDF_MLP_PARAMS]; adam device
+ *               float[2*MECDF_MLP_PARAMS] (Adam moments)
+ *   losses      device float[steps] or NULL: the loss before each step
+ *   checkpoint  host path or NULL
+ *   step        in: Adam steps already taken on params/adam (0 = start
+ *               fresh from the seed, which overwrites params and adam);
+ *               out: the total after this call
+ *
+ * With a checkpoint path naming an existing file, the parameters, moments
+ * and step count are read from it (it must have been written with the same
+ * seed: MECDF_EINVAL otherwise; MECDF_EIO when it is not a whole
+ * checkpoint) and training continues from there, so that training in parts
+ * gives the same parameters as in one call.  When a path is given the file is
+ * written (replaced atomically) after the steps, and the call waits for the
+ * device.
+ */
+int mecdf_bw_train(int B, const float *feat, const int *label, int nhg,
+                   const double *hgrid, int steps, float lr, float wd,
+                   uint64_t seed, float *params, float *adam, float *losses,
+                   const char *checkpoint, int64_t *step, void *stream);
 
 /*
  * mecdf_bw_select -- likelihood-CV bandwidth on an ascending grid of nhg

@@ -30,31 +30,34 @@ def to_device(sets):
     return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in sets]
 
 
+def grid_search_device(dsets, hgrid):
+    """Exact LCV at every grid bandwidth: (best index per dataset as an int32
+    GPU tensor, the score rows as a list of GPU tensors)."""
+    res, best = mecdf.kde_lcv_batched(dsets, [hgrid] * len(dsets), want_best=True)
+    return best, res
+
+
 def grid_search(dsets, hgrid):
-    """Exact LCV at every grid bandwidth; returns (argmax index, score matrix)."""
-    res = mecdf.kde_lcv_batched(dsets, [hgrid] * len(dsets))
-    mat = torch.stack(res).cpu().numpy()
-    return np.argmax(mat, axis=1), mat
-
-
-def targets(feat, hidx, hgrid):
-    """Network target: log of the grid optimum minus the rule-of-thumb log h0."""
-    return torch.tensor(np.log(np.asarray(hgrid))[hidx], dtype=torch.float32,
-                        device=feat.device) - feat[:, 12]
+    """Exact LCV at every grid bandwidth; returns (best index, score matrix)
+    as numpy arrays copied from the library's outputs."""
+    best, res = grid_search_device(dsets, hgrid)
+    return best.cpu().numpy().astype(np.int64), torch.stack(res).cpu().numpy()
 
 
 def train(dsets, hgrid, steps: int = 2000, lr: float = 1e-3, wd: float = 1.0, seed: int = 0,
-          hidx=None):
-    """Labels from the exact grid search, then full-batch Adam with decoupled
-    weight decay on the device.  Returns (params, losses, labels)."""
+          hidx=None, checkpoint=None):
+    """Labels from the exact grid search (the library's device argmax), then
+    full-batch Adam with decoupled weight decay, all in the library
+    (mecdf_bw_train; with a checkpoint path, training resumes from the file
+    and rewrites it).  Returns (params, losses, labels)."""
     feat = mecdf.bw_features(dsets)
     if hidx is None:
-        hidx, _ = grid_search(dsets, hgrid)
-    t = targets(feat, hidx, hgrid)
-    params = init_params(seed)
-    adam = torch.zeros((2 * mecdf.MLP_PARAMS,), dtype=torch.float32, device="cuda")
-    losses = mecdf.mlp_train(feat, t, params, adam, steps, lr, wd)
-    return params, losses.cpu().numpy(), hidx
+        label, _ = grid_search_device(dsets, hgrid)
+    else:
+        label = torch.as_tensor(np.asarray(hidx), dtype=torch.int32).cuda()
+    params, _, losses, _ = mecdf.bw_train(feat, label, hgrid, steps, lr, wd, seed,
+                                          checkpoint=checkpoint)
+    return params, losses.cpu().numpy(), label.cpu().numpy().astype(np.int64)
 
 
 def select(dsets, params, hgrid, mode=mecdf.BW_EXTEND):

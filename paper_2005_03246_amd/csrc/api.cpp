@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <functional>
 #include <string>
 #include <vector>
@@ -26,6 +28,11 @@ int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, fl
              hipStream_t s);
 int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps,
               float lr, float wd, float *losses, hipStream_t s);
+int mlp_init(uint64_t seed, float *P, float *adam, hipStream_t s);
+int bw_train_steps(int B, const float *feat, const int *label, int nhg, const double *hgrid,
+                   int steps, float lr, float wd, float *P, float *adam, float *losses,
+                   int64_t t0, hipStream_t s);
+int lcv_argmax(const double *score, const int *cnt, int nsets, int *best, hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -102,6 +109,8 @@ const char *mecdf_strerror(int code) {
         return "HIP runtime error";
     case MECDF_EUNSUPPORTED:
         return "unsupported size or option";
+    case MECDF_EIO:
+        return "file input/output error";
     default:
         return "unknown error code";
     }
@@ -204,14 +213,16 @@ static int check_sets(const mecdf_dataset *sets, int nsets) {
             return fail(MECDF_EINVAL, "dataset dimension must be 1..3");
         if (sets[i].N < 2 || sets[i].x == nullptr)
             return fail(MECDF_EINVAL, "datasets need N >= 2 points");
-        if (sets[i].N >= (int64_t(1) << 31))
-            return fail(MECDF_EUNSUPPORTED, "dataset too large");
+        // the kernel-sum limits, checked for every dataset before any is run
+        if (sets[i].N > (int64_t(1) << 28) || (sets[i].d == 3 && sets[i].N > (int64_t(1) << 24)))
+            return fail(MECDF_EUNSUPPORTED,
+                        "dataset too large: kernel sums support N <= 2^28 (2^24 for d = 3)");
     }
     return MECDF_OK;
 }
 
 int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
-                          const double *h, double *lcv, int prec, void *stream) {
+                          const double *h, double *lcv, int *best, int prec, void *stream) {
     MECDF_TRY(check_sets(sets, nsets));
     if (nh == nullptr || h == nullptr || lcv == nullptr)
         return fail(MECDF_EINVAL, "nh, h and lcv are required");
@@ -238,6 +249,8 @@ int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
         }
         off += nh[i];
     }
+    if (best)
+        MECDF_TRY(lcv_argmax(lcv, nh, nsets, best, (hipStream_t)stream));
     return MECDF_OK;
 }
 
@@ -269,6 +282,148 @@ int mecdf_mlp_train(int B, const float *feat, const float *target, float *params
         return fail(MECDF_EINVAL, "mlp_train: bad arguments");
     return mlp_train(B, feat, target, params, adam, steps, lr, wd, losses,
                      (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ checkpoints
+// File layout (host byte order): "MECDFBW1", uint32 version (1), uint32
+// parameter count, uint64 seed, int64 step count, float parameters, float
+// Adam moments (first, then second), uint64 FNV-1a hash of everything before
+// it.  Written to "<path>.tmp" and renamed over the path.
+namespace {
+const char kCkptMagic[8] = {'M', 'E', 'C', 'D', 'F', 'B', 'W', '1'};
+
+uint64_t fnv1a(const unsigned char *p, size_t n, uint64_t h = 0xcbf29ce484222325ull) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, nparams;
+    uint64_t seed;
+    int64_t step;
+};
+
+int ckpt_write(const char *path, uint64_t seed, int64_t step, const std::vector<float> &p,
+               const std::vector<float> &m) {
+    CkptHeader h;
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.nparams = (uint32_t)p.size();
+    h.seed = seed;
+    h.step = step;
+    uint64_t hash = fnv1a((const unsigned char *)&h, sizeof(h));
+    hash = fnv1a((const unsigned char *)p.data(), sizeof(float) * p.size(), hash);
+    hash = fnv1a((const unsigned char *)m.data(), sizeof(float) * m.size(), hash);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f)
+        return fail(MECDF_EIO, std::string("checkpoint: cannot write ") + tmp);
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+              std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size() &&
+              std::fwrite(m.data(), sizeof(float), m.size(), f) == m.size() &&
+              std::fwrite(&hash, sizeof(hash), 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(MECDF_EIO, std::string("checkpoint: writing ") + path + " failed");
+    }
+    return MECDF_OK;
+}
+
+// found = false when the file does not exist; a file that exists must be whole
+int ckpt_read(const char *path, uint64_t seed, std::vector<float> &p, std::vector<float> &m,
+              int64_t &step, bool &found) {
+    found = false;
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return MECDF_OK;
+    CkptHeader h;
+    uint64_t hash = 0;
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, kCkptMagic, 8) == 0 &&
+              h.version == 1 && h.nparams == (uint32_t)p.size();
+    ok = ok && std::fread(p.data(), sizeof(float), p.size(), f) == p.size() &&
+         std::fread(m.data(), sizeof(float), m.size(), f) == m.size() &&
+         std::fread(&hash, sizeof(hash), 1, f) == 1;
+    std::fclose(f);
+    if (ok) {
+        uint64_t want = fnv1a((const unsigned char *)&h, sizeof(h));
+        want = fnv1a((const unsigned char *)p.data(), sizeof(float) * p.size(), want);
+        want = fnv1a((const unsigned char *)m.data(), sizeof(float) * m.size(), want);
+        ok = want == hash;
+    }
+    if (!ok)
+        return fail(MECDF_EIO, std::string("checkpoint: ") + path +
+                                   " is not a whole bandwidth-network checkpoint");
+    if (h.seed != seed)
+        return fail(MECDF_EINVAL, std::string("checkpoint: ") + path +
+                                      " was written with another seed");
+    if (h.step < 0)
+        return fail(MECDF_EIO, std::string("checkpoint: ") + path + " has a negative step count");
+    step = h.step;
+    found = true;
+    return MECDF_OK;
+}
+
+bool grid_ok(int nhg, const double *hgrid) {
+    if (nhg < 1 || hgrid == nullptr)
+        return false;
+    for (int j = 0; j < nhg; ++j)
+        if (!(hgrid[j] > 0.0) || !std::isfinite(hgrid[j]) || (j > 0 && !(hgrid[j] > hgrid[j - 1])))
+            return false;
+    return true;
+}
+}  // namespace
+
+int mecdf_bw_train(int B, const float *feat, const int *label, int nhg, const double *hgrid,
+                   int steps, float lr, float wd, uint64_t seed, float *params, float *adam,
+                   float *losses, const char *checkpoint, int64_t *step, void *stream) {
+    if (B < 1 || !feat || !label || !params || !adam || !step || steps < 0 || !(lr > 0.f) ||
+        !(wd >= 0.f) || !std::isfinite(lr) || !std::isfinite(wd) || *step < 0)
+        return fail(MECDF_EINVAL, "bw_train: bad arguments");
+    if (!grid_ok(nhg, hgrid))
+        return fail(MECDF_EINVAL, "bw_train: hgrid must be positive, finite and ascending");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> hl((size_t)B);
+    MECDF_TRY_HIP(hipMemcpyAsync(hl.data(), label, sizeof(int) * (size_t)B,
+                                 hipMemcpyDeviceToHost, s));
+    MECDF_TRY_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < B; ++r)
+        if (hl[r] < 0 || hl[r] >= nhg)
+            return fail(MECDF_EINVAL, "bw_train: a label is outside the bandwidth grid");
+    int64_t t0 = *step;
+    bool found = false;
+    if (checkpoint) {
+        std::vector<float> p(MECDF_MLP_PARAMS), m(2 * (size_t)MECDF_MLP_PARAMS);
+        int64_t fs = 0;
+        MECDF_TRY(ckpt_read(checkpoint, seed, p, m, fs, found));
+        if (found) {
+            MECDF_TRY_HIP(hipMemcpyAsync(params, p.data(), sizeof(float) * p.size(),
+                                         hipMemcpyHostToDevice, s));
+            MECDF_TRY_HIP(hipMemcpyAsync(adam, m.data(), sizeof(float) * m.size(),
+                                         hipMemcpyHostToDevice, s));
+            MECDF_TRY_HIP(hipStreamSynchronize(s));  // p and m go out of scope
+            t0 = fs;
+        }
+    }
+    if (!found && t0 == 0)
+        MECDF_TRY(mlp_init(seed, params, adam, s));
+    MECDF_TRY(bw_train_steps(B, feat, label, nhg, hgrid, steps, lr, wd, params, adam, losses, t0,
+                             s));
+    *step = t0 + steps;
+    if (checkpoint) {
+        std::vector<float> p(MECDF_MLP_PARAMS), m(2 * (size_t)MECDF_MLP_PARAMS);
+        MECDF_TRY_HIP(hipMemcpyAsync(p.data(), params, sizeof(float) * p.size(),
+                                     hipMemcpyDeviceToHost, s));
+        MECDF_TRY_HIP(hipMemcpyAsync(m.data(), adam, sizeof(float) * m.size(),
+                                     hipMemcpyDeviceToHost, s));
+        MECDF_TRY_HIP(hipStreamSynchronize(s));
+        MECDF_TRY(ckpt_write(checkpoint, seed, *step, p, m));
+    }
+    return MECDF_OK;
 }
 
 int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, int nhg,

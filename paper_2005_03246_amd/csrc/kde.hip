@@ -1856,6 +1856,40 @@ static int kde_direct_t(int d, int64_t n, const double *x, const WT *w0in, const
     return MECDF_OK;
 }
 
+// best[s] = the index in [0, cnt[s]) of the largest of score[off[s] ..
+// off[s] + cnt[s]), the lowest index among equal ones (NaN counts as the
+// smallest), -1 for an empty list; one thread per list.
+__global__ void k_seg_argmax(const double *__restrict__ score, const int64_t *__restrict__ off,
+                             int nsets, int *__restrict__ best) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nsets)
+        return;
+    const int64_t a = off[i], n = off[i + 1] - off[i];
+    int bi = n > 0 ? 0 : -1;
+    double bv = n > 0 ? score[a] : 0.0;
+    for (int64_t j = 1; j < n; ++j) {
+        const double v = score[a + j];
+        if (v > bv || (bv != bv && v == v)) {
+            bv = v;
+            bi = (int)j;
+        }
+    }
+    best[i] = bi;
+}
+
+int lcv_argmax(const double *score, const int *cnt, int nsets, int *best, hipStream_t s) {
+    std::vector<int64_t> off((size_t)nsets + 1, 0);
+    for (int i = 0; i < nsets; ++i)
+        off[i + 1] = off[i] + cnt[i];
+    void *wsb = nullptr;
+    MECDF_TRY(workspace_reserve(sizeof(int64_t) * off.size(), &wsb));
+    MECDF_TRY(upload_small(off.data(), sizeof(int64_t) * off.size(), wsb, s));
+    hipLaunchKernelGGL(k_seg_argmax, dim3((unsigned)ceil_div(nsets, 256)), dim3(256), 0, s, score,
+                       (const int64_t *)wsb, nsets, best);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
 // Leave-one-out log-likelihood scores of one unweighted sample for the
 // bandwidths h[b0 .. b0+nb) of a list of nh (d entries each), batches chosen
 // by source; the structure over the sample is built once.

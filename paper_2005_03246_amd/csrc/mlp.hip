@@ -427,6 +427,51 @@ __global__ void k_mlp_adam(float *__restrict__ P, const float *__restrict__ G,
     P[i] = p - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p);
 }
 
+// Initial parameters from a seed: He-style normals for W1 (sd sqrt(2/32)) and
+// W2 (sd sqrt(2/128)), w3 with sd 0.1 sqrt(1/128), zero biases.  Each entry
+// draws its own pair of uniforms from a counter-based generator (SplitMix64
+// of seed and the entry's index), turned into a normal by Box-Muller.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_mlp_init(float *__restrict__ P, uint64_t seed) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= kParams)
+        return;
+    const uint64_t a = splitmix64(seed ^ splitmix64(2 * (uint64_t)i + 1));
+    const uint64_t b = splitmix64(a);
+    const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;  // (0, 1]
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;          // [0, 1)
+    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    double sd = 0.0;
+    if (i < ob1)
+        sd = sqrt(2.0 / kIn);
+    else if (i >= oW2 && i < ob2)
+        sd = sqrt(2.0 / kH);
+    else if (i >= ow3 && i < ob3)
+        sd = 0.1 * sqrt(1.0 / kH);
+    P[i] = (float)(sd * z);
+}
+
+// Regression targets of the proposal: T[r] = log(h of the label's grid index)
+// minus the rule-of-thumb log h0 (feature 12).
+__global__ void k_bw_targets(const float *__restrict__ feat, const int *__restrict__ label,
+                             const double *__restrict__ hgrid, int B, float *__restrict__ T) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r < B)
+        T[r] = (float)(log(hgrid[label[r]]) - (double)feat[(int64_t)r * kIn + 12]);
+}
+
+__global__ void k_fill_f32(float *__restrict__ a, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        a[i] = v;
+}
+
 // ------------------------------------------------------------ host side
 struct MlpWork {
     MlpBufs b;
@@ -434,7 +479,8 @@ struct MlpWork {
     int Bp, ntile, nchunk;
 };
 
-static int mlp_work(int B, MlpWork &w) {
+// extra: bytes of caller scratch carved after the network's buffers (*extra_out)
+static int mlp_work(int B, MlpWork &w, size_t extra = 0, void **extra_out = nullptr) {
     w.Bp = (int)ceil_div(B, 16) * 16;
     w.ntile = w.Bp / 16;
     w.nchunk = (int)ceil_div(w.Bp, kKc);
@@ -452,6 +498,7 @@ static int mlp_work(int B, MlpWork &w) {
     pl.add<float>((size_t)w.nchunk * kH * kIn);
     pl.add<float>((size_t)w.nchunk * kH * kH);
     pl.add<float>((size_t)w.Bp);
+    pl.add<char>(extra);
     void *base = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &base));
     Arena a;
@@ -469,6 +516,9 @@ static int mlp_work(int B, MlpWork &w) {
     w.pW1 = a.take<float>((size_t)w.nchunk * kH * kIn);
     w.pW2 = a.take<float>((size_t)w.nchunk * kH * kH);
     w.sq = a.take<float>((size_t)w.Bp);
+    char *ex = a.take<char>(extra);
+    if (extra_out)
+        *extra_out = ex;
     return MECDF_OK;
 }
 
@@ -515,12 +565,15 @@ int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, fl
     return MECDF_OK;
 }
 
-int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps, float lr,
-              float wd, float *losses, hipStream_t s) {
-    MlpWork w;
-    MECDF_TRY(mlp_work(B, w));
+// Adam steps t0 + 1 .. t0 + steps (the bias corrections continue from t0).
+static int mlp_train_w(MlpWork &w, int B, const float *X, const float *T, float *P, float *adam,
+                       int steps, float lr, float wd, float *losses, int64_t t0, hipStream_t s) {
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     double p1 = 1.0, p2 = 1.0;
+    for (int64_t t = 0; t < t0; ++t) {
+        p1 *= b1;
+        p2 *= b2;
+    }
     for (int t = 0; t < steps; ++t) {
         MECDF_TRY(mlp_forward_w(w, B, X, P, s));
         MECDF_TRY(mlp_grad_w(w, B, T, P, losses ? losses + t : nullptr, s));
@@ -532,6 +585,41 @@ int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int 
         MECDF_LAUNCH_CHECK();
     }
     return MECDF_OK;
+}
+
+int mlp_train(int B, const float *X, const float *T, float *P, float *adam, int steps, float lr,
+              float wd, float *losses, hipStream_t s) {
+    MlpWork w;
+    MECDF_TRY(mlp_work(B, w));
+    return mlp_train_w(w, B, X, T, P, adam, steps, lr, wd, losses, 0, s);
+}
+
+// Fresh parameters from the seed and zero Adam moments.
+int mlp_init(uint64_t seed, float *P, float *adam, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_init, dim3((unsigned)ceil_div(kParams, 256)), dim3(256), 0, s, P,
+                       seed);
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)ceil_div(2 * kParams, 256)), dim3(256), 0, s,
+                       adam, (int64_t)2 * kParams, 0.f);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
+// Training on grid labels: targets formed on the device from the labels and
+// the grid (host), then Adam steps t0 + 1 .. t0 + steps.
+int bw_train_steps(int B, const float *feat, const int *label, int nhg, const double *hgrid,
+                   int steps, float lr, float wd, float *P, float *adam, float *losses,
+                   int64_t t0, hipStream_t s) {
+    MlpWork w;
+    void *extra = nullptr;
+    const size_t tbytes = ((sizeof(float) * (size_t)B + 255) / 256) * 256;
+    MECDF_TRY(mlp_work(B, w, tbytes + sizeof(double) * (size_t)nhg, &extra));
+    float *T = (float *)extra;
+    double *hg = (double *)((char *)extra + tbytes);
+    MECDF_TRY(upload_small(hgrid, sizeof(double) * (size_t)nhg, hg, s));
+    hipLaunchKernelGGL(k_bw_targets, dim3((unsigned)ceil_div(B, 256)), dim3(256), 0, s, feat,
+                       label, hg, B, T);
+    MECDF_LAUNCH_CHECK();
+    return mlp_train_w(w, B, feat, T, P, adam, steps, lr, wd, losses, t0, s);
 }
 
 int bw_features(const mecdf_dataset *sets, int nsets, float *feat, hipStream_t s) {

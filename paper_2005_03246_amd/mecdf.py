@@ -28,6 +28,7 @@ MECDF_EINVAL = -1
 MECDF_ENOMEM = -2
 MECDF_EDEVICE = -3
 MECDF_EUNSUPPORTED = -4
+MECDF_EIO = -5
 MECDF_F64 = 0
 MECDF_F32C = 1
 
@@ -307,7 +308,7 @@ class _Dataset(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int64), ("x", ctypes.c_void_p)]
 
 
-_lib.mecdf_kde_lcv_batched.argtypes = [_P, _I, _P, _P, _P, _I, _P]
+_lib.mecdf_kde_lcv_batched.argtypes = [_P, _I, _P, _P, _P, _P, _I, _P]
 _lib.mecdf_kde_lcv_batched.restype = _I
 _lib.mecdf_bw_features.argtypes = [_P, _I, _P, _P]
 _lib.mecdf_bw_features.restype = _I
@@ -319,6 +320,9 @@ _lib.mecdf_mlp_train.argtypes = [_I, _P, _P, _P, _P, _I, ctypes.c_float, ctypes.
 _lib.mecdf_mlp_train.restype = _I
 _lib.mecdf_bw_select.argtypes = [_P, _I, _P, _I, _P, _I, _P, _P, _P, _P]
 _lib.mecdf_bw_select.restype = _I
+_lib.mecdf_bw_train.argtypes = [_I, _P, _P, _I, _P, _I, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_uint64, _P, _P, _P, ctypes.c_char_p, _P, _P]
+_lib.mecdf_bw_train.restype = _I
 
 
 def _sets(datasets):
@@ -333,23 +337,26 @@ def _sets(datasets):
     return arr, keep
 
 
-def kde_lcv_batched(datasets, hs, prec="f64", stream=None):
+def kde_lcv_batched(datasets, hs, prec="f64", stream=None, want_best=False):
     """LCV scores for a list of (d, N) GPU datasets; hs[i] is the list of
     isotropic bandwidths of dataset i.  Returns a list of (len(hs[i]),) float64
-    GPU tensors (C ABI ``mecdf_kde_lcv_batched``)."""
+    GPU tensors (C ABI ``mecdf_kde_lcv_batched``), and with want_best also the
+    (nsets,) int32 GPU tensor of each dataset's best index."""
     arr, keep = _sets(datasets)
     nh = (ctypes.c_int * len(datasets))(*[len(h) for h in hs])
     flat = [float(v) for h in hs for v in h]
     hv = (ctypes.c_double * max(1, len(flat)))(*flat)
     out = torch.empty((max(1, len(flat)),), dtype=torch.float64, device=keep[0].device)
+    best = torch.empty((len(datasets),), dtype=torch.int32, device=keep[0].device) \
+        if want_best else None
     _check(_lib.mecdf_kde_lcv_batched(ctypes.addressof(arr), len(datasets), nh, hv,
-                                      _ptr(out), _prec(prec), _stream_ptr(stream)),
+                                      _ptr(out), _ptr(best), _prec(prec), _stream_ptr(stream)),
            "mecdf_kde_lcv_batched")
     res, off = [], 0
     for h in hs:
         res.append(out[off:off + len(h)])
         off += len(h)
-    return res
+    return (res, best) if want_best else res
 
 
 def bw_features(datasets, stream=None):
@@ -397,6 +404,36 @@ def mlp_train(feat, target, params, adam, steps, lr, wd=0.0, stream=None):
                                 _ptr(adam), int(steps), float(lr), float(wd), _ptr(losses),
                                 _stream_ptr(stream)), "mecdf_mlp_train")
     return losses[:steps]
+
+
+def bw_train(feat, label, hgrid, steps, lr, wd=0.0, seed=0, params=None, adam=None,
+             step=0, checkpoint=None, stream=None):
+    """Train the proposal network on grid labels (C ABI ``mecdf_bw_train``).
+    feat: (B, 32) float32 GPU features; label: (B,) int32 GPU grid indices.
+    params / adam: float32 GPU vectors (allocated when None; then step must
+    be 0, so that they are initialised from the seed).  Returns (params,
+    adam, losses, total steps)."""
+    feat = _f32(feat)
+    if not (label.is_cuda and label.dtype == torch.int32):
+        raise TypeError("label must be an int32 GPU tensor")
+    label = label.contiguous()
+    dev = feat.device
+    if params is None:
+        params = torch.empty((MLP_PARAMS,), dtype=torch.float32, device=dev)
+    if adam is None:
+        adam = torch.empty((2 * MLP_PARAMS,), dtype=torch.float32, device=dev)
+    for t in (params, adam):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("params and adam must be contiguous float32 GPU tensors")
+    hg = (ctypes.c_double * len(hgrid))(*[float(v) for v in hgrid])
+    losses = torch.empty((max(1, steps),), dtype=torch.float32, device=dev)
+    st = ctypes.c_int64(int(step))
+    ck = None if checkpoint is None else os.fsencode(checkpoint)
+    _check(_lib.mecdf_bw_train(feat.shape[0], _ptr(feat), _ptr(label), len(hgrid), hg,
+                               int(steps), float(lr), float(wd), int(seed), _ptr(params),
+                               _ptr(adam), _ptr(losses), ck, ctypes.byref(st),
+                               _stream_ptr(stream)), "mecdf_bw_train")
+    return params, adam, losses[:steps], int(st.value)
 
 
 BW_EXTEND = 0

@@ -81,11 +81,30 @@ def test_host_validation_errors(lib):
     h = (ctypes.c_double * 2)(0.1, 0.1)
     hneg = (ctypes.c_double * 2)(0.1, -0.1)
     assert kde(2, 1, fake, None, 1, h, fake, None, 0, None) == -1   # N < 2
-    assert kde(4, 10, fake, None, 1, h, fake, None, 0, None) == -1  # d > 3
+    assert kde(7, 10, fake, None, 1, h, fake, None, 0, None) == -1  # d > 6
+    h4 = (ctypes.c_double * 4)(0.1, 0.1, 0.1, 0.1)
+    assert kde(4, (1 << 20) + 1, fake, None, 1, h4, fake, None, 0, None) == -4  # direct sums
+    assert kde(3, (1 << 24) + 1, fake, None, 1, h4, fake, None, 0, None) == -4
     assert kde(2, 10, fake, None, 0, h, fake, None, 0, None) == -1
     assert kde(2, 10, fake, None, 1, hneg, fake, None, 0, None) == -1
     assert kde(2, 10, fake, None, 1, h, None, None, 0, None) == -1
     kreg = _c(lib, "kreg_laplace", [I, I64, P, P, I, P, P, P, I, P])
     assert kreg(2, 10, fake, None, 1, h, fake, None, 0, None) == -1  # y NULL
+    train = _c(lib, "mecdf_bw_train", [I, P, P, I, P, I, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_uint64, P, P, P, ctypes.c_char_p, P, P])
+    hg = (ctypes.c_double * 3)(0.1, 0.2, 0.4)
+    hg_bad = (ctypes.c_double * 3)(0.1, 0.4, 0.2)
+    st = ctypes.c_int64(0)
+    ref = ctypes.byref(st)
+    assert train(0, fake, fake, 3, hg, 10, 1e-3, 0.0, 1, fake, fake, None, None, ref, None) == -1
+    assert train(4, fake, fake, 3, hg, 10, 0.0, 0.0, 1, fake, fake, None, None, ref, None) == -1
+    assert train(4, fake, fake, 3, hg, 10, 1e-3, -1.0, 1, fake, fake, None, None, ref, None) == -1
+    assert train(4, fake, fake, 3, hg_bad, 10, 1e-3, 0.0, 1, fake, fake, None, None, ref,
+                 None) == -1
+    assert train(4, fake, None, 3, hg, 10, 1e-3, 0.0, 1, fake, fake, None, None, ref, None) == -1
+    assert train(4, fake, fake, 3, hg, 10, 1e-3, 0.0, 1, fake, fake, None, None, None, None) == -1
+    batched = _c(lib, "mecdf_kde_lcv_batched", [P, I, P, P, P, P, I, P])
+    assert batched(None, 0, None, None, fake, None, 0, None) == -1
     lib.mecdf_strerror.restype = ctypes.c_char_p
     assert lib.mecdf_strerror(-1) == b"invalid argument"
+    assert lib.mecdf_strerror(-5) == b"file input/output error"

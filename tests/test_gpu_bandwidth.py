@@ -172,3 +172,67 @@ def test_learned_selection_vs_grid_search(lib):
     gap_rot = mat[rows, gidx] - rlcv
     assert gap_learned.mean() < gap_rot.mean()
     assert np.mean(gap_learned <= lim) >= np.mean(gap_rot <= lim)
+
+
+def test_batched_best_index_is_the_argmax(lib):
+    sets = datagen.config5(count=7, log2n_lo=8, log2n_hi=10, seed=23)
+    hs = [bandwidth.hgrid64()[::3]] * 6 + [[0.3]]
+    rows, best = lib.kde_lcv_batched(bandwidth.to_device(sets), hs, want_best=True)
+    best = best.cpu().numpy()
+    for r, b in zip(rows, best):
+        r = r.cpu().numpy()
+        assert b == int(np.argmax(r))
+
+
+def test_bw_train_from_seed_and_checkpoint_resume(lib, tmp_path):
+    """Training through the C ABI: fresh parameters come from the seed alone;
+    60 steps in one call equal 25 steps written to a checkpoint and 35 more
+    resumed from it, bit for bit (parameters, moments and losses); the first
+    loss is the network's loss on the targets log h[label] - log h0."""
+    hgrid = bandwidth.hgrid64()
+    dsets = bandwidth.to_device(datagen.config5(count=48, log2n_lo=9, log2n_hi=11, seed=31))
+    feat = lib.bw_features(dsets)
+    label, _ = bandwidth.grid_search_device(dsets, hgrid)
+    p0, a0, _, n0 = lib.bw_train(feat, label, hgrid, 0, 1e-3, 0.5, seed=9)
+    q0, _, _, _ = lib.bw_train(feat, label, hgrid, 0, 1e-3, 0.5, seed=9)
+    r0, _, _, _ = lib.bw_train(feat, label, hgrid, 0, 1e-3, 0.5, seed=10)
+    assert n0 == 0 and torch.equal(p0, q0) and not torch.equal(p0, r0)
+    assert torch.all(a0 == 0)
+    w1 = p0[omlp.OW1:omlp.OB1].cpu().numpy()
+    assert abs(w1.std() / np.sqrt(2.0 / 32) - 1) < 0.05
+    assert torch.all(p0[omlp.OB1:omlp.OW2] == 0) and float(p0[omlp.OB3]) == 0.0
+    # the targets the library forms on the device
+    t = (np.log(hgrid)[label.cpu().numpy()] - feat[:, 12].cpu().numpy().astype(np.float64))
+    _, l_ref = lib.mlp_grad(feat, torch.from_numpy(t.astype(np.float32)).cuda(), p0)
+
+    pf, af, lf, nf = lib.bw_train(feat, label, hgrid, 60, 2e-3, 0.5, seed=9)
+    assert nf == 60
+    assert float(lf[0]) == pytest.approx(float(l_ref), rel=1e-6)
+    assert float(lf[-1]) < float(lf[0])
+    ck = str(tmp_path / "bw.ckpt")
+    _, _, l1, n1 = lib.bw_train(feat, label, hgrid, 25, 2e-3, 0.5, seed=9, checkpoint=ck)
+    assert n1 == 25
+    p2, a2, l2, n2 = lib.bw_train(feat, label, hgrid, 35, 2e-3, 0.5, seed=9, checkpoint=ck)
+    assert n2 == 60
+    assert torch.equal(p2, pf) and torch.equal(a2, af)
+    assert torch.equal(torch.cat([l1, l2]), lf)
+    # resuming from memory (no file) continues the same way
+    p3, a3, _, n3 = lib.bw_train(feat, label, hgrid, 25, 2e-3, 0.5, seed=9)
+    p3, a3, _, n3 = lib.bw_train(feat, label, hgrid, 35, 2e-3, 0.5, seed=9, params=p3,
+                                 adam=a3, step=n3)
+    assert n3 == 60 and torch.equal(p3, pf)
+    # a checkpoint of another seed, or a damaged one, is refused
+    with pytest.raises(lib.MecdfError) as e:
+        lib.bw_train(feat, label, hgrid, 1, 2e-3, 0.5, seed=8, checkpoint=ck)
+    assert e.value.code == lib.MECDF_EINVAL
+    raw = bytearray(open(ck, "rb").read())
+    raw[100] ^= 0xFF
+    bad = str(tmp_path / "bad.ckpt")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(lib.MecdfError) as e:
+        lib.bw_train(feat, label, hgrid, 1, 2e-3, 0.5, seed=9, checkpoint=bad)
+    assert e.value.code == lib.MECDF_EIO
+    # labels outside the grid are refused
+    with pytest.raises(lib.MecdfError) as e:
+        lib.bw_train(feat, label + 64, hgrid, 1, 2e-3, 0.5, seed=9)
+    assert e.value.code == lib.MECDF_EINVAL
