@@ -170,8 +170,36 @@ def _time_calls(fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+def _profiled(fn, cold=False):
+    """Per-kernel-group (total ms, launches) of one call of fn, from the
+    library's HIP events on the launch stream (cold: a 1 GiB buffer is read
+    before each group so that its inputs come from HBM)."""
+    import torch
+
+    from paper_2005_03246_amd import mecdf
+
+    torch.cuda.synchronize()
+    mecdf.profile_reset()
+    mecdf.profile_enable(True, cold=cold)
+    fn()
+    torch.cuda.synchronize()
+    mecdf.profile_enable(False)
+    return mecdf.profile_collect()
+
+
+def _rate(kern, name, bytes_per_launch):
+    """Achieved GB/s of a kernel group from (total ms, launches)."""
+    ms, n = kern.get(name, (0.0, 0))
+    if not n:
+        return None
+    gbs = bytes_per_launch / (ms / n * 1e-3) / 1e9
+    return {"launches": n, "avg_launch_ms": ms / n, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
 def secondary():
-    """Per-call times of the other workloads (points, kernel sums); figures of
+    """Per-call times of the other workloads (points, kernel sums) and the
+    per-kernel HBM fractions of their main kernels, warm and cold; figures of
     the same library, reported beside the headline grid measurement."""
     import numpy as np
     import torch
@@ -179,48 +207,76 @@ def secondary():
     from paper_2005_03246_amd import datagen, mecdf
 
     out = {}
+    # C1: d = 2, N = 4096 counts, by the direct kernel (the default at this
+    # size) and by the divide-and-conquer recursion
     x = torch.from_numpy(datagen.config1()).cuda()
     ms = _time_calls(lambda: (mecdf.ecdf_points(x), mecdf.esf_points(x)), 20, 3)
-    out["points_d2_N4096_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
-                                     "Gpoint-evals/s": 2 * 4096 / (ms * 1e-3) / 1e9,
-                                     "note": "latency bound (96 KB in and out); no roofline"}
+    os.environ["MECDF_POINTS_DIRECT_MAX"] = "0"
+    try:
+        ms_dc = _time_calls(lambda: (mecdf.ecdf_points(x), mecdf.esf_points(x)), 20, 3)
+    finally:
+        del os.environ["MECDF_POINTS_DIRECT_MAX"]
+    out["points_d2_N4096_counts"] = {
+        "ms_per_call_ecdf_plus_esf": ms, "Gpoint-evals/s": 2 * 4096 / (ms * 1e-3) / 1e9,
+        "divide_and_conquer_ms_per_call_ecdf_plus_esf": ms_dc,
+        "note": "latency bound (96 KB in and out); no roofline"}
+    # C3: d = 4, N = 2^22 tied, counts
     x3 = torch.from_numpy(datagen.config3()).cuda()
     n3 = x3.shape[1]
     ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
-    # merge levels of the last coordinate (all but the last level of each
-    # sub-problem): per item, the 8-byte compact item (last coordinate, id and
-    # side bits) and the 8-byte pair of 32-bit prefix and carried count, read
-    # and written once
-    torch.cuda.synchronize()
-    mecdf.profile_reset()
-    mecdf.profile_enable(True)
-    mecdf.ecdf_points(x3)
-    torch.cuda.synchronize()
-    mecdf.profile_enable(False)
-    kern = mecdf.profile_collect()
-    mc_ms, mc_n = kern.get("points_merge_count", (0.0, 0))
-    merge = None
-    if mc_n:
-        ab = 2 * n3 * (2 * 8 + 2 * 8)
-        gbs = ab / (mc_ms / mc_n * 1e-3) / 1e9
-        merge = {"kernel": "points_merge_count", "launches": mc_n,
-                 "avg_launch_ms": mc_ms / mc_n, "algorithmic_bytes_per_launch": ab,
-                 "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    items = 2 * n3  # a data and a query item per point
+    per = {}
+    for mode in ("warm", "cold"):
+        kern = _profiled(lambda: mecdf.ecdf_points(x3), cold=(mode == "cold"))
+        per[mode] = {
+            # the last coordinate's merges: 8-byte compact item and 8-byte
+            # {prefix, carried count} pair, each read and written
+            "points_merge_count": _rate(kern, "points_merge_count", items * 32),
+            # 512-item LDS blocks: item read, prefix/count pair written
+            "points_block_count": _rate(kern, "points_block_count", items * 16),
+            # merges below the last coordinate (d = 4: 16-byte items with three
+            # ranks and the id/side word): read, written merged, copied down
+            "points_merge": _rate(kern, "points_merge", items * 48),
+            "kernel_ms_per_call": {k: v[0] for k, v in kern.items()},
+        }
     out["points_d4_N2^22_tied_counts"] = {"ms_per_call_ecdf_plus_esf": ms,
                                           "Gpoint-evals/s": 2 * n3 / (ms * 1e-3) / 1e9,
-                                          "merge_levels": merge}
+                                          "kernels": per}
     del x3
+    # C4: d = 2, N = 2^22, 64 bandwidths in one call
     x4, y4, h4 = datagen.config4()
     n4 = x4.shape[1]
     x4t = torch.from_numpy(x4).cuda()
     y4t = torch.from_numpy(y4).cuda()
     for prec in ("f64", "f32c"):
         yy = y4t if prec == "f64" else y4t.float()
-        ms_k = _time_calls(lambda: mecdf.kde_laplace(x4t, h4, prec=prec), 2, 1)
-        ms_r = _time_calls(lambda: mecdf.kreg_laplace(x4t, yy, h4, prec=prec), 2, 1)
-        out["kde_nw_d2_N2^22_64h_" + prec] = {
-            "ms_kde_lcv": ms_k, "ms_nw_cv": ms_r,
-            "Gpoint-evals/s": 2 * 64 * n4 / ((ms_k + ms_r) * 1e-3) / 1e9}
+        kde = lambda: mecdf.kde_laplace(x4t, h4, prec=prec)
+        nw = lambda: mecdf.kreg_laplace(x4t, yy, h4, prec=prec)
+        ms_k = _time_calls(kde, 2, 1)
+        ms_r = _time_calls(nw, 2, 1)
+        rec = {"ms_kde_lcv": ms_k, "ms_nw_cv": ms_r,
+               "Gpoint-evals/s": 2 * 64 * n4 / ((ms_k + ms_r) * 1e-3) / 1e9}
+        if prec == "f64":
+            kern = {}
+            for name, fn, ch in (("kde", kde, 1), ("nw", nw, 2)):
+                kk = _profiled(fn)
+                # per item of a level: scanned and split coordinates, weights,
+                # side byte, the 4-byte merge-map entry, and the accumulator
+                # record of the 4 bandwidths (8 * ch bytes each) gathered from
+                # the level above and written for this level
+                ab_apply = n4 * (8 + 8 + 8 * ch + 1 + 4 + 2 * 4 * 8 * ch)
+                ab_agg = n4 * (8 + 8 + 8 * ch + 1)
+                kern[name] = {
+                    "kde_apply": _rate(kk, "kde_apply", ab_apply),
+                    "kde_tile_agg": _rate(kk, "kde_tile_agg", ab_agg),
+                    "kernel_ms_per_call": {k: v[0] for k, v in kk.items()},
+                    # per item and bandwidth: the decay to the neighbour and the
+                    # split-point factor in each of the two passes
+                    "fp64_exp_per_s_apply": None if "kde_apply" not in kk else
+                        2 * 4 * n4 * kk["kde_apply"][1] / (kk["kde_apply"][0] * 1e-3),
+                }
+            rec["kernels"] = kern
+        out["kde_nw_d2_N2^22_64h_" + prec] = rec
     return out
 
 
@@ -374,6 +430,142 @@ def cpu_baseline(x, y, nodes, target_s, sample=None):
     return res
 
 
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_legs(target_s):
+    """The brute-force oracle on the other workloads, on the host cores: C1 in
+    full (all cores and one core); C3, C4 and the bandwidth search on bounded
+    samples, timed and extrapolated linearly in the number of queries (the
+    oracle's cost per query is fixed); with the library's error at the same
+    sampled queries."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2005_03246_amd import datagen, mecdf
+
+    legs = {}
+    cores = oracle.max_threads()
+    g = np.random.default_rng(1234)
+    # C1: ECDF and ESF at all 4096 points, d = 2
+    x1 = datagen.config1()
+    n1 = x1.shape[1]
+    oracle.ecdf(x1, x1)
+    t0 = time.perf_counter()
+    c1 = oracle.ecdf(x1, x1)
+    s1 = oracle.esf(x1, x1)
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.ecdf(x1, x1, nthreads=1)
+    oracle.esf(x1, x1, nthreads=1)
+    t_one = time.perf_counter() - t0
+    xt = torch.from_numpy(x1).cuda()
+    ok = bool(np.array_equal(mecdf.ecdf_points(xt).cpu().numpy(), c1) and
+              np.array_equal(mecdf.esf_points(xt).cpu().numpy(), s1))
+    legs["points_d2_N4096_counts"] = {
+        "kind": "oracle", "cores": cores, "extrapolated": False,
+        "ms_per_call_ecdf_plus_esf": t_all * 1e3, "Gpoint-evals/s": 2 * n1 / t_all / 1e9,
+        "single_core_ms": t_one * 1e3,
+        "sample": "all 4096 points, ECDF and ESF (1.7e7 pair tests each)",
+        "library_counts_equal": ok}
+    # C3: ECDF and ESF at sampled points of the d = 4, N = 2^22 tied sample
+    x3 = datagen.config3()
+    n3 = x3.shape[1]
+    q = np.sort(g.choice(n3, 64, replace=False))
+    oracle.ecdf(x3, x3[:, q[:4]])
+    t0 = time.perf_counter()
+    oracle.ecdf(x3, x3[:, q])
+    t = time.perf_counter() - t0
+    S = int(max(64, min(4096, 64 * (target_s / 3) / max(t, 1e-3))))
+    q = np.sort(g.choice(n3, S, replace=False))
+    t0 = time.perf_counter()
+    ce = oracle.ecdf(x3, x3[:, q])
+    cs = oracle.esf(x3, x3[:, q])
+    t = time.perf_counter() - t0
+    x3t = torch.from_numpy(x3).cuda()
+    qt = torch.from_numpy(q).cuda()
+    ok = bool(np.array_equal(mecdf.ecdf_points(x3t)[qt].cpu().numpy(), ce) and
+              np.array_equal(mecdf.esf_points(x3t)[qt].cpu().numpy(), cs))
+    del x3t
+    legs["points_d4_N2^22_tied_counts"] = {
+        "kind": "oracle", "cores": cores, "extrapolated": True,
+        "seconds_full_call_ecdf_plus_esf": t * n3 / S, "Gpoint-evals/s": 2 * S / t / 1e9,
+        "sample": "ECDF and ESF at %d random points of the 2^22 (%.1f s), times 2^22 / %d"
+                  % (S, t, S),
+        "library_counts_equal_at_sample": ok}
+    # C4: densities and NW estimates, 64 bandwidths, at sampled points
+    x4, y4, h4 = datagen.config4()
+    n4 = x4.shape[1]
+    hm = np.repeat(h4[:, None], 2, 1)
+    q = g.choice(n4, 2, replace=False)
+    t0 = time.perf_counter()
+    oracle.kde_laplace(x4, x4[:, q], hm)
+    t = time.perf_counter() - t0
+    S = int(max(2, min(256, 2 * (target_s / 3) / max(t, 1e-3))))
+    q = np.sort(g.choice(n4, S, replace=False))
+    t0 = time.perf_counter()
+    fo, fa = oracle.kde_laplace(x4, x4[:, q], hm)
+    mo = oracle.nw_regression(x4, y4, x4[:, q], hm)
+    t = time.perf_counter() - t0
+    x4t = torch.from_numpy(x4).cuda()
+    qt = torch.from_numpy(q).cuda()
+    err = {}
+    for prec in ("f64", "f32c"):
+        yy = torch.from_numpy(y4 if prec == "f64" else y4.astype(np.float32)).cuda()
+        f, _ = mecdf.kde_laplace(x4t, h4, prec=prec, want_lcv=False)
+        fg = f[:, qt].double().cpu().numpy()
+        del f
+        m, _ = mecdf.kreg_laplace(x4t, yy, h4, prec=prec, want_cv=False)
+        mg = m[:, qt].double().cpu().numpy()
+        del m
+        mo_p = mo if prec == "f64" else oracle.nw_regression(
+            x4, y4.astype(np.float32).astype(np.float64), x4[:, q], hm)
+        err[prec] = {"density_max_rel": float(np.max(np.abs(fg - fo) / fa)),
+                     "nw_max_abs_over_max_abs_y": float(np.max(np.abs(mg - mo_p)) /
+                                                        np.max(np.abs(y4)))}
+    del x4t
+    legs["kde_nw_d2_N2^22_64h"] = {
+        "kind": "oracle", "cores": cores, "extrapolated": True,
+        "seconds_full_call_kde_plus_nw": t * n4 / S,
+        "Gpoint-evals/s": 2 * 64 * S / t / 1e9,
+        "sample": "density and NW estimate for all 64 bandwidths at %d random points of "
+                  "the 2^22 (%.1f s), times 2^22 / %d" % (S, t, S),
+        "library_error_at_sample": err}
+    # bandwidth search: the 64-bandwidth LCV grid search on the smallest of
+    # the 512 datasets, extrapolated by sum N^2 (the oracle's cost per dataset)
+    sets = datagen.config5()
+    order = np.argsort([x.shape[1] for x in sets])
+    pick = order[:4]
+    hs = bandwidths64 = datagen.bandwidths(64)
+    t0 = time.perf_counter()
+    scores = [oracle.lcv(sets[i], hs) for i in pick]
+    t = time.perf_counter() - t0
+    n2_all = float(sum(float(x.shape[1]) ** 2 * x.shape[0] for x in sets))
+    n2_pick = float(sum(float(sets[i].shape[1]) ** 2 * sets[i].shape[0] for i in pick))
+    t_all = t * n2_all / n2_pick
+    got = mecdf.kde_lcv_batched([torch.from_numpy(sets[i]).cuda() for i in pick],
+                                [bandwidths64] * len(pick))
+    lerr = max(float(np.max(np.abs(r.cpu().numpy() - s_))) for r, s_ in zip(got, scores))
+    legs["bandwidth_grid_search_512"] = {
+        "kind": "oracle", "cores": cores, "extrapolated": True,
+        "datasets_per_s": len(sets) / t_all, "seconds_all_512": t_all,
+        "sample": "64-bandwidth LCV of the 4 smallest datasets (%.1f s), times "
+                  "sum(d N^2) over all 512 / the same over the 4" % t,
+        "library_max_abs_lcv_error_at_sample": lerr}
+    return legs
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -420,11 +612,12 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    def timed(profile):
+    def timed(profile, cold=False):
         """K steps between two events on the launch stream; with profile, the
-        library also brackets each kernel group with events on that stream."""
+        library also brackets each kernel group with events on that stream
+        (cold: a 1 GiB buffer is read before each group)."""
         mecdf.profile_reset()
-        mecdf.profile_enable(profile)
+        mecdf.profile_enable(profile, cold=cold)
         start = torch.cuda.Event(enable_timing=True)
         end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -440,27 +633,66 @@ def main():
         return start.elapsed_time(end) / args.steps, wall, kern
 
     # throughput from plain steps; per-kernel durations from a second timed
-    # run of the same steps with the per-kernel events on
+    # run of the same steps with the per-kernel events on, and from a third
+    # with the infinity cache flushed before every kernel group
     ms_step, wall, _ = timed(False)
     ms_step_prof, _, kern = timed(True)
+    _, _, kern_cold = timed(True, cold=True)
     value = 2.0 * G / (ms_step * 1e-3) / 1e9
-
-    # dominant kernel by total time over the timed steps
-    dom = max(kern.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dlaunch) = dom
-    avg_ms = dms / dlaunch
-    ab = algorithmic_bytes(dname, n, G, ysize, dlaunch // args.steps)
-    roof = {"bound": "hbm", "kernel": dname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "achieved": None, "frac": None, "traffic": measured_traffic(dname, args.prec),
-            "avg_launch_ms": avg_ms}
     ceil = copy_ceiling()
-    roof["copy_ceiling"] = ceil
-    if ab is not None:
-        gbs = ab / (avg_ms * 1e-3) / 1e9
-        roof.update(achieved=gbs, frac=gbs / HBM_PEAK_GBS, frac_of_copy=gbs / ceil,
-                    algorithmic_bytes_per_launch=ab)
+
+    def figures(name, kk):
+        tot, launches = kk[name]
+        avg_ms = tot / launches
+        ab = algorithmic_bytes(name, n, G, ysize, launches // args.steps)
+        rec = {"kernel": name, "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps,
+               "total_ms_per_step": tot / args.steps, "algorithmic_bytes_per_launch": ab,
+               "achieved": None, "frac": None}
+        if ab is not None:
+            gbs = ab / (avg_ms * 1e-3) / 1e9
+            rec.update(achieved=gbs, frac=gbs / HBM_PEAK_GBS, frac_of_copy=gbs / ceil,
+                       working_set_under_infinity_cache=ab < 256e6)
+        return rec
+
+    # Fixed rule: the dominant kernel is the one with the largest total time
+    # per step in the profiled run of the timed steps; every other kernel
+    # within 10 % of it is reported beside it (co-dominant), each with its
+    # warm (timed run) and cold (infinity cache flushed) figures.
+    ranked = sorted(kern.items(), key=lambda kv: -kv[1][0])
+    dname = ranked[0][0]
+    co = [k for k, v in ranked[1:] if v[0] >= 0.9 * ranked[0][1][0]]
+    warm = figures(dname, kern)
+    roof = {"bound": "hbm", "kernel": dname, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "achieved": warm["achieved"], "frac": warm["frac"],
+            "traffic": measured_traffic(dname, args.prec),
+            "avg_launch_ms": warm["avg_launch_ms"],
+            "algorithmic_bytes_per_launch": warm["algorithmic_bytes_per_launch"],
+            "copy_ceiling": ceil, "frac_of_copy": warm.get("frac_of_copy"),
+            "rule": "largest total time per step in the profiled timed steps; kernels within "
+                    "10% listed in co_dominant",
+            "cold": figures(dname, kern_cold) if dname in kern_cold else None,
+            "co_dominant": [{"warm": figures(k, kern),
+                             "cold": figures(k, kern_cold) if k in kern_cold else None}
+                            for k in co]}
+    # the whole step against the bytes it must move: x and y read once, F and
+    # Fbar written once
+    compulsory = n * (3 * 8 + ysize) + 2 * G * ysize
+    moved = 0
+    for k, (tot, launches) in kern.items():
+        ab = algorithmic_bytes(k, n, G, ysize, launches // args.steps)
+        if ab is not None:
+            moved += ab * launches / args.steps
+    roof["path_frac"] = compulsory / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+    roof["path"] = {"compulsory_bytes_per_step": compulsory,
+                    "compulsory_GBs": compulsory / (ms_step * 1e-3) / 1e9,
+                    "moved_bytes_per_step": moved,
+                    "moved_GBs": moved / (ms_step * 1e-3) / 1e9,
+                    "moved_frac": moved / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "note": "moved = the algorithmic bytes of every kernel group of the step"}
     kernels = {k: {"total_ms_per_step": v[0] / args.steps,
-                   "launches_per_step": v[1] / args.steps} for k, v in kern.items()}
+                   "launches_per_step": v[1] / args.steps,
+                   "cold_total_ms_per_step": kern_cold[k][0] / args.steps if k in kern_cold
+                   else None} for k, v in kern.items()}
 
     out = {
         "metric": METRIC,
@@ -493,6 +725,9 @@ def main():
         out["bandwidth"] = bandwidth_eval(args.bw_train)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds, sample)
+        out["cpu_baseline"].update(cpu_info())
+        if not args.no_secondary:
+            out["cpu_baselines_other_workloads"] = cpu_legs(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

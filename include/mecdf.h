@@ -346,8 +346,11 @@ void mecdf_release(void);
 
 /*
  * Kernel timing support for benchmarks (not part of the method).  While
- * enabled, every kernel launch of the entry points above is bracketed by a
- * pair of HIP events on the caller's stream.  mecdf_profile_collect waits for
+ * enabled (on = 1), every kernel launch of the entry points above is
+ * bracketed by a pair of HIP events on the caller's stream; with on = 2
+ * ("cold"), a 1 GiB device buffer that the library allocates once is also
+ * read before each bracketed group, outside its events, so that the group's
+ * inputs are not in the 256 MB infinity cache.  mecdf_profile_collect waits for
  * the recorded events and writes, for up to max distinct kernel names in
  * launch order, the name (64 bytes each, NUL-terminated, into names), the
  * summed duration in milliseconds and the launch count; it returns the number

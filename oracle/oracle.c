@@ -43,11 +43,26 @@ static inline void nsum_add(nsum_t *a, double v)
 
 static inline double nsum_get(const nsum_t *a) { return a->s + a->c; }
 
+/* nthreads > 0: that many threads; 0: the OpenMP default of the process
+ * (OMP_NUM_THREADS, else all processors), restored on every call so that a
+ * one-thread call does not leave later calls on one thread.  Every query's
+ * sum runs on one thread in a fixed order, so results do not depend on it. */
+static int default_threads(void)
+{
+#ifdef _OPENMP
+    static int n = 0;
+    if (n == 0)
+        n = omp_get_max_threads();
+    return n;
+#else
+    return 1;
+#endif
+}
+
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
+    omp_set_num_threads(nthreads > 0 ? nthreads : default_threads());
 #else
     (void)nthreads;
 #endif
@@ -56,7 +71,7 @@ static void set_threads(int nthreads)
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP
-    return omp_get_max_threads();
+    return default_threads();
 #else
     return 1;
 #endif

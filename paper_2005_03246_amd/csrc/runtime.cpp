@@ -148,6 +148,8 @@ int upload_small(const void *host, size_t bytes, void *dev_dst,
 }
 
 // ------------------------------------------------------------- profiling
+int flush_read(const void *buf, size_t bytes, hipStream_t s);  // profiling.hip
+
 namespace {
 struct ProfRec {
     std::string name;
@@ -155,9 +157,15 @@ struct ProfRec {
     int dev = 0;
 };
 std::atomic<bool> g_prof_on{false};
+std::atomic<bool> g_prof_cold{false};
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 size_t g_prof_used = 0;
+// cold mode: a buffer larger than the 256 MB infinity cache, written before
+// each timed group (outside its events) so that its inputs come from HBM
+constexpr size_t kFlushBytes = size_t(1) << 30;
+void *g_flush = nullptr;
+int g_flush_dev = -1;
 }  // namespace
 
 bool profiling_enabled() { return g_prof_on.load(std::memory_order_relaxed); }
@@ -181,6 +189,8 @@ void profile_begin(const char *name, hipStream_t s, int *slot) {
         r.dev = dev;
     }
     r.name = name;
+    if (g_prof_cold.load() && g_flush && g_flush_dev == dev)
+        (void)flush_read(g_flush, kFlushBytes, s);
     if (hipEventRecord(r.a, s) != hipSuccess)
         return;
     *slot = (int)g_prof_used++;
@@ -218,6 +228,25 @@ void workspace_release_all() {
 extern "C" {
 
 int mecdf_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(mecdf::g_prof_mu);
+    if (on == 2) {
+        int dev = 0;
+        MECDF_TRY_HIP(hipGetDevice(&dev));
+        if (mecdf::g_flush && mecdf::g_flush_dev != dev) {
+            // the buffer of another device: freed with that device current
+            int cur = dev;
+            (void)hipSetDevice(mecdf::g_flush_dev);
+            (void)hipFree(mecdf::g_flush);
+            (void)hipSetDevice(cur);
+            mecdf::g_flush = nullptr;
+        }
+        if (!mecdf::g_flush) {
+            MECDF_TRY_HIP(hipMalloc(&mecdf::g_flush, mecdf::kFlushBytes));
+            MECDF_TRY_HIP(hipMemset(mecdf::g_flush, 0, mecdf::kFlushBytes));
+            mecdf::g_flush_dev = dev;
+        }
+    }
+    mecdf::g_prof_cold.store(on == 2);
     mecdf::g_prof_on.store(on != 0);
     return MECDF_OK;
 }

@@ -274,9 +274,11 @@ _lib.mecdf_profile_collect.argtypes = [_I, _P, _P, _P]
 _lib.mecdf_profile_collect.restype = _I
 
 
-def profile_enable(on: bool = True):
-    """Bracket every library kernel launch with HIP events (timing only)."""
-    _lib.mecdf_profile_enable(1 if on else 0)
+def profile_enable(on=True, cold: bool = False):
+    """Bracket every library kernel launch with HIP events (timing only);
+    with cold, a 1 GiB buffer is read before each bracketed group so that its
+    inputs come from HBM rather than the infinity cache."""
+    _check(_lib.mecdf_profile_enable((2 if cold else 1) if on else 0), "mecdf_profile_enable")
 
 
 def profile_reset():
