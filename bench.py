@@ -88,6 +88,14 @@ def algorithmic_bytes(kernel: str, n: int, g: int, ysize: int, launches_per_step
     return None
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +215,7 @@ def secondary():
     from paper_2005_03246_amd import datagen, mecdf
 
     out = {}
+    log("secondary: points d=2 N=4096")
     # C1: d = 2, N = 4096 counts, by the direct kernel (the default at this
     # size) and by the divide-and-conquer recursion
     x = torch.from_numpy(datagen.config1()).cuda()
@@ -221,6 +230,7 @@ def secondary():
         "divide_and_conquer_ms_per_call_ecdf_plus_esf": ms_dc,
         "note": "latency bound (96 KB in and out); no roofline"}
     # C3: d = 4, N = 2^22 tied, counts
+    log("secondary: points d=4 N=2^22")
     x3 = torch.from_numpy(datagen.config3()).cuda()
     n3 = x3.shape[1]
     ms = _time_calls(lambda: (mecdf.ecdf_points(x3), mecdf.esf_points(x3)), 2, 1)
@@ -244,6 +254,7 @@ def secondary():
                                           "kernels": per}
     del x3
     # C4: d = 2, N = 2^22, 64 bandwidths in one call
+    log("secondary: kernel sums d=2 N=2^22 64h")
     x4, y4, h4 = datagen.config4()
     n4 = x4.shape[1]
     x4t = torch.from_numpy(x4).cuda()
@@ -294,9 +305,11 @@ def bandwidth_eval(train_count):
     from paper_2005_03246_amd import bandwidth, datagen, mecdf
 
     hgrid = bandwidth.hgrid64()
+    log("bandwidth: datasets")
     tr = bandwidth.to_device(datagen.config5(count=train_count, seed=datagen.BASE_SEED + 500))
     te = bandwidth.to_device(datagen.config5())
     torch.cuda.synchronize()
+    log("bandwidth: training")
     t0 = time.perf_counter()
     params, losses, _ = bandwidth.train(tr, hgrid)
     torch.cuda.synchronize()
@@ -306,6 +319,7 @@ def bandwidth_eval(train_count):
     bandwidth.grid_search(te[:4], hgrid)
     bandwidth.select(te[:4], params, hgrid)
     torch.cuda.synchronize()
+    log("bandwidth: grid search")
     t0 = time.perf_counter()
     gidx, mat = bandwidth.grid_search(te, hgrid)
     torch.cuda.synchronize()
@@ -328,14 +342,39 @@ def bandwidth_eval(train_count):
                 "mean_evaluations": float(evals.mean()),
                 "window_extended_fraction": float(np.mean(evals > 4))}
 
+    log("bandwidth: learned and rule-of-thumb selection")
     ext = run(params, mecdf.BW_EXTEND)
     win = run(params, mecdf.BW_WINDOW)
     zero = torch.zeros_like(params)
     rot = run(zero, mecdf.BW_EXTEND)
     rot_win = run(zero, mecdf.BW_WINDOW)
+    # the same grid search prepared once (work queue recorded into a HIP
+    # graph) and run again
+    log("bandwidth: grid search plan")
+    t0 = time.perf_counter()
+    plan = mecdf.LcvPlan(te, [hgrid] * n)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        res, pbest = plan.run()
+    torch.cuda.synchronize()
+    t_replay = (time.perf_counter() - t0) / reps
+    same = bool(np.array_equal(pbest.cpu().numpy(), gidx))
+    plan.close()
+    qmax, qsrc = mecdf.tuning()
     return {
         "datasets": n,
         "grid_datasets_per_s": n / t_grid,
+        "grid_graph_replay_datasets_per_s": n / t_replay,
+        "grid_graph_record_seconds": t_rec,
+        "grid_graph_same_choice": same,
+        "queue_max_n": qmax, "queue_max_n_source": qsrc,
+        "learned_window_speedup_vs_graph_replay": (n / win["datasets_per_s"]) and
+            t_replay / (n / win["datasets_per_s"]),
         "gap_limit_nats": lim,
         "learned_extend": ext,
         "learned_window": win,
@@ -457,6 +496,7 @@ def cpu_legs(target_s):
 
     legs = {}
     cores = oracle.max_threads()
+    log("cpu legs: points d=2")
     g = np.random.default_rng(1234)
     # C1: ECDF and ESF at all 4096 points, d = 2
     x1 = datagen.config1()
@@ -480,6 +520,7 @@ def cpu_legs(target_s):
         "sample": "all 4096 points, ECDF and ESF (1.7e7 pair tests each)",
         "library_counts_equal": ok}
     # C3: ECDF and ESF at sampled points of the d = 4, N = 2^22 tied sample
+    log("cpu legs: points d=4")
     x3 = datagen.config3()
     n3 = x3.shape[1]
     q = np.sort(g.choice(n3, 64, replace=False))
@@ -505,14 +546,18 @@ def cpu_legs(target_s):
                   % (S, t, S),
         "library_counts_equal_at_sample": ok}
     # C4: densities and NW estimates, 64 bandwidths, at sampled points
+    log("cpu legs: kernel sums")
     x4, y4, h4 = datagen.config4()
     n4 = x4.shape[1]
     hm = np.repeat(h4[:, None], 2, 1)
-    q = g.choice(n4, 2, replace=False)
+    # the oracle runs one thread per query: probe with one query per thread
+    q0 = max(1, cores)
+    q = g.choice(n4, q0, replace=False)
     t0 = time.perf_counter()
     oracle.kde_laplace(x4, x4[:, q], hm)
     t = time.perf_counter() - t0
-    S = int(max(2, min(256, 2 * (target_s / 3) / max(t, 1e-3))))
+    S = int(max(q0, min(512, q0 * (target_s / 6) / max(t, 1e-3))))
+    S = (S // q0) * q0
     q = np.sort(g.choice(n4, S, replace=False))
     t0 = time.perf_counter()
     fo, fa = oracle.kde_laplace(x4, x4[:, q], hm)
@@ -544,6 +589,7 @@ def cpu_legs(target_s):
         "library_error_at_sample": err}
     # bandwidth search: the 64-bandwidth LCV grid search on the smallest of
     # the 512 datasets, extrapolated by sum N^2 (the oracle's cost per dataset)
+    log("cpu legs: bandwidth search")
     sets = datagen.config5()
     order = np.argsort([x.shape[1] for x in sets])
     pick = order[:4]
@@ -585,6 +631,7 @@ def main():
     from paper_2005_03246_amd import datagen, mecdf
 
     torch.cuda.set_device(0)
+    log("headline: grid ECDF+ESF d=3 N=2^24 256^3")
     x, y, nodes = datagen.config2(n=1 << LOG2N, m=M_NODES)
     n = x.shape[1]
     xt = torch.from_numpy(x).cuda()
@@ -724,10 +771,12 @@ def main():
     if not args.no_bandwidth:
         out["bandwidth"] = bandwidth_eval(args.bw_train)
     if not args.no_cpu_baseline:
+        log("cpu baseline: grid")
         out["cpu_baseline"] = cpu_baseline(x, y, nodes, args.cpu_seconds, sample)
         out["cpu_baseline"].update(cpu_info())
         if not args.no_secondary:
             out["cpu_baselines_other_workloads"] = cpu_legs(args.cpu_seconds)
+    log("done")
     print(json.dumps(out), flush=True)
 
 

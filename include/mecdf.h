@@ -246,6 +246,46 @@ int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
                           void *stream);
 
 /*
+ * Batched scores prepared once and run repeatedly: mecdf_lcv_plan_create
+ * takes the arguments of mecdf_kde_lcv_batched (the same outputs, written on
+ * every run), copies what the kernels read from the host into memory the
+ * plan owns (with its own working memory, so other calls cannot disturb it)
+ * and records the work queue of the small datasets into a HIP graph.
+ * mecdf_lcv_plan_run launches that graph on the plan's own stream, enqueues
+ * the recursions of the larger datasets on the given stream meanwhile, joins
+ * the two on the given stream and writes the best indices (the datasets may
+ * change in value between runs, not in place or size; runs of one plan must
+ * not overlap).  mecdf_lcv_plan_destroy waits for the device and frees the
+ * plan.  Creation waits for the device.  For callers that score the same
+ * shapes repeatedly.
+ */
+typedef struct mecdf_lcv_plan_s *mecdf_lcv_plan;
+int mecdf_lcv_plan_create(const mecdf_dataset *sets, int nsets, const int *nh,
+                          const double *h, double *lcv, int *best, int prec,
+                          mecdf_lcv_plan *plan);
+int mecdf_lcv_plan_run(mecdf_lcv_plan plan, void *stream);
+void mecdf_lcv_plan_destroy(mecdf_lcv_plan plan);
+
+/*
+ * mecdf_autotune -- chooses, per precision and d = 1, 2, 3, up to which N the
+ * batched scores use the work queue (every pair, one launch for all small
+ * datasets) rather than the recursion, by timing both on the current device
+ * for N = 512 .. 32768 with 64 bandwidths; writes the choice and the times as
+ * JSON to path (NULL: the file the library reads, $MECDF_TUNE_FILE or
+ * tune_<arch>.json beside libmecdf.so) and uses it from then on.  The library
+ * reads that file on first use when its architecture matches the device's;
+ * otherwise built-in values apply.  Takes seconds; waits for the device.
+ *
+ * mecdf_tuning -- the values in use: queue_max_n[p * 3 + d - 1] for
+ * precision p (0 float64, 1 float32) and d, and where they came from (a file
+ * path, "built-in defaults" or "set by the caller") into source (cap bytes).
+ * mecdf_tuning_set replaces them for this process (each in 0..2^24).
+ */
+int mecdf_autotune(const char *path, void *stream);
+int mecdf_tuning(int64_t *queue_max_n, char *source, int cap);
+int mecdf_tuning_set(const int64_t *queue_max_n);
+
+/*
  * mecdf_bw_features -- 32 summary statistics per dataset (device floats,
  * feat[s*32 + q]), computed on the device in one block per dataset:
  * log N / 10, d / 3, per-axis log sd, skewness, excess kurtosis / 10,
@@ -328,12 +368,13 @@ int mecdf_bw_train(int B, const float *feat, const int *label, int nhg,
  * window centred within half a step of j, clamped to the grid).  With mode MECDF_BW_EXTEND the evaluated window is
  * then extended by four grid points at a time towards the best score until
  * the best score is interior to it (or at the grid's end); with
- * MECDF_BW_WINDOW the four-point window is the answer.  Each dataset's
- * structure over its sample is built once for all its windows.  Returns, per
- * dataset (host arrays), the chosen grid index, its LCV score (lcv_out may be
- * NULL) and the number of bandwidths evaluated (evals_out may be NULL).
- * Every returned score is an exact evaluation.  Synchronous: waits for the
- * device after each window.
+ * MECDF_BW_WINDOW the four-point window is the answer.  The windows of all
+ * datasets are scored together by the batched scores of
+ * mecdf_kde_lcv_batched, one round per extension.  Returns, per dataset
+ * (host arrays), the chosen grid index, its LCV score (lcv_out may be NULL)
+ * and the number of bandwidths evaluated (evals_out may be NULL).  Every
+ * returned score is an exact evaluation.  Synchronous: waits for the device
+ * after the proposals and after each round.
  */
 #define MECDF_BW_EXTEND 0
 #define MECDF_BW_WINDOW 1

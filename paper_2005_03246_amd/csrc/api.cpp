@@ -19,9 +19,6 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh,
             const double *h, void *f, double *score, int regression,
             int prec, hipStream_t s);
-using BatchSource = std::function<int(int &b0, int &nb, bool &more)>;
-int kde_lcv_select(int d, int64_t N, const double *x, int nh, const double *h, double *score,
-                   const BatchSource &source, hipStream_t s);
 int bw_features(const mecdf_dataset *sets, int nsets, float *feat, hipStream_t s);
 int mlp_forward(int B, const float *X, const float *P, float *out, hipStream_t s);
 int mlp_grad(int B, const float *X, const float *T, const float *P, float *G, float *loss,
@@ -33,6 +30,15 @@ int bw_train_steps(int B, const float *feat, const int *label, int nhg, const do
                    int steps, float lr, float wd, float *P, float *adam, float *losses,
                    int64_t t0, hipStream_t s);
 int lcv_argmax(const double *score, const int *cnt, int nsets, int *best, hipStream_t s);
+int batch_lcv(const mecdf_dataset *sets, int nsets, const int *nh, const double *h,
+              double *lcv, int *best, int prec, int force, hipStream_t s);
+int lcv_plan_create(const mecdf_dataset *sets, int nsets, const int *nh, const double *h,
+                    double *lcv, int *best, int prec, void **out);
+int lcv_plan_run(void *plan, hipStream_t s);
+void lcv_plan_destroy(void *plan);
+int autotune(const char *path, hipStream_t s);
+int tuning_info(int64_t *queue_max, char *source, int cap);
+int tuning_set(const int64_t *queue_max);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -221,8 +227,8 @@ static int check_sets(const mecdf_dataset *sets, int nsets) {
     return MECDF_OK;
 }
 
-int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
-                          const double *h, double *lcv, int *best, int prec, void *stream) {
+static int check_batch(const mecdf_dataset *sets, int nsets, const int *nh, const double *h,
+                       const double *lcv) {
     MECDF_TRY(check_sets(sets, nsets));
     if (nh == nullptr || h == nullptr || lcv == nullptr)
         return fail(MECDF_EINVAL, "nh, h and lcv are required");
@@ -235,23 +241,55 @@ int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
                 return fail(MECDF_EINVAL, "bandwidths must be positive and finite");
         off += nh[i];
     }
-    off = 0;
-    std::vector<double> hh;
-    for (int i = 0; i < nsets; ++i) {
-        if (nh[i] > 0) {
-            const int d = sets[i].d;
-            hh.assign((size_t)nh[i] * d, 0.0);
-            for (int b = 0; b < nh[i]; ++b)
-                for (int k = 0; k < d; ++k)
-                    hh[(size_t)b * d + k] = h[off + b];
-            MECDF_TRY(kde_run(d, sets[i].N, sets[i].x, nullptr, nh[i], hh.data(), nullptr,
-                              lcv + off, 0, prec, (hipStream_t)stream));
-        }
-        off += nh[i];
-    }
-    if (best)
-        MECDF_TRY(lcv_argmax(lcv, nh, nsets, best, (hipStream_t)stream));
     return MECDF_OK;
+}
+
+int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
+                          const double *h, double *lcv, int *best, int prec, void *stream) {
+    MECDF_TRY(check_batch(sets, nsets, nh, h, lcv));
+    if (prec != MECDF_F64 && prec != MECDF_F32C)
+        return fail(MECDF_EINVAL, "prec must be MECDF_F64 or MECDF_F32C");
+    return batch_lcv(sets, nsets, nh, h, lcv, best, prec, -1, (hipStream_t)stream);
+}
+
+int mecdf_lcv_plan_create(const mecdf_dataset *sets, int nsets, const int *nh,
+                          const double *h, double *lcv, int *best, int prec,
+                          mecdf_lcv_plan *plan) {
+    if (plan == nullptr)
+        return fail(MECDF_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    MECDF_TRY(check_batch(sets, nsets, nh, h, lcv));
+    if (prec != MECDF_F64 && prec != MECDF_F32C)
+        return fail(MECDF_EINVAL, "prec must be MECDF_F64 or MECDF_F32C");
+    void *p = nullptr;
+    MECDF_TRY(lcv_plan_create(sets, nsets, nh, h, lcv, best, prec, &p));
+    *plan = (mecdf_lcv_plan)p;
+    return MECDF_OK;
+}
+
+int mecdf_lcv_plan_run(mecdf_lcv_plan plan, void *stream) {
+    if (plan == nullptr)
+        return fail(MECDF_EINVAL, "plan is NULL");
+    return lcv_plan_run((void *)plan, (hipStream_t)stream);
+}
+
+void mecdf_lcv_plan_destroy(mecdf_lcv_plan plan) {
+    if (plan)
+        lcv_plan_destroy((void *)plan);
+}
+
+int mecdf_autotune(const char *path, void *stream) {
+    return autotune(path, (hipStream_t)stream);
+}
+
+int mecdf_tuning(int64_t *queue_max_n, char *source, int cap) {
+    return tuning_info(queue_max_n, source, cap);
+}
+
+int mecdf_tuning_set(const int64_t *queue_max_n) {
+    if (queue_max_n == nullptr)
+        return fail(MECDF_EINVAL, "queue_max_n is NULL");
+    return tuning_set(queue_max_n);
 }
 
 int mecdf_bw_features(const mecdf_dataset *sets, int nsets, float *feat, void *stream) {
@@ -430,20 +468,17 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
                     const double *hgrid, int mode, int *hidx_out, double *lcv_out,
                     int *evals_out, void *stream) {
     MECDF_TRY(check_sets(sets, nsets));
-    if (!params || !hgrid || !hidx_out || nhg < 1 || nhg > 4096 ||
-        (mode != MECDF_BW_EXTEND && mode != MECDF_BW_WINDOW))
+    if (!params || !hidx_out || (mode != MECDF_BW_EXTEND && mode != MECDF_BW_WINDOW) ||
+        nhg > 4096 || !grid_ok(nhg, hgrid))
         return fail(MECDF_EINVAL, "bw_select: bad arguments");
-    for (int j = 0; j < nhg; ++j)
-        if (!(hgrid[j] > 0.0) || (j > 0 && !(hgrid[j] > hgrid[j - 1])))
-            return fail(MECDF_EINVAL, "hgrid must be positive and ascending");
     hipStream_t s = (hipStream_t)stream;
     // device buffers of this call (outside the shared workspace, which the
-    // kernel sums below reuse)
+    // batched scores below reuse)
     float *feat = nullptr, *pred = nullptr;
     double *scd = nullptr;
     MECDF_TRY_HIP(hipMalloc(&feat, sizeof(float) * 32 * nsets));
     hipError_t e1 = hipMalloc(&pred, sizeof(float) * nsets);
-    hipError_t e2 = hipMalloc(&scd, sizeof(double) * nhg);
+    hipError_t e2 = hipMalloc(&scd, sizeof(double) * 4 * (size_t)nsets);
     auto cleanup = [&]() {
         (void)hipFree(feat);
         (void)hipFree(pred);
@@ -471,17 +506,14 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
     const double l0 = std::log(hgrid[0]);
     const double dl = nhg > 1 ? (std::log(hgrid[nhg - 1]) - l0) / (nhg - 1) : 1.0;
     const int w = nhg < 4 ? nhg : 4;
-    // the grid repeated on every axis, for d = 1, 2, 3
-    std::vector<double> hh[3];
-    for (int d = 1; d <= 3; ++d) {
-        hh[d - 1].resize((size_t)nhg * d);
-        for (int j = 0; j < nhg; ++j)
-            for (int k = 0; k < d; ++k)
-                hh[d - 1][(size_t)j * d + k] = hgrid[j];
-    }
-    std::vector<double> sc(nhg);
-    for (int i = 0; i < nsets && rc == MECDF_OK; ++i) {
-        double lh = (double)hf[(size_t)i * 32 + 12] + (double)hp[i];
+    // per dataset: the evaluated range [lo, hi] of grid indices, the scores
+    // there (host copy), the best index
+    std::vector<int> lo(nsets), hi(nsets), best(nsets), evals(nsets, 0);
+    std::vector<std::vector<double>> sc(nsets, std::vector<double>(nhg, 0.0));
+    // the next batch: per dataset its first grid index and count (0: none)
+    std::vector<int> b0(nsets), bn(nsets);
+    for (int i = 0; i < nsets; ++i) {
+        const double lh = (double)hf[(size_t)i * 32 + 12] + (double)hp[i];
         double jf = std::isfinite(lh) ? (lh - l0) / dl : 0.0;
         jf = jf < -1e6 ? -1e6 : (jf > 1e6 ? 1e6 : jf);
         // the four grid points nearest the proposal: round(jf) - 2 .. round(jf) + 1
@@ -490,58 +522,64 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
             j0 = nhg - w;
         if (j0 < 0)
             j0 = 0;
-        // evaluated range [lo, hi], best index, the batch in flight
-        int lo = j0, hi = j0 + w - 1, best = j0, evals = 0;
-        int cur0 = -1, curn = 0;
-        BatchSource source = [&](int &b0, int &nb, bool &more) -> int {
-            if (cur0 < 0) {
-                cur0 = b0 = j0;
-                curn = nb = w;
-                more = true;
-                return MECDF_OK;
-            }
-            // scores of the batch just enqueued
-            if (hipMemcpyAsync(sc.data() + cur0, scd + cur0, sizeof(double) * curn,
-                               hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return fail(MECDF_EDEVICE, "bw_select: copy failed");
-            evals += curn;
-            lo = cur0 < lo ? cur0 : lo;
-            hi = cur0 + curn - 1 > hi ? cur0 + curn - 1 : hi;
-            best = lo;
-            for (int j = lo; j <= hi; ++j)
-                if (sc[j] > sc[best])
-                    best = j;
-            more = false;
-            if (mode == MECDF_BW_EXTEND) {
-                if (best == lo && lo > 0) {
-                    b0 = lo - 4 > 0 ? lo - 4 : 0;
-                    nb = lo - b0;
-                    more = true;
-                } else if (best == hi && hi < nhg - 1) {
-                    b0 = hi + 1;
-                    nb = hi + 4 < nhg - 1 ? 4 : nhg - 1 - hi;
-                    more = true;
-                }
-            }
-            if (more) {
-                cur0 = b0;
-                curn = nb;
-            }
-            return MECDF_OK;
-        };
-        rc = kde_lcv_select(sets[i].d, sets[i].N, sets[i].x, nhg, hh[sets[i].d - 1].data(),
-                            scd, source, s);
+        b0[i] = j0;
+        bn[i] = w;
+        lo[i] = j0;
+        hi[i] = j0 + w - 1;
+    }
+    std::vector<double> hl, got;
+    for (;;) {
+        // one batched evaluation of every dataset's pending bandwidths
+        hl.clear();
+        for (int i = 0; i < nsets; ++i)
+            for (int b = 0; b < bn[i]; ++b)
+                hl.push_back(hgrid[b0[i] + b]);
+        if (hl.empty())
+            break;
+        rc = batch_lcv(sets, nsets, bn.data(), hl.data(), scd, nullptr, MECDF_F64, -1, s);
+        got.resize(hl.size());
+        if (rc == MECDF_OK &&
+            (hipMemcpyAsync(got.data(), scd, sizeof(double) * got.size(), hipMemcpyDeviceToHost,
+                            s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            rc = fail(MECDF_EDEVICE, "bw_select: copy failed");
         if (rc != MECDF_OK)
             break;
-        hidx_out[i] = best;
-        if (lcv_out)
-            lcv_out[i] = sc[best];
-        if (evals_out)
-            evals_out[i] = evals;
+        size_t k = 0;
+        for (int i = 0; i < nsets; ++i) {
+            for (int b = 0; b < bn[i]; ++b)
+                sc[i][b0[i] + b] = got[k++];
+            evals[i] += bn[i];
+            lo[i] = std::min(lo[i], b0[i]);
+            hi[i] = std::max(hi[i], b0[i] + bn[i] - 1);
+            int bi = lo[i];
+            for (int j = lo[i]; j <= hi[i]; ++j)
+                if (sc[i][j] > sc[i][bi])
+                    bi = j;
+            best[i] = bi;
+            bn[i] = 0;
+            if (mode == MECDF_BW_EXTEND) {
+                // widen towards the best score until it is interior
+                if (bi == lo[i] && lo[i] > 0) {
+                    b0[i] = lo[i] - 4 > 0 ? lo[i] - 4 : 0;
+                    bn[i] = lo[i] - b0[i];
+                } else if (bi == hi[i] && hi[i] < nhg - 1) {
+                    b0[i] = hi[i] + 1;
+                    bn[i] = hi[i] + 4 < nhg - 1 ? 4 : nhg - 1 - hi[i];
+                }
+            }
+        }
     }
     cleanup();
-    return rc;
+    MECDF_TRY(rc);
+    for (int i = 0; i < nsets; ++i) {
+        hidx_out[i] = best[i];
+        if (lcv_out)
+            lcv_out[i] = sc[i][best[i]];
+        if (evals_out)
+            evals_out[i] = evals[i];
+    }
+    return MECDF_OK;
 }
 
 void mecdf_release(void) { mecdf::workspace_release_all(); }

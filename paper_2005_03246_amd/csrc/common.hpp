@@ -69,6 +69,13 @@ struct FixedWorkspace {
 // The library's fixed device scratch array on the current device, for the
 // entry points that allocate nothing.
 int noalloc_scratch(void **base, size_t *bytes);
+
+// Sizing: while set for the calling thread, workspace_reserve records the
+// largest request in *bytes and returns kSizingOnly, which the drivers pass
+// up before launching anything (every driver reserves before its first
+// launch).  Never returned through the C ABI.
+constexpr int kSizingOnly = 1;
+void set_workspace_sizing(size_t *bytes);
 int upload_small(const void *host, size_t bytes, void *dev_dst,
                  hipStream_t stream);
 

@@ -38,10 +38,10 @@
 // d = 1 is the same scan over the sorted sample (the two-sided recursion of
 // the 1-D decomposition).  The sums exclude the point itself (leave-one-out);
 // the full estimate adds w_j K(0).
-#include <functional>
 #include <vector>
 
 #include "common.hpp"
+#include "lse.hpp"
 #include "radix.hpp"
 
 namespace mecdf {
@@ -1094,69 +1094,6 @@ __global__ __launch_bounds__(256) void k_kfinish(const double *__restrict__ acc,
     }
 }
 
-// ------------------------------------------- sums relative to the nearest point
-// Leave-one-out kernel sums at a query j written relative to its nearest
-// other point, so that their logarithm exists even where every term
-// exp(-e_i) is below the float64 range:
-//   e_i = sum_k |x_k,i - x_k,j| / h_k,   m = min_{i != j} e_i,
-//   S_c = sum_{i != j} w_c,i exp(-(e_i - m)),   sum_{i != j} w_c,i exp(-e_i) = exp(-m) S_c.
-// Accumulated in one pass: a smaller e_i rescales the sums seen so far by
-// exp(-(m - e_i)) and becomes the new m.  Sums carry a Neumaier compensation
-// term (rescaled with them).
-template <int CH> struct LooAcc {
-    double m;
-    double s[CH], c[CH];
-};
-
-template <int CH> __device__ __forceinline__ void loo_init(LooAcc<CH> &a) {
-    a.m = INFINITY;
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-        a.s[c] = a.c[c] = 0.0;
-}
-
-__device__ __forceinline__ void neum_add(double &s, double &c, double v) {
-    const double t = s + v;
-    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-    s = t;
-}
-
-// one term: scaled distance e with factor t = exp(-|e - m|) already formed
-template <int CH>
-__device__ __forceinline__ void loo_add(LooAcc<CH> &a, double e, double t, const double (&w)[CH]) {
-    const bool lower = e < a.m;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        if (lower) {
-            a.s[c] *= t;
-            a.c[c] *= t;
-        }
-        neum_add(a.s[c], a.c[c], lower ? w[c] : w[c] * t);
-    }
-    a.m = lower ? e : a.m;
-}
-
-// b merged into a (a's terms first)
-template <int CH> __device__ __forceinline__ void loo_merge(LooAcc<CH> &a, const LooAcc<CH> &b) {
-    if (!(b.m < INFINITY))
-        return;
-    if (!(a.m < INFINITY)) {
-        a = b;
-        return;
-    }
-    const double m = a.m < b.m ? a.m : b.m;
-    const double fa = exp(-(a.m - m)), fb = exp(-(b.m - m));
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-        double s = a.s[c] * fa, cc = a.c[c] * fa;
-        neum_add(s, cc, b.s[c] * fb);
-        neum_add(s, cc, b.c[c] * fb);
-        a.s[c] = s;
-        a.c[c] = cc;
-    }
-    a.m = m;
-}
-
 // The score term of an item from its sums relative to the nearest point.
 template <int CH>
 __device__ __forceinline__ double loo_term(const LooAcc<CH> &r, int mode, double norm_loo,
@@ -1571,16 +1508,10 @@ static int run_scan(const KLevelArgs &la, const KBatch &kb, int64_t nt, void *ag
     return MECDF_OK;
 }
 
-// Chooses the next batch of bandwidths: with more = true, [b0, b0 + nb)
-// (nb <= kKB) indexes the bandwidth list; more = false ends the call.  It is
-// called before the first batch and after each batch has been enqueued, and
-// returns an error code.
-using BatchSource = std::function<int(int &b0, int &nb, bool &more)>;
-
 template <typename T, int CH, typename WT, typename OutT>
 static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT *w1in,
                      int nh, const double *h, OutT *out, double *score, int mode,
-                     hipStream_t s, const BatchSource *source = nullptr) {
+                     hipStream_t s) {
     // outer merge levels (x1 split): blocks of hs[q] merged into 2 hs[q]
     std::vector<int64_t> hs;
     if (d >= 2)
@@ -1696,24 +1627,8 @@ static int kde_run_t(int d, int64_t n, const double *x, const WT *w0in, const WT
         MECDF_LAUNCH_CHECK();
     }
 
-    int b0 = 0, bcount = 0;
-    for (;;) {
-        if (source) {
-            bool more = false;
-            MECDF_TRY((*source)(b0, bcount, more));
-            if (!more)
-                break;
-            if (b0 < 0 || bcount < 1 || bcount > kKB || b0 + bcount > nh) {
-                set_error("bandwidth batch out of range");
-                return MECDF_EINVAL;
-            }
-        } else {
-            if (bcount > 0)
-                b0 += kKB;
-            if (b0 >= nh)
-                break;
-            bcount = nh - b0 < kKB ? nh - b0 : kKB;
-        }
+    for (int b0 = 0; b0 < nh; b0 += kKB) {
+        const int bcount = nh - b0 < kKB ? nh - b0 : kKB;
         KBatch kb{};
         kb.nb = bcount;
         for (int b = 0; b < kKB; ++b) {
@@ -1877,6 +1792,15 @@ __global__ void k_seg_argmax(const double *__restrict__ score, const int64_t *__
     best[i] = bi;
 }
 
+// off: device, nsets + 1 list offsets
+int launch_seg_argmax(const double *score, const int64_t *off, int nsets, int *best,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_argmax, dim3((unsigned)ceil_div(nsets, 256)), dim3(256), 0, s, score,
+                       off, nsets, best);
+    MECDF_LAUNCH_CHECK();
+    return MECDF_OK;
+}
+
 int lcv_argmax(const double *score, const int *cnt, int nsets, int *best, hipStream_t s) {
     std::vector<int64_t> off((size_t)nsets + 1, 0);
     for (int i = 0; i < nsets; ++i)
@@ -1888,19 +1812,6 @@ int lcv_argmax(const double *score, const int *cnt, int nsets, int *best, hipStr
                        (const int64_t *)wsb, nsets, best);
     MECDF_LAUNCH_CHECK();
     return MECDF_OK;
-}
-
-// Leave-one-out log-likelihood scores of one unweighted sample for the
-// bandwidths h[b0 .. b0+nb) of a list of nh (d entries each), batches chosen
-// by source; the structure over the sample is built once.
-int kde_lcv_select(int d, int64_t N, const double *x, int nh, const double *h, double *score,
-                   const BatchSource &source, hipStream_t s) {
-    if (N > (int64_t(1) << 28) || (d == 3 && N > (int64_t(1) << 24))) {
-        set_error("kernel sums support N <= 2^28 (2^24 for d = 3)");
-        return MECDF_EUNSUPPORTED;
-    }
-    return kde_run_t<double, 1, double, double>(d, N, x, nullptr, nullptr, nh, h, nullptr, score,
-                                                0, s, &source);
 }
 
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh, const double *h,

@@ -52,6 +52,7 @@ const char *last_error() { return g_last_error.c_str(); }
 namespace {
 thread_local void *t_fixed_ws = nullptr;
 thread_local size_t t_fixed_bytes = 0;
+thread_local size_t *t_sizing = nullptr;
 }  // namespace
 
 void set_fixed_workspace(void *base, size_t bytes) {
@@ -59,7 +60,14 @@ void set_fixed_workspace(void *base, size_t bytes) {
     t_fixed_bytes = bytes;
 }
 
+void set_workspace_sizing(size_t *bytes) { t_sizing = bytes; }
+
 int workspace_reserve(size_t bytes, void **base) {
+    if (t_sizing) {
+        if (bytes > *t_sizing)
+            *t_sizing = bytes;
+        return kSizingOnly;
+    }
     if (t_fixed_ws) {
         if (bytes > t_fixed_bytes) {
             set_error("this call needs " + std::to_string(bytes) +

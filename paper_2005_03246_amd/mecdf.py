@@ -361,6 +361,82 @@ def kde_lcv_batched(datasets, hs, prec="f64", stream=None, want_best=False):
     return (res, best) if want_best else res
 
 
+_lib.mecdf_lcv_plan_create.argtypes = [_P, _I, _P, _P, _P, _P, _I, _P]
+_lib.mecdf_lcv_plan_create.restype = _I
+_lib.mecdf_lcv_plan_run.argtypes = [_P, _P]
+_lib.mecdf_lcv_plan_run.restype = _I
+_lib.mecdf_lcv_plan_destroy.argtypes = [_P]
+_lib.mecdf_lcv_plan_destroy.restype = None
+_lib.mecdf_autotune.argtypes = [ctypes.c_char_p, _P]
+_lib.mecdf_autotune.restype = _I
+_lib.mecdf_tuning.argtypes = [_P, ctypes.c_char_p, _I]
+_lib.mecdf_tuning.restype = _I
+_lib.mecdf_tuning_set.argtypes = [_P]
+_lib.mecdf_tuning_set.restype = _I
+
+
+class LcvPlan:
+    """The batched scores of a fixed list of datasets recorded into a HIP
+    graph (C ABI ``mecdf_lcv_plan_*``); ``run()`` replays it and returns the
+    same outputs as :func:`kde_lcv_batched` (written in place each run)."""
+
+    def __init__(self, datasets, hs, prec="f64", want_best=True):
+        arr, self._keep = _sets(datasets)
+        nh = (ctypes.c_int * len(datasets))(*[len(h) for h in hs])
+        flat = [float(v) for h in hs for v in h]
+        hv = (ctypes.c_double * max(1, len(flat)))(*flat)
+        dev = self._keep[0].device
+        self.out = torch.empty((max(1, len(flat)),), dtype=torch.float64, device=dev)
+        self.best = torch.empty((len(datasets),), dtype=torch.int32, device=dev) \
+            if want_best else None
+        self._hs = [len(h) for h in hs]
+        self._plan = ctypes.c_void_p()
+        _check(_lib.mecdf_lcv_plan_create(ctypes.addressof(arr), len(datasets), nh, hv,
+                                          _ptr(self.out), _ptr(self.best), _prec(prec),
+                                          ctypes.byref(self._plan)), "mecdf_lcv_plan_create")
+
+    def run(self, stream=None):
+        _check(_lib.mecdf_lcv_plan_run(self._plan, _stream_ptr(stream)), "mecdf_lcv_plan_run")
+        res, off = [], 0
+        for k in self._hs:
+            res.append(self.out[off:off + k])
+            off += k
+        return res, self.best
+
+    def close(self):
+        if self._plan:
+            _lib.mecdf_lcv_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(path=None, stream=None):
+    """Time the work queue against the recursion on this GPU and store the
+    choice (C ABI ``mecdf_autotune``)."""
+    ck = None if path is None else os.fsencode(path)
+    _check(_lib.mecdf_autotune(ck, _stream_ptr(stream)), "mecdf_autotune")
+
+
+def tuning_set(queue_max_n):
+    """Replace the queue sizes for this process: {"f64": [d1, d2, d3], "f32c":
+    [...]} (C ABI ``mecdf_tuning_set``)."""
+    v = (ctypes.c_int64 * 6)(*(list(queue_max_n["f64"]) + list(queue_max_n["f32c"])))
+    _check(_lib.mecdf_tuning_set(v), "mecdf_tuning_set")
+
+
+def tuning():
+    """(queue_max_n as {"f64": [d1, d2, d3], "f32c": [...]}, source)."""
+    v = (ctypes.c_int64 * 6)()
+    src = ctypes.create_string_buffer(4096)
+    _check(_lib.mecdf_tuning(v, src, 4096), "mecdf_tuning")
+    return {"f64": list(v[0:3]), "f32c": list(v[3:6])}, src.value.decode()
+
+
 def bw_features(datasets, stream=None):
     """(nsets, 32) float32 GPU tensor of summary features (C ABI
     ``mecdf_bw_features``)."""

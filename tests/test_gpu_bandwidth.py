@@ -236,3 +236,90 @@ def test_bw_train_from_seed_and_checkpoint_resume(lib, tmp_path):
     with pytest.raises(lib.MecdfError) as e:
         lib.bw_train(feat, label + 64, hgrid, 1, 2e-3, 0.5, seed=9)
     assert e.value.code == lib.MECDF_EINVAL
+
+
+def _mixed_sets(qn, rn, seed):
+    """Datasets on both sides of the queue sizes qn / rn per dimension, with
+    bandwidth lists of different lengths (one empty)."""
+    g = np.random.default_rng(seed)
+    sets, hs = [], []
+    for d in (1, 2, 3):
+        for n in (qn[d - 1], rn[d - 1], 2, 257):
+            sets.append(datagen.mixture_dataset(g, n, d))
+            hs.append(list(np.sort(g.uniform(0.004, 1.5, size=int(g.integers(1, 7))))))
+    hs[3] = []
+    return sets, hs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32c"])
+def test_batched_queue_and_recursion_match_oracle(lib, prec):
+    """The work queue (small datasets, every pair) and the recursion (larger
+    ones) in one batched call, against the oracle's leave-one-out scores;
+    bandwidths down to 0.004 put some sums below the float ranges."""
+    old, _ = lib.tuning()
+    lib.tuning_set({"f64": [1500, 1000, 800], "f32c": [1500, 1000, 800]})
+    try:
+        sets, hs = _mixed_sets([1400, 900, 700], [2100, 1300, 1100], 41)
+        got, best = lib.kde_lcv_batched(bandwidth.to_device(sets), hs, prec=prec,
+                                        want_best=True)
+        tol = 1e-12 if prec == "f64" else 1e-5
+        for x, h, r, b in zip(sets, hs, got, best.cpu().numpy()):
+            if not h:
+                assert b == -1
+                continue
+            ref = oracle.lcv(x, np.asarray(h))
+            r = r.cpu().numpy()
+            assert np.all(np.abs(r - ref) <= tol * np.maximum(1.0, np.abs(ref))), (x.shape, h)
+            assert b == int(np.argmax(r))
+    finally:
+        lib.tuning_set(old)
+
+
+def test_lcv_plan_replays_the_batch(lib):
+    """A recorded plan gives the eager call's scores bit for bit, on every
+    replay, and follows in-place changes of the data's values."""
+    old, _ = lib.tuning()
+    lib.tuning_set({"f64": [1500, 1000, 800], "f32c": [1500, 1000, 800]})
+    try:
+        sets, hs = _mixed_sets([1400, 900, 700], [2100, 1300, 1100], 43)
+        dev = bandwidth.to_device(sets)
+        want, wbest = lib.kde_lcv_batched(dev, hs, want_best=True)
+        plan = lib.LcvPlan(dev, hs)
+        for _ in range(3):
+            got, best = plan.run()
+            torch.cuda.synchronize()
+            for a, b in zip(want, got):
+                assert torch.equal(a, b)
+            assert torch.equal(best, wbest)
+            # eager work between replays
+            lib.kde_lcv_batched(dev[:2], hs[:2])
+        for x in dev:
+            x.mul_(1.25)
+        want2, _ = lib.kde_lcv_batched(dev, hs, want_best=True)
+        got2, _ = plan.run()
+        torch.cuda.synchronize()
+        for a, b in zip(want2, got2):
+            assert torch.equal(a, b)
+        plan.close()
+    finally:
+        lib.tuning_set(old)
+
+
+def test_autotune_writes_its_choice(lib, tmp_path):
+    import json
+
+    old, _ = lib.tuning()
+    path = str(tmp_path / "tune.json")
+    try:
+        lib.autotune(path)
+        doc = json.load(open(path))
+        assert doc["arch"].startswith("gfx")
+        sizes = {0, 512, 1024, 2048, 4096, 8192, 16384, 32768}
+        for p in ("f64", "f32c"):
+            assert len(doc["kde_queue_max_n"][p]) == 3
+            assert all(v in sizes for v in doc["kde_queue_max_n"][p])
+        now, src = lib.tuning()
+        assert src == path and now == doc["kde_queue_max_n"]
+        assert len(doc["ms_64_bandwidths"]) == 2 * 3 * 7
+    finally:
+        lib.tuning_set(old)
