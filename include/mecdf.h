@@ -155,10 +155,9 @@ int ecdf_esf_grid_noalloc(int d, int64_t N, const double *x, const void *y,
  *   F   device, N results in input order
  *
  * Limits: N <= 2^26 (MECDF_EUNSUPPORTED above).  Results are deterministic.
- * Above the direct-evaluation size (N > 2^16, or the value of the
- * environment variable MECDF_POINTS_DIRECT_MAX) the call waits for the
- * device once, to read the number of points without a NaN coordinate before
- * it enqueues the recursion.
+ * Up to N = 2^16 (or the value of the environment variable
+ * MECDF_POINTS_DIRECT_MAX) every pair is evaluated directly; above, the
+ * divide-and-conquer recursion runs.  Neither waits for the device.
  */
 int ecdf_points(int d, int64_t N, const double *x, const void *y, void *F,
                 int prec, void *stream);

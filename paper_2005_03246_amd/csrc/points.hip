@@ -100,15 +100,15 @@ __global__ __launch_bounds__(256) void k_rank_scatter(const uint32_t *__restrict
         *U = r + 1;
 }
 
-// Two item slots per point: 2i data, 2i+1 query.  Invalid slots get the
-// largest top key so they sort last; nvalid counts the valid ones.
+// Two item slots per point: 2i data, 2i+1 query.  Inert slots (see below)
+// get the largest top key so they sort last.
 template <int NC, typename YT>
 __global__ __launch_bounds__(256) void k_make_items(
     const uint32_t *__restrict__ rank /*[d][N]*/, const uint32_t *__restrict__ U,
     const uint32_t *__restrict__ drop, const YT *__restrict__ y, int64_t N, int d,
     int survival, uint64_t invalid_key, uint64_t *__restrict__ topkey,
     uint32_t *__restrict__ slot, Item<NC> *__restrict__ items,
-    double *__restrict__ W, unsigned int *__restrict__ nvalid) {
+    double *__restrict__ W) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N)
         return;
@@ -140,7 +140,12 @@ __global__ __launch_bounds__(256) void k_make_items(
         di.c[k] = 0u;
         qi.c[k] = 0u;
     }
-    di.idt = ((uint32_t)i << kIdShift) | 0u;
+    // A point with a NaN coordinate counts for no query: its data item is
+    // made a query (it only receives), and its results are discarded in
+    // k_points_out, like those of a survival query below every point.  Such
+    // items sort after all others (invalid_key) and run through the
+    // recursion, so the number of items is 2N whatever the data.
+    di.idt = ((uint32_t)i << kIdShift) | (ok ? 0u : 1u);
     qi.idt = ((uint32_t)i << kIdShift) | 1u;
     topkey[2 * i] = ok ? (((uint64_t)a0 << 1) | 0ull) : invalid_key;
     topkey[2 * i + 1] = qok ? (((uint64_t)(b0 < 0 ? 0 : b0) << 1) | 1ull) : invalid_key;
@@ -152,12 +157,9 @@ __global__ __launch_bounds__(256) void k_make_items(
         double w = 1.0;
         if constexpr (!std::is_same<YT, NoPayload>::value)
             w = (double)y[i];
-        W[2 * i] = w;
+        W[2 * i] = ok ? w : 0.0;
         W[2 * i + 1] = 0.0;
     }
-    unsigned int c = (ok ? 1u : 0u) + (qok ? 1u : 0u);
-    if (c)
-        atomicAdd(nvalid, c);
 }
 
 template <int NC>
@@ -884,14 +886,26 @@ __global__ __launch_bounds__(256) void k_d1_collect(const Item<1> *__restrict__ 
         reinterpret_cast<T *>(acc_raw)[idt >> kIdShift] = P[p];
 }
 
+// The result of point i, 0 for a point with a NaN coordinate and, for the
+// survival function, for a point at the largest rank of some coordinate (no
+// point is strictly above it there).
 template <typename OutT, typename AccT>
 __global__ __launch_bounds__(256) void k_points_out(const AccT *__restrict__ acc,
                                                     int64_t N, int scale,
-                                                    OutT *__restrict__ F) {
+                                                    const uint32_t *__restrict__ drop,
+                                                    const uint32_t *__restrict__ rank,
+                                                    const uint32_t *__restrict__ U, int d,
+                                                    int survival, OutT *__restrict__ F) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N)
         return;
-    if constexpr (std::is_same<AccT, int64_t>::value)
+    bool zero = drop[i] != 0u;
+    if (survival)
+        for (int k = 0; k < d; ++k)
+            zero = zero || rank[(int64_t)k * N + i] + 1u == U[k];
+    if (zero)
+        F[i] = (OutT)0;
+    else if constexpr (std::is_same<AccT, int64_t>::value)
         F[i] = (OutT)acc[i];
     else
         F[i] = scale ? (OutT)(acc[i] / (double)N) : (OutT)acc[i];
@@ -1041,7 +1055,6 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     pl.add<uint32_t>((size_t)N * d);       // ranks
     pl.add<uint32_t>((size_t)N);           // drop
     pl.add<uint32_t>(8);                   // U
-    pl.add<uint32_t>(1);                   // nvalid
     pl.add<uint64_t>((size_t)n2);          // topkey x3
     pl.add<uint64_t>((size_t)n2);
     pl.add<uint64_t>((size_t)n2);
@@ -1084,7 +1097,6 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     uint32_t *rank = a.take<uint32_t>((size_t)N * d);
     uint32_t *drop = a.take<uint32_t>((size_t)N);
     uint32_t *U = a.take<uint32_t>(8);
-    unsigned int *nvalid = a.take<unsigned int>(1);
     uint64_t *tk0 = a.take<uint64_t>((size_t)n2), *tk1 = a.take<uint64_t>((size_t)n2),
              *tk2 = a.take<uint64_t>((size_t)n2);
     uint32_t *sl0 = a.take<uint32_t>((size_t)n2), *sl1 = a.take<uint32_t>((size_t)n2),
@@ -1135,9 +1147,8 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     // ---- items, sorted by (coordinate 0, type)
     const int kb = bits_for((uint64_t)N) + 1;
     const uint64_t invalid_key = (kb >= 63) ? ~0ull : ((1ull << (kb + 1)) - 1ull);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, (uint32_t *)nvalid, (int64_t)1);
     hipLaunchKernelGGL((k_make_items<NC, YT>), dim3(nbN), dim3(256), 0, s, rank, U, drop, y,
-                       N, d, survival, invalid_key, tk0, sl0, items, Wslot, nvalid);
+                       N, d, survival, invalid_key, tk0, sl0, items, Wslot);
     MECDF_LAUNCH_CHECK();
     int which = 0;
     {
@@ -1146,10 +1157,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
                                                        kb + 1, rs, s, &which)));
     }
     uint32_t *perm = which == 1 ? sl1 : (which == 2 ? sl2 : sl0);
-    unsigned int hn = 0;
-    MECDF_TRY_HIP(hipMemcpyAsync(&hn, nvalid, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-    MECDF_TRY_HIP(hipStreamSynchronize(s));
-    const int64_t n = hn;
+    const int64_t n = n2;  // every item, the inert ones last
     dnc.n = n;
     hipLaunchKernelGGL((k_gather_items<NC>), dim3((unsigned)ceil_div(n > 0 ? n : 1, 256)),
                        dim3(256), 0, s, perm, n, items, Wslot, dnc.S[1], dnc.SW[1]);
@@ -1175,7 +1183,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
         }
     }
     hipLaunchKernelGGL((k_points_out<OutT, AccT>), dim3(nbN), dim3(256), 0, s, dnc.acc, N,
-                       kW ? 1 : 0, F);
+                       kW ? 1 : 0, drop, rank, U, d, survival, F);
     MECDF_LAUNCH_CHECK();
     return MECDF_OK;
 }

@@ -138,3 +138,20 @@ def test_points_deterministic(lib, path):
     a = lib.ecdf_points(x, y)
     b = lib.ecdf_points(x, y)
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("d", [1, 3, 4])
+def test_nan_points_weighted(lib, path, d):
+    """Points with a NaN coordinate count for nothing and get 0, with
+    weights too, in d = 1, 3, 4 (the recursion keeps them as items that only
+    receive, and discards what they receive)."""
+    g = np.random.default_rng(60 + d)
+    n = 1500
+    x = np.round(g.normal(size=(d, n)), 1)
+    x[d - 1, ::9] = np.nan
+    x[0, 5::13] = np.nan
+    y = g.integers(-3, 4, size=n).astype(np.float64)
+    for fn, ofn in ((lib.ecdf_points, oracle.ecdf), (lib.esf_points, oracle.esf)):
+        np.testing.assert_array_equal(fn(dev(x)).cpu().numpy(), ofn(x, x))
+        want, _ = ofn(x, x, y)
+        np.testing.assert_array_equal(fn(dev(x), dev(y)).cpu().numpy(), want)
