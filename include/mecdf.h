@@ -144,6 +144,26 @@ int ecdf_esf_grid_noalloc(int d, int64_t N, const double *x, const void *y,
                           int prec, void *stream);
 
 /*
+ * mecdf_grid_interp -- values given at the nodes of a rectilinear grid (for
+ * example the output of ecdf_grid) at arbitrary points, by multilinear
+ * interpolation: the route from a grid evaluation to values at the sample
+ * points whose error Section 4.1 (ECDF) and Section 4.2 (KDE) measure.
+ *
+ *   d, M, z  the grid as in ecdf_grid (host), any sizes M_k >= 1
+ *   G        device, prod(M_k) values in C order (double, or float with
+ *            MECDF_F32C; interpolation is computed in float64)
+ *   Q, q     Q >= 0 points, device d*Q doubles, q[k*Q + p]
+ *   out      device Q results (type of G)
+ *
+ * Along each axis a point outside [z_0, z_{M-1}] takes the value at the
+ * nearest end node (no extrapolation); an axis with one node is constant; a
+ * NaN coordinate gives NaN.
+ */
+int mecdf_grid_interp(int d, const int64_t *M, const double *z, const void *G,
+                      int64_t Q, const double *q, void *out, int prec,
+                      void *stream);
+
+/*
  * ecdf_points -- generalized ECDF at the sample points themselves
  * (Section 2.2): F[j] = F_N(x_j) = (1/N) sum_i y_i 1{x_i <= x_j componentwise}.
  * Unlike the recursion's own output in Section 2.2, which leaves the point

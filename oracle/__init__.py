@@ -10,7 +10,9 @@ Langrene & Warin, arXiv 2005.03246:
   the same section;
 * leave-one-out likelihood and squared-error cross-validation scores built
   from those sums (Section 3.2 notes that infinite-support kernels such as
-  the Laplacian suit likelihood cross-validation).
+  the Laplacian suit likelihood cross-validation);
+* linear interpolation of grid values to arbitrary points (Sections 4.1 and
+  4.2), through scipy's regular-grid interpolator.
 
 The arithmetic lives in ``oracle.c`` (a double loop over query and data
 point, Neumaier-compensated FP64 sums, OpenMP over queries).  This module only
@@ -307,3 +309,36 @@ def nw_cv(x, y, h, nthreads=0):
     """Squared-error LOO CV score CV(h) = (1/N) sum_j (y_j - m_{-j}(x_j))^2."""
     m, _, _, _ = nw_loo(x, y, h, nthreads)
     return ((_f64(y)[None, :] - m) ** 2).mean(axis=1)
+
+
+# --------------------------------------------------------------------------
+# grid -> point interpolation (Sections 4.1 and 4.2 interpolate grid values
+# linearly to the sample points)
+# --------------------------------------------------------------------------
+def grid_interp(nodes, G, q):
+    """Multilinear interpolation of node values G (shape (M_1..M_d)) at the
+    points q (d, Q): each coordinate clipped to its axis's node range (no
+    extrapolation), axes with a single node dropped (constant), then
+    scipy's RegularGridInterpolator with method "linear"."""
+    from scipy.interpolate import RegularGridInterpolator
+
+    q = _as_2d(q)
+    G = np.asarray(G, dtype=np.float64)
+    axes, pts, keep = [], [], []
+    for k, z in enumerate(nodes):
+        z = np.asarray(z, dtype=np.float64)
+        if len(z) == 1:
+            continue
+        keep.append(k)
+        axes.append(z)
+        qk = np.where(np.isnan(q[k]), z[0], q[k])  # NaN rows are set to NaN below
+        pts.append(np.clip(qk, z[0], z[-1]))
+    single = [k for k in range(len(nodes)) if k not in keep]
+    Gk = G[tuple(0 if k in single else slice(None) for k in range(len(nodes)))]
+    if keep:
+        f = RegularGridInterpolator(tuple(axes), Gk, method="linear")
+        out = f(np.stack(pts, axis=1))
+    else:
+        out = np.full(q.shape[1], float(Gk))
+    out[np.any(np.isnan(q), axis=0)] = np.nan
+    return out

@@ -39,6 +39,8 @@ void lcv_plan_destroy(void *plan);
 int autotune(const char *path, hipStream_t s);
 int tuning_info(int64_t *queue_max, char *source, int cap);
 int tuning_set(const int64_t *queue_max);
+int grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,
+                const double *q, void *out, int prec, hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -61,6 +63,28 @@ int check_common(int d, int64_t N, const double *x, int prec, int maxd) {
         return fail(MECDF_EINVAL, "x is NULL");
     if (prec != MECDF_F64 && prec != MECDF_F32C)
         return fail(MECDF_EINVAL, "prec must be MECDF_F64 or MECDF_F32C");
+    return MECDF_OK;
+}
+
+// per-axis node counts >= 1 (at most max_m), finite strictly increasing nodes
+int check_nodes(int d, const int64_t *M, const double *z, int64_t max_m) {
+    if (M == nullptr || z == nullptr)
+        return fail(MECDF_EINVAL, "grid sizes M and nodes z are required");
+    int64_t off = 0;
+    for (int k = 0; k < d; ++k) {
+        if (M[k] < 1)
+            return fail(MECDF_EINVAL, "grid size M_k must be >= 1");
+        if (M[k] > max_m)
+            return fail(MECDF_EUNSUPPORTED, "grid size M_k too large");
+        for (int64_t j = 0; j < M[k]; ++j) {
+            double v = z[off + j];
+            if (!std::isfinite(v))
+                return fail(MECDF_EINVAL, "grid nodes must be finite");
+            if (j > 0 && !(z[off + j - 1] < v))
+                return fail(MECDF_EINVAL, "grid nodes must be strictly increasing per axis");
+        }
+        off += M[k];
+    }
     return MECDF_OK;
 }
 
@@ -580,6 +604,22 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
             evals_out[i] = evals[i];
     }
     return MECDF_OK;
+}
+
+int mecdf_grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,
+                      const double *q, void *out, int prec, void *stream) {
+    if (d < 1 || d > MECDF_MAX_DIM)
+        return fail(MECDF_EINVAL, "d must be in 1.." + std::to_string(MECDF_MAX_DIM));
+    if (prec != MECDF_F64 && prec != MECDF_F32C)
+        return fail(MECDF_EINVAL, "prec must be MECDF_F64 or MECDF_F32C");
+    if (Q < 0)
+        return fail(MECDF_EINVAL, "Q must be >= 0");
+    if (Q >= (int64_t(1) << 40))
+        return fail(MECDF_EUNSUPPORTED, "Q too large");
+    MECDF_TRY(check_nodes(d, M, z, int64_t(1) << 24));
+    if (Q > 0 && (G == nullptr || q == nullptr || out == nullptr))
+        return fail(MECDF_EINVAL, "G, q and out are required");
+    return grid_interp(d, M, z, G, Q, q, out, prec, (hipStream_t)stream);
 }
 
 void mecdf_release(void) { mecdf::workspace_release_all(); }

@@ -157,6 +157,34 @@ def ecdf_esf_grid(x: torch.Tensor, nodes, y=None, prec="f64", want_ecdf=True,
     return F, Fb
 
 
+_lib.mecdf_grid_interp.argtypes = [_I, _P, _P, _P, _I64, _P, _P, _I, _P]
+_lib.mecdf_grid_interp.restype = _I
+
+
+def grid_interp(G: torch.Tensor, nodes, q: torch.Tensor, stream=None):
+    """Multilinear interpolation of grid values G (shape (M_1, ..., M_d),
+    float64 or float32 GPU tensor) at the points q (d, Q) (C ABI
+    ``mecdf_grid_interp``).  Returns (Q,) of G's dtype."""
+    q = _x(q)
+    d, Q = q.shape
+    if len(nodes) != d or G.dim() != d:
+        raise ValueError("need one node vector per dimension of G and q")
+    ms, zs, shape = _grid_args(nodes)
+    if tuple(G.shape) != shape:
+        raise ValueError("G's shape must be the node counts")
+    if G.dtype == torch.float64:
+        p = MECDF_F64
+    elif G.dtype == torch.float32:
+        p = MECDF_F32C
+    else:
+        raise TypeError("G must be float64 or float32")
+    G = G.contiguous()
+    out = torch.empty((Q,), dtype=G.dtype, device=q.device)
+    _check(_lib.mecdf_grid_interp(d, ms, zs, _ptr(G), Q, _ptr(q), _ptr(out), p,
+                                  _stream_ptr(stream)), "mecdf_grid_interp")
+    return out
+
+
 def ecdf_grid(x, nodes, y=None, prec="f64", stream=None):
     """F_N at every grid node (C ABI ``ecdf_grid``)."""
     x = _x(x)

@@ -305,3 +305,41 @@ def test_nw_loo_ratio_under_underflow():
     assert m[0, 2] == pytest.approx(2.0, rel=1e-15)
     cv = oracle.nw_cv(x, y, [0.01])[0]
     assert cv == pytest.approx(((1 - m[0, 0]) ** 2 + 4 + 4) / 3, rel=1e-15)
+
+
+# ------------------------------------------------- grid -> point interpolation
+def test_interp_reproduces_multilinear_functions():
+    """Multilinear interpolation is exact for functions that are affine in
+    each coordinate separately (a + sum b_k z_k + c z_0 z_1 + e z_0 z_1 z_2)."""
+    g = np.random.default_rng(21)
+    nodes = [np.sort(g.uniform(-2, 2, 7)), np.sort(g.uniform(-1, 3, 5)),
+             np.sort(g.uniform(0, 1, 4))]
+    Z = np.meshgrid(*nodes, indexing="ij")
+    f = lambda a, b, c: 0.3 + 1.5 * a - 2.0 * b + 0.7 * c + 0.9 * a * b - 1.1 * a * b * c
+    G = f(*Z)
+    q = np.stack([g.uniform(z[0], z[-1], 200) for z in nodes])
+    np.testing.assert_allclose(oracle.grid_interp(nodes, G, q), f(*q), rtol=1e-12, atol=1e-12)
+
+
+def test_interp_nodes_clamping_and_1d():
+    g = np.random.default_rng(22)
+    z = np.sort(g.uniform(0, 1, 9))
+    v = g.normal(size=9)
+    q = np.concatenate([z, [-1.0, 2.0], g.uniform(-0.5, 1.5, 50)])
+    # one dimension: numpy's interp clamps outside the nodes in the same way
+    np.testing.assert_allclose(oracle.grid_interp([z], v, q[None]), np.interp(q, z, v),
+                               rtol=1e-14, atol=1e-15)
+    # at the nodes the node values, in two dimensions, and a one-node axis
+    z2 = np.sort(g.uniform(0, 1, 4))
+    G = g.normal(size=(9, 4))
+    Zq = np.array([[z[i], z2[j]] for i in range(9) for j in range(4)]).T
+    np.testing.assert_allclose(oracle.grid_interp([z, z2], G, Zq), G.reshape(-1), rtol=1e-14)
+    G1 = g.normal(size=(9, 1))
+    qq = np.stack([g.uniform(0, 1, 20), g.uniform(-5, 5, 20)])
+    np.testing.assert_allclose(oracle.grid_interp([z, [0.5]], G1, qq),
+                               np.interp(qq[0], z, G1[:, 0]), rtol=1e-14)
+    # a NaN coordinate gives NaN, the other points are unaffected
+    qn = qq.copy()
+    qn[1, 3] = np.nan
+    r = oracle.grid_interp([z, [0.5]], G1, qn)
+    assert np.isnan(r[3]) and not np.any(np.isnan(np.delete(r, 3)))
