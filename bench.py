@@ -288,7 +288,50 @@ def secondary():
                 }
             rec["kernels"] = kern
         out["kde_nw_d2_N2^22_64h_" + prec] = rec
+    # the same sample on a 1024^2 grid (fast-summation KDE and NW at the nodes)
+    log("secondary: grid kernel sums d=2 N=2^22 1024^2")
+    nodes4 = datagen.uniform_grid(x4, 1024)
+    h4g = h4[[0, 21, 42, 63]]
+    ms_g = _time_calls(lambda: mecdf.kde_laplace_grid(x4t, nodes4, h4g), 2, 1)
+    ms_gr = _time_calls(lambda: mecdf.kreg_laplace_grid(x4t, y4t, nodes4, h4g), 2, 1)
+    out["grid_kde_nw_d2_N2^22_1024^2_4h_f64"] = {
+        "ms_kde": ms_g, "ms_nw": ms_gr,
+        "Gpoint-evals/s": 2 * 4 * 1024 ** 2 / ((ms_g + ms_gr) * 1e-3) / 1e9}
+    del x4t, y4t
+    out["interpolation_error_study"] = interpolation_study()
     return out
+
+
+def interpolation_study():
+    """Sections 4.1 / 4.2: the grid evaluation (M = N nodes, M_k = N^(1/d))
+    linearly interpolated to the sample points against the exact values at the
+    points, X ~ N(0, I_d), h = 0.1 for the KDE; maximum absolute error over
+    the N points (ECDF normalised by N)."""
+    import numpy as np
+    import torch
+
+    from paper_2005_03246_amd import datagen, mecdf
+
+    log("secondary: interpolation error study")
+    res = []
+    g = np.random.default_rng(4_1)
+    for d in (2, 3):
+        for n in (20000, 160000, 1280000):
+            x = torch.from_numpy(g.normal(size=(d, n))).cuda()
+            m = int(round(n ** (1.0 / d)))
+            nodes = datagen.uniform_grid(x.cpu().numpy(), m)
+            F, _ = mecdf.ecdf_esf_grid(x, nodes, want_esf=False)
+            ecdf_i = mecdf.grid_interp(F.double() / n, nodes, x)
+            ecdf_x = mecdf.ecdf_points(x).double() / n
+            rec = {"d": d, "N": n, "grid": [m] * d,
+                   "ecdf_max_abs_error": float(torch.max(torch.abs(ecdf_i - ecdf_x)))}
+            if d == 2:
+                fg = mecdf.kde_laplace_grid(x, nodes, [0.1])[0]
+                fx, _ = mecdf.kde_laplace(x, [0.1], want_lcv=False)
+                rec["kde_max_abs_error"] = float(torch.max(torch.abs(
+                    mecdf.grid_interp(fg, nodes, x) - fx[0])))
+            res.append(rec)
+    return res
 
 
 def bandwidth_eval(train_count):

@@ -237,6 +237,39 @@ int kde_laplace(int d, int64_t N, const double *x, const void *w, int nh,
 int kreg_laplace(int d, int64_t N, const double *x, const void *y, int nh,
                  const double *h, void *m, double *cv, int prec, void *stream);
 
+/*
+ * kde_laplace_grid -- the Laplacian kernel density estimate of kde_laplace at
+ * every node of a rectilinear grid (the paper's "fast summation" KDE,
+ * Section 3 with the grid of Section 2.1):
+ *
+ *   f[b*G + node] = 1/(2^d N prod_k h_{b,k}) sum_i w_i exp(-sum_k |x_{k,i} - z_k| / h_{b,k})
+ *
+ * for the G = prod(M_k) nodes z in C order.  Each point's weight is carried
+ * to the nodes of its cell's corners (factors <= 1) and spread by decayed
+ * scans along every axis, 2^d channels: O(N + 2^d d G) per bandwidth.
+ *
+ *   x, w, nh, h, prec  as kde_laplace (N >= 1)
+ *   M, z               the grid as ecdf_grid (host)
+ *   f                  device nh*G results (double, or float with MECDF_F32C)
+ *
+ * Points with a NaN coordinate are left out.  Far from every point the sums
+ * underflow to 0 as float64 sums do.  Float32 weights and results are
+ * converted; the arithmetic is float64.  Limits: prod(M_k + 1) < 2^31 - 1
+ * cells.  Deterministic.
+ */
+int kde_laplace_grid(int d, int64_t N, const double *x, const void *w,
+                     const int64_t *M, const double *z, int nh, const double *h,
+                     void *f, int prec, void *stream);
+
+/*
+ * kreg_laplace_grid -- the Nadaraya-Watson estimate of kreg_laplace at every
+ * grid node: m[b*G + node] = sum_i y_i K / sum_i K (NaN where both sums
+ * underflow).  Arguments as kde_laplace_grid with y the response.
+ */
+int kreg_laplace_grid(int d, int64_t N, const double *x, const void *y,
+                      const int64_t *M, const double *z, int nh, const double *h,
+                      void *m, int prec, void *stream);
+
 /* ---------------------------------------------------------------------
  * Bandwidth selection (batched exact LOO likelihood cross-validation, and a
  * learned proposal that only decides where to evaluate it).

@@ -41,6 +41,9 @@ int tuning_info(int64_t *queue_max, char *source, int cap);
 int tuning_set(const int64_t *queue_max);
 int grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,
                 const double *q, void *out, int prec, hipStream_t s);
+int gridkde_run(int d, int64_t N, const double *x, const void *w, const int64_t *M,
+                const double *z, int nh, const double *h, void *out, int regression, int prec,
+                hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -604,6 +607,47 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
             evals_out[i] = evals[i];
     }
     return MECDF_OK;
+}
+
+static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, const double *z,
+                         int nh, const double *h, void *out, int prec) {
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (N < 1)
+        return fail(MECDF_EINVAL, "grid kernel sums need N >= 1");
+    if (nh < 1 || nh > 256)
+        return fail(MECDF_EINVAL, "nh must be in 1..256");
+    if (h == nullptr || out == nullptr)
+        return fail(MECDF_EINVAL, "h and the output are required");
+    for (int i = 0; i < nh * d; ++i)
+        if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+            return fail(MECDF_EINVAL, "bandwidths must be positive and finite");
+    MECDF_TRY(check_nodes(d, M, z, int64_t(1) << 24));
+    double cells = 1.0, nodes = 1.0;
+    for (int k = 0; k < d; ++k) {
+        cells *= (double)(M[k] + 1);
+        nodes *= (double)M[k];
+    }
+    if (cells >= 2147483647.0)
+        return fail(MECDF_EUNSUPPORTED, "grid has 2^31 - 1 or more cells");
+    if (nodes * (double)(1 << d) * 2.0 * 8.0 > 64e9)
+        return fail(MECDF_EUNSUPPORTED, "grid too large for the 2^d channel arrays");
+    return MECDF_OK;
+}
+
+int kde_laplace_grid(int d, int64_t N, const double *x, const void *w, const int64_t *M,
+                     const double *z, int nh, const double *h, void *f, int prec,
+                     void *stream) {
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, f, prec));
+    return gridkde_run(d, N, x, w, M, z, nh, h, f, 0, prec, (hipStream_t)stream);
+}
+
+int kreg_laplace_grid(int d, int64_t N, const double *x, const void *y, const int64_t *M,
+                      const double *z, int nh, const double *h, void *m, int prec,
+                      void *stream) {
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, m, prec));
+    if (y == nullptr)
+        return fail(MECDF_EINVAL, "y is NULL");
+    return gridkde_run(d, N, x, y, M, z, nh, h, m, 1, prec, (hipStream_t)stream);
 }
 
 int mecdf_grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,

@@ -288,6 +288,48 @@ def kreg_laplace(x, y, h, prec="f64", want_m=True, want_cv=True, stream=None):
     return m, cv
 
 
+_lib.kde_laplace_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
+_lib.kde_laplace_grid.restype = _I
+_lib.kreg_laplace_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
+_lib.kreg_laplace_grid.restype = _I
+
+
+def kde_laplace_grid(x, nodes, h, w=None, prec="f64", stream=None):
+    """Laplacian KDE at every grid node (C ABI ``kde_laplace_grid``):
+    (nh, M_1, ..., M_d) tensor."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    w = _y(w, n, p, x)
+    ms, zs, shape = _grid_args(nodes)
+    hm = _hmat(h, d)
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    f = torch.empty((hm.shape[0],) + shape, dtype=dt, device=x.device)
+    _check(_lib.kde_laplace_grid(d, n, _ptr(x), _ptr(w), ms, zs, hm.shape[0], hs, _ptr(f), p,
+                                 _stream_ptr(stream)), "kde_laplace_grid")
+    return f
+
+
+def kreg_laplace_grid(x, y, nodes, h, prec="f64", stream=None):
+    """Nadaraya-Watson regression at every grid node (C ABI
+    ``kreg_laplace_grid``): (nh, M_1, ..., M_d) tensor."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    if y is None:
+        raise ValueError("kreg_laplace_grid needs the response y")
+    ms, zs, shape = _grid_args(nodes)
+    hm = _hmat(h, d)
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    m = torch.empty((hm.shape[0],) + shape, dtype=dt, device=x.device)
+    _check(_lib.kreg_laplace_grid(d, n, _ptr(x), _ptr(y), ms, zs, hm.shape[0], hs, _ptr(m), p,
+                                  _stream_ptr(stream)), "kreg_laplace_grid")
+    return m
+
+
 def release():
     """Free the library's device workspaces."""
     _lib.mecdf_release()

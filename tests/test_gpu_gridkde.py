@@ -1,0 +1,95 @@
+"""Laplacian kernel sums at grid nodes (kde_laplace_grid / kreg_laplace_grid,
+the paper's fast-summation KDE) against the brute-force oracle at every node:
+densities within 1e-12 (float64) / 1e-5 (float32) of the |w|-weighted scale,
+NW ratios within 1e-12 / 1e-5 of max |y|."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_03246_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_03246_amd import mecdf
+
+    return mecdf
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def hmat(hs, d):
+    return np.repeat(np.asarray(hs, dtype=float)[:, None], d, 1)
+
+
+CASES = [(1, 1, [5]), (1, 700, [1]), (1, 900, [40]), (2, 2, [3, 4]), (2, 1500, [17, 23]),
+         (2, 3000, [64, 1]), (3, 1200, [9, 7, 11]), (4, 600, [5, 4, 6, 3])]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_grid_kde_and_nw_random(lib, case):
+    d, n, m = case
+    g = np.random.default_rng(300 + 11 * d + n)
+    x = np.round(g.normal(size=(d, n)), 2)
+    w = g.uniform(0.2, 2.0, n)
+    y = np.sin(x[0]) + 0.1 * g.normal(size=n)
+    # nodes reaching past the data, and data values among them (ties with nodes)
+    nodes = []
+    for k in range(d):
+        z = np.sort(g.uniform(-3.0, 3.0, m[k]))
+        if m[k] > 2:
+            z[m[k] // 2] = x[k, 0]
+            z = np.unique(z)
+        nodes.append(z)
+    hs = hmat([0.05, 0.3, 1.5], d)
+    hs[1] = g.uniform(0.1, 0.6, d)
+    zq = oracle.grid_points(nodes)
+    f = lib.kde_laplace_grid(dev(x), nodes, hs, dev(w)).cpu().numpy().reshape(len(hs), -1)
+    want, scale = oracle.kde_laplace(x, zq, hs, w)
+    nz = scale > 0
+    assert np.all(f[~nz] == 0)
+    assert np.max(np.abs(f[nz] - want[nz]) / scale[nz]) <= 1e-12
+    mm = lib.kreg_laplace_grid(dev(x), dev(y), nodes, hs).cpu().numpy().reshape(len(hs), -1)
+    wm = oracle.nw_regression(x, y, zq, hs)
+    ok = np.isfinite(wm)
+    assert np.array_equal(np.isfinite(mm), ok)
+    assert np.max(np.abs(mm[ok] - wm[ok])) <= 1e-12 * np.max(np.abs(y))
+    # float32 weights and results
+    f32 = lib.kde_laplace_grid(dev(x), nodes, hs, dev(w.astype(np.float32), torch.float32),
+                               prec="f32c").cpu().numpy().reshape(len(hs), -1)
+    w32, s32 = oracle.kde_laplace(x, zq, hs, w.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(f32[nz] - w32[nz]) / s32[nz]) <= 1e-5
+
+
+def test_grid_kde_paper_accuracy_claim(lib):
+    """Section 4.2: the fast-summation KDE within 1e-14 of the naive sums for
+    X ~ N(0, I_2), h = 0.1; here N = 20000 points and a 141 x 141 grid over
+    the data (about N nodes), float64, maximum absolute difference."""
+    g = np.random.default_rng(42)
+    x = g.normal(size=(2, 20000))
+    nodes = datagen.uniform_grid(x, 141)
+    f = lib.kde_laplace_grid(dev(x), nodes, [0.1]).cpu().numpy().reshape(-1)
+    want, _ = oracle.kde_laplace(x, oracle.grid_points(nodes), hmat([0.1], 2))
+    assert np.max(np.abs(f - want[0])) < 1e-14
+
+
+def test_grid_kde_interpolated_to_the_points(lib):
+    """Section 4.2's route to the sample points: the grid KDE interpolated
+    linearly to the points against the exact KDE there; finer grids are
+    closer."""
+    g = np.random.default_rng(43)
+    x = g.normal(size=(2, 20000))
+    xt = dev(x)
+    exact, _ = lib.kde_laplace(xt, [0.3], want_lcv=False)
+    exact = exact[0].cpu().numpy()
+    errs = []
+    for m in (70, 141, 282):
+        nodes = datagen.uniform_grid(x, m)
+        f = lib.kde_laplace_grid(xt, nodes, [0.3])[0]
+        errs.append(np.max(np.abs(lib.grid_interp(f, nodes, xt).cpu().numpy() - exact)))
+    assert errs[2] < errs[1] < errs[0]
