@@ -238,6 +238,45 @@ int kreg_laplace(int d, int64_t N, const double *x, const void *y, int nh,
                  const double *h, void *m, double *cv, int prec, void *stream);
 
 /*
+ * kde_laplace_H / kreg_laplace_H -- kde_laplace and kreg_laplace with general
+ * symmetric positive definite bandwidth matrices (Appendix B,
+ * eq. (kde_nD_H)), read as the paper does: with H = R diag(h)^2 R^T, the
+ * estimator with diagonal bandwidth h in the coordinates R^T x,
+ *
+ *   f[b*N + j] = 1/(2^d N prod_k h_k) sum_i w_i exp(-|| diag(1/h) R^T (x_i - x_j) ||_1).
+ *
+ * (For the product form of the Laplacian kernel this depends on R, which is
+ * unique up to the signs and order of its columns when the eigenvalues are
+ * distinct; with a repeated eigenvalue the eigenvectors the library's Jacobi
+ * sweeps find are used.)  H: host, nh row-major d x d matrices; the points
+ * are rotated on the device and the kernel sums run as in kde_laplace (one
+ * pass per matrix).  Other arguments as kde_laplace / kreg_laplace;
+ * MECDF_EINVAL for a matrix that is not positive definite or whose two
+ * triangles differ by more than 1e-12 of its largest entry (otherwise its
+ * symmetric part is used).
+ */
+int kde_laplace_H(int d, int64_t N, const double *x, const void *w, int nh,
+                  const double *H, void *f, double *lcv, int prec, void *stream);
+int kreg_laplace_H(int d, int64_t N, const double *x, const void *y, int nh,
+                   const double *H, void *m, double *cv, int prec, void *stream);
+
+/*
+ * kreg_loclin_laplace -- local-linear regression with the Laplacian kernel at
+ * the sample points: m[b*N + j] is the intercept of the weighted
+ * least-squares fit of y ~ a + c^T (x - x_j) with weights
+ * exp(-sum_k |x_{k,i} - x_{k,j}| / h_{b,k}) (the point itself included).
+ * Its moments are kernel sums with the weights 1, x_l, x_l x_m, y and y x_l
+ * (1 + d + d(d+1)/2 + 1 + d calls of the kernel-sum path per bandwidth,
+ * float64), expanded about x_j, and a (d+1) x (d+1) system per point is
+ * solved with partial pivoting; where a pivot is below 1e-10 of the largest
+ * diagonal entry the local constant (Nadaraya-Watson) estimate is returned.
+ * The expansion about x_j loses about (|x_j| / local spread)^2 in relative
+ * accuracy to cancellation.  Arguments as kreg_laplace (m required).
+ */
+int kreg_loclin_laplace(int d, int64_t N, const double *x, const void *y, int nh,
+                        const double *h, void *m, int prec, void *stream);
+
+/*
  * kde_laplace_grid -- the Laplacian kernel density estimate of kde_laplace at
  * every node of a rectilinear grid (the paper's "fast summation" KDE,
  * Section 3 with the grid of Section 2.1):

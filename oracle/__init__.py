@@ -342,3 +342,87 @@ def grid_interp(nodes, G, q):
         out = np.full(q.shape[1], float(Gk))
     out[np.any(np.isnan(q), axis=0)] = np.nan
     return out
+
+
+# --------------------------------------------------------------------------
+# general matrix bandwidth (Appendix B, eq. (kde_nD_H)) and local-linear
+# regression with the Laplacian kernel
+# --------------------------------------------------------------------------
+def matrix_bandwidth(H):
+    """H = R diag(h)^2 R^T (numpy's symmetric eigendecomposition): (R, h)."""
+    H = np.asarray(H, dtype=np.float64)
+    ev, R = np.linalg.eigh(H)
+    if np.any(ev <= 0):
+        raise ValueError("H must be positive definite")
+    return R, np.sqrt(ev)
+
+
+def kde_laplace_H(x, z, Hs, w=None, nthreads=0):
+    """eq. (kde_nD_H) with the Laplacian kernel, read as in Appendix B: the
+    estimator with diagonal bandwidth h in the rotated coordinates R^T x, R^T z
+    (H = R diag(h)^2 R^T), so fhat(z) = 1/(2^d N prod h) sum_i w_i
+    exp(-|| diag(1/h) R^T (x_i - z) ||_1).  Hs: (nh, d, d).  Returns (f, A)
+    of shape (nh, Q) like kde_laplace."""
+    x = _as_2d(x)
+    z = _as_2d(z)
+    fs, As = [], []
+    for H in np.asarray(Hs, dtype=np.float64):
+        R, h = matrix_bandwidth(H)
+        f, a = kde_laplace(R.T @ x, R.T @ z, h[None, :], w, nthreads)
+        fs.append(f[0])
+        As.append(a[0])
+    return np.array(fs), np.array(As)
+
+
+def nw_regression_H(x, y, z, Hs, nthreads=0):
+    """NW ratio with a matrix bandwidth, in the coordinates of kde_laplace_H."""
+    x = _as_2d(x)
+    z = _as_2d(z)
+    out = []
+    for H in np.asarray(Hs, dtype=np.float64):
+        R, h = matrix_bandwidth(H)
+        out.append(nw_regression(R.T @ x, y, R.T @ z, h[None, :], nthreads)[0])
+    return np.array(out)
+
+
+def local_linear(x, y, z, h):
+    """Local-linear regression at the points z (d, Q): the intercept a of the
+    weighted least-squares fit of y ~ a + b^T (x - z_j) with Laplacian weights
+    exp(-sum_k |x_k - z_k| / h_k), from the moments about z_j formed directly
+    (no expansion).  Where the (d+1) x (d+1) system has a pivot below 1e-10 of
+    its largest diagonal entry (Gaussian elimination with partial pivoting),
+    the local constant (NW) estimate.  Pure Python loops over the queries:
+    small cases only."""
+    x = _as_2d(x)
+    z = _as_2d(z)
+    y = _f64(y)
+    h = np.asarray(h, dtype=np.float64).reshape(-1)
+    d, n = x.shape
+    out = np.empty(z.shape[1])
+    for j in range(z.shape[1]):
+        u = x - z[:, j:j + 1]
+        k = np.exp(-np.sum(np.abs(u) / h[:, None], axis=0))
+        X = np.vstack([np.ones(n), u])          # (d+1, N)
+        A = (X * k) @ X.T
+        rhs = (X * k) @ y
+        M = np.hstack([A, rhs[:, None]])
+        dmax = np.max(np.abs(np.diag(A)))
+        ok = dmax > 0
+        m = d + 1
+        for c in range(m):
+            if not ok:
+                break
+            p = c + int(np.argmax(np.abs(M[c:, c])))
+            if not abs(M[p, c]) > 1e-10 * dmax:
+                ok = False
+                break
+            M[[c, p]] = M[[p, c]]
+            M[c + 1:] -= np.outer(M[c + 1:, c] / M[c, c], M[c])
+        if ok:
+            sol = np.zeros(m)
+            for r in range(m - 1, -1, -1):
+                sol[r] = (M[r, m] - M[r, r + 1:m] @ sol[r + 1:]) / M[r, r]
+            out[j] = sol[0]
+        else:
+            out[j] = rhs[0] / A[0, 0]
+    return out

@@ -44,6 +44,10 @@ int grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t
 int gridkde_run(int d, int64_t N, const double *x, const void *w, const int64_t *M,
                 const double *z, int nh, const double *h, void *out, int regression, int prec,
                 hipStream_t s);
+int kde_matrix_run(int d, int64_t N, const double *x, const void *w, int nh, const double *H,
+                   void *f, double *score, int regression, int prec, hipStream_t s);
+int loclin_run(int d, int64_t N, const double *x, const void *y, int nh, const double *h,
+               void *m, int prec, hipStream_t s);
 }  // namespace mecdf
 
 using namespace mecdf;
@@ -607,6 +611,51 @@ int mecdf_bw_select(const mecdf_dataset *sets, int nsets, const float *params, i
             evals_out[i] = evals[i];
     }
     return MECDF_OK;
+}
+
+static int check_matrices(int d, int nh, const double *H) {
+    if (nh < 1 || nh > 256)
+        return fail(MECDF_EINVAL, "nh must be in 1..256");
+    if (H == nullptr)
+        return fail(MECDF_EINVAL, "H is NULL");
+    for (int i = 0; i < nh * d * d; ++i)
+        if (!std::isfinite(H[i]))
+            return fail(MECDF_EINVAL, "bandwidth matrices must be finite");
+    return MECDF_OK;
+}
+
+int kde_laplace_H(int d, int64_t N, const double *x, const void *w, int nh, const double *H,
+                  void *f, double *lcv, int prec, void *stream) {
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (N < 2)
+        return fail(MECDF_EINVAL, "kernel sums at the points need N >= 2");
+    MECDF_TRY(check_matrices(d, nh, H));
+    if (f == nullptr && lcv == nullptr)
+        return fail(MECDF_EINVAL, "no output requested");
+    return kde_matrix_run(d, N, x, w, nh, H, f, lcv, 0, prec, (hipStream_t)stream);
+}
+
+int kreg_laplace_H(int d, int64_t N, const double *x, const void *y, int nh, const double *H,
+                   void *m, double *cv, int prec, void *stream) {
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (N < 2)
+        return fail(MECDF_EINVAL, "kernel sums at the points need N >= 2");
+    MECDF_TRY(check_matrices(d, nh, H));
+    if (y == nullptr)
+        return fail(MECDF_EINVAL, "y is NULL");
+    if (m == nullptr && cv == nullptr)
+        return fail(MECDF_EINVAL, "no output requested");
+    return kde_matrix_run(d, N, x, y, nh, H, m, cv, 1, prec, (hipStream_t)stream);
+}
+
+int kreg_loclin_laplace(int d, int64_t N, const double *x, const void *y, int nh,
+                        const double *h, void *m, int prec, void *stream) {
+    MECDF_TRY(kde_check(d, N, x, nh, h, m, nullptr, prec));
+    if (y == nullptr)
+        return fail(MECDF_EINVAL, "y is NULL");
+    if (m == nullptr)
+        return fail(MECDF_EINVAL, "m is NULL");
+    return loclin_run(d, N, x, y, nh, h, m, prec, (hipStream_t)stream);
 }
 
 static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, const double *z,

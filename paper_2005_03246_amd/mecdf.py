@@ -330,6 +330,71 @@ def kreg_laplace_grid(x, y, nodes, h, prec="f64", stream=None):
     return m
 
 
+_lib.kde_laplace_H.argtypes = [_I, _I64, _P, _P, _I, _P, _P, _P, _I, _P]
+_lib.kde_laplace_H.restype = _I
+_lib.kreg_laplace_H.argtypes = [_I, _I64, _P, _P, _I, _P, _P, _P, _I, _P]
+_lib.kreg_laplace_H.restype = _I
+_lib.kreg_loclin_laplace.argtypes = [_I, _I64, _P, _P, _I, _P, _P, _I, _P]
+_lib.kreg_loclin_laplace.restype = _I
+
+
+def _hmats(Hs, d):
+    import numpy as np
+
+    H = np.ascontiguousarray(np.asarray(Hs, dtype=np.float64))
+    if H.ndim == 2:
+        H = H[None]
+    if H.ndim != 3 or H.shape[1:] != (d, d):
+        raise ValueError("bandwidth matrices must be (nh, d, d)")
+    return H, (ctypes.c_double * H.size)(*H.reshape(-1).tolist())
+
+
+def kde_laplace_H(x, Hs, w=None, prec="f64", want_f=True, want_lcv=True, stream=None):
+    """kde_laplace with bandwidth matrices (C ABI ``kde_laplace_H``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    w = _y(w, n, p, x)
+    H, hs = _hmats(Hs, d)
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    f = torch.empty((H.shape[0], n), dtype=dt, device=x.device) if want_f else None
+    lcv = torch.empty((H.shape[0],), dtype=torch.float64, device=x.device) if want_lcv else None
+    _check(_lib.kde_laplace_H(d, n, _ptr(x), _ptr(w), H.shape[0], hs, _ptr(f), _ptr(lcv), p,
+                              _stream_ptr(stream)), "kde_laplace_H")
+    return f, lcv
+
+
+def kreg_laplace_H(x, y, Hs, prec="f64", want_m=True, want_cv=True, stream=None):
+    """kreg_laplace with bandwidth matrices (C ABI ``kreg_laplace_H``)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    H, hs = _hmats(Hs, d)
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    m = torch.empty((H.shape[0], n), dtype=dt, device=x.device) if want_m else None
+    cv = torch.empty((H.shape[0],), dtype=torch.float64, device=x.device) if want_cv else None
+    _check(_lib.kreg_laplace_H(d, n, _ptr(x), _ptr(y), H.shape[0], hs, _ptr(m), _ptr(cv), p,
+                               _stream_ptr(stream)), "kreg_laplace_H")
+    return m, cv
+
+
+def kreg_loclin_laplace(x, y, h, prec="f64", stream=None):
+    """Local-linear regression at the sample points (C ABI
+    ``kreg_loclin_laplace``): (nh, N)."""
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    hm = _hmat(h, d)
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    m = torch.empty((hm.shape[0], n), dtype=dt, device=x.device)
+    _check(_lib.kreg_loclin_laplace(d, n, _ptr(x), _ptr(y), hm.shape[0], hs, _ptr(m), p,
+                                    _stream_ptr(stream)), "kreg_loclin_laplace")
+    return m
+
+
 def release():
     """Free the library's device workspaces."""
     _lib.mecdf_release()

@@ -343,3 +343,55 @@ def test_interp_nodes_clamping_and_1d():
     qn[1, 3] = np.nan
     r = oracle.grid_interp([z, [0.5]], G1, qn)
     assert np.isnan(r[3]) and not np.any(np.isnan(np.delete(r, 3)))
+
+
+# ------------------------------------------ matrix bandwidth and local linear
+def test_matrix_bandwidth_diagonal_and_rotation_invariance():
+    g = np.random.default_rng(51)
+    x = g.normal(size=(2, 60))
+    z = g.normal(size=(2, 9))
+    # a diagonal H is the per-axis bandwidth h = sqrt(diag)
+    f, _ = oracle.kde_laplace_H(x, z, [np.diag([0.09, 0.25])])
+    want, _ = oracle.kde_laplace(x, z, np.array([[0.3, 0.5]]))
+    np.testing.assert_allclose(f, want, rtol=1e-13)
+    # rotating the data, the points and H together changes nothing
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    H = np.array([[0.2, 0.05], [0.05, 0.1]])
+    a, _ = oracle.kde_laplace_H(x, z, [H])
+    b, _ = oracle.kde_laplace_H(Q @ x, Q @ z, [Q @ H @ Q.T])
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+def test_matrix_bandwidth_two_points_by_hand():
+    """H with eigenvectors at 45 degrees, eigenvalues 0.25 and 1: one data
+    point at the origin seen from (1, 1): R^T (x - z) = (0, -sqrt 2) up to
+    signs, so the kernel is exp(-sqrt(2) / 1) / 4 and f = that / (N h1 h2)."""
+    c = 1 / np.sqrt(2)
+    R = np.array([[c, -c], [c, c]])
+    H = R @ np.diag([1.0, 0.25]) @ R.T
+    f, _ = oracle.kde_laplace_H(np.zeros((2, 1)), np.ones((2, 1)), [H])
+    want = np.exp(-np.sqrt(2.0) / 1.0) / 4.0 / (1.0 * 0.5)
+    assert f[0, 0] == pytest.approx(want, rel=1e-13)
+
+
+def test_local_linear_reproduces_linear_functions():
+    g = np.random.default_rng(52)
+    for d in (1, 2, 3):
+        x = g.normal(size=(d, 80))
+        b = g.normal(size=d)
+        y = 0.4 + b @ x
+        z = g.normal(size=(d, 7))
+        got = oracle.local_linear(x, y, z, np.full(d, 0.6))
+        np.testing.assert_allclose(got, 0.4 + b @ z, rtol=1e-10, atol=1e-10)
+
+
+def test_local_linear_large_bandwidth_is_least_squares():
+    g = np.random.default_rng(53)
+    x = g.normal(size=(2, 50))
+    y = np.sin(x[0]) + x[1] ** 2
+    z = g.normal(size=(2, 5))
+    got = oracle.local_linear(x, y, z, np.full(2, 1e7))
+    X = np.vstack([np.ones(50), x]).T
+    coef = np.linalg.lstsq(X, y, rcond=None)[0]
+    np.testing.assert_allclose(got, coef[0] + coef[1:] @ z, rtol=1e-6, atol=1e-6)
