@@ -285,7 +285,9 @@ int kreg_loclin_laplace(int d, int64_t N, const double *x, const void *y, int nh
  *
  * for the G = prod(M_k) nodes z in C order.  Each point's weight is carried
  * to the nodes of its cell's corners (factors <= 1) and spread by decayed
- * scans along every axis, 2^d channels: O(N + 2^d d G) per bandwidth.
+ * scans along every axis, 2^d channels, the two channels of a corner pair
+ * added after the scan of their axis: O(N log N) once and O(N + 2^d G) per
+ * bandwidth.
  *
  *   x, w, nh, h, prec  as kde_laplace (N >= 1)
  *   M, z               the grid as ecdf_grid (host)
@@ -308,6 +310,33 @@ int kde_laplace_grid(int d, int64_t N, const double *x, const void *w,
 int kreg_laplace_grid(int d, int64_t N, const double *x, const void *y,
                       const int64_t *M, const double *z, int nh, const double *h,
                       void *m, int prec, void *stream);
+
+/*
+ * kde_matern32_grid -- kernel density estimate at every grid node with the
+ * additive multivariate Matern-3/2 kernel of Appendix C, eq.
+ * (Matern32_average), K_d(u) = (1 + sum_k |u_k|) exp(-sum_k |u_k|) /
+ * (2^d (1 + d)), u = (x - z) / h:
+ *
+ *   f[b*G + node] = 1/(N prod_k h_{b,k}) sum_i w_i K_d((x_i - z) / h_b)
+ *
+ * through its CDF decomposition (eq. (Matern32_decomposition_nD)): 2^d (d+1)
+ * channels, the plain exponential sums and one distance-weighted sum per
+ * axis, spread by decayed scans (the distance sums move with the plain sums
+ * along their own axis).  Arguments, layout, errors and precision as
+ * kde_laplace_grid; d <= 4 (MECDF_EUNSUPPORTED above).
+ */
+int kde_matern32_grid(int d, int64_t N, const double *x, const void *w,
+                      const int64_t *M, const double *z, int nh, const double *h,
+                      void *f, int prec, void *stream);
+
+/*
+ * kreg_matern32_grid -- the Nadaraya-Watson estimate with the same kernel at
+ * every grid node: m[b*G + node] = sum_i y_i K / sum_i K (NaN where both sums
+ * underflow).  Arguments as kreg_laplace_grid; d <= 4.
+ */
+int kreg_matern32_grid(int d, int64_t N, const double *x, const void *y,
+                       const int64_t *M, const double *z, int nh, const double *h,
+                       void *m, int prec, void *stream);
 
 /* ---------------------------------------------------------------------
  * Bandwidth selection (batched exact LOO likelihood cross-validation, and a

@@ -64,6 +64,10 @@ def _load():
         lib.oracle_laplace_loo_shifted.argtypes = [I, I64, P, I, P, I, P, P,
                                                    P, P, I]
         lib.oracle_laplace_loo_shifted.restype = I
+        lib.oracle_ecdf_delta.argtypes = [I, I64, P, P, I64, P, P, P, P, P, I]
+        lib.oracle_ecdf_delta.restype = I
+        lib.oracle_kernel_sums.argtypes = [I, I, I64, P, I, P, I64, P, I, P, P, P, I]
+        lib.oracle_kernel_sums.restype = I
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = I
         _lib = lib
@@ -144,6 +148,36 @@ def esf(x, z, y=None, nthreads=0):
         return r
     n = _as_2d(x).shape[1]
     return r[0] / n, r[1] / n
+
+
+def ecdf_delta(x, z, delta, y=None, nthreads=0):
+    """F_N(z, delta; x, y) of eq. (ECDFdelta) without the 1/N factor, at the
+    points z (d, Q) with a sign pattern per point: delta (Q,) bit masks, bit
+    k set for delta_k = -1 (strict < on axis k), clear for <=.  y None: int64
+    counts, else (sum, abs_sum)."""
+    x = _as_2d(x)
+    z = _as_2d(z)
+    d, n = x.shape
+    q = z.shape[1]
+    dl = np.ascontiguousarray(delta, dtype=np.uint8)
+    if z.shape[0] != d or dl.shape != (q,):
+        raise ValueError("z must be (d, Q) and delta (Q,)")
+    lib = _load()
+    if y is None:
+        cnt = np.zeros(q, dtype=np.int64)
+        rc = lib.oracle_ecdf_delta(d, n, _ptr(x), None, q, _ptr(z), _ptr(dl), _ptr(cnt),
+                                   None, None, int(nthreads))
+        if rc:
+            raise ValueError("oracle_ecdf_delta rejected its arguments")
+        return cnt
+    y = _f64(y)
+    s = np.zeros(q)
+    a = np.zeros(q)
+    rc = lib.oracle_ecdf_delta(d, n, _ptr(x), _ptr(y), q, _ptr(z), _ptr(dl), None, _ptr(s),
+                               _ptr(a), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ecdf_delta rejected its arguments")
+    return s, a
 
 
 def grid_points(nodes, index=None) -> np.ndarray:
@@ -309,6 +343,71 @@ def nw_cv(x, y, h, nthreads=0):
     """Squared-error LOO CV score CV(h) = (1/N) sum_j (y_j - m_{-j}(x_j))^2."""
     m, _, _, _ = nw_loo(x, y, h, nthreads)
     return ((_f64(y)[None, :] - m) ** 2).mean(axis=1)
+
+
+# --------------------------------------------------------------------------
+# the uniform kernel (Section 3.2) and the additive Matern-3/2 kernel
+# (Appendix C)
+# --------------------------------------------------------------------------
+def kernel_sums(kind, x, z, h, w=None, nthreads=0):
+    """Raw sums of the uniform ("uniform": prod_k 1{z_k - h_k <= x_k <= z_k +
+    h_k}, both ends rounded to doubles) or additive Matern-3/2 ("matern32":
+    (1 + e) exp(-e), e = sum_k |x_k - z_k| / h_k) kernel; conventions of
+    laplace_sums without skip.  Returns (S, A) of shape (nw, nh, Q)."""
+    kd = {"uniform": 0, "matern32": 1}[kind]
+    x = _as_2d(x)
+    z = _as_2d(z)
+    d, n = x.shape
+    q = z.shape[1]
+    h = _f64(_hmat(h, d))
+    nh = h.shape[0]
+    if w is None:
+        wv, nw = None, 1
+    else:
+        wv = _f64(w)
+        if wv.ndim == 1:
+            wv = wv[None, :]
+        nw = wv.shape[0]
+        wv = _f64(wv)
+    s = np.zeros((nw, nh, q))
+    a = np.zeros((nw, nh, q))
+    rc = _load().oracle_kernel_sums(kd, d, n, _ptr(x), nw, _ptr(wv), q, _ptr(z), nh, _ptr(h),
+                                    _ptr(s), _ptr(a), int(nthreads))
+    if rc:
+        raise ValueError("oracle_kernel_sums rejected its arguments")
+    return s, a
+
+
+def kde_uniform(x, z, h, w=None, nthreads=0):
+    """f_KDE(z) of eq. (uniform_kde_nD), 1/(2^d N prod h) times the box sums:
+    (nh, Q) values and the |w| scale."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    s, a = kernel_sums("uniform", x, z, hm, w, nthreads)
+    c = 1.0 / (2.0 ** d * n * np.prod(hm, axis=1))
+    return s[0] * c[:, None], a[0] * c[:, None]
+
+
+def kde_matern32(x, z, h, w=None, nthreads=0):
+    """The kernel density estimate with the additive Matern-3/2 kernel of eq.
+    (Matern32_average), K_d(u) = (1 + |u|_1) exp(-|u|_1) / (2^d (1 + d)):
+    (nh, Q) values and the |w| scale."""
+    x = _as_2d(x)
+    d, n = x.shape
+    hm = _hmat(h, d)
+    s, a = kernel_sums("matern32", x, z, hm, w, nthreads)
+    c = 1.0 / (2.0 ** d * (1 + d) * n * np.prod(hm, axis=1))
+    return s[0] * c[:, None], a[0] * c[:, None]
+
+
+def nw_matern32(x, y, z, h, nthreads=0):
+    """Nadaraya-Watson ratio with the additive Matern-3/2 kernel: (nh, Q)."""
+    x = _as_2d(x)
+    hm = _hmat(h, x.shape[0])
+    s, _ = kernel_sums("matern32", x, z, hm, np.stack([np.ones_like(_f64(y)), _f64(y)]),
+                       nthreads)
+    return s[1] / s[0]
 
 
 # --------------------------------------------------------------------------

@@ -285,3 +285,130 @@ int oracle_laplace_loo_shifted(int d, int64_t N, const double *x, int nw,
         }
     return 0;
 }
+
+/*
+ * Generalized ECDF of eq. (ECDFdelta), Section 1, at query points with a
+ * sign pattern per query, without the 1/N factor:
+ *
+ *   S_q = sum_i y_i * prod_k [ x_{k,i} <=_{delta_{k,q}} z_{k,q} ]
+ *
+ * where <=_{+1} is <= and <=_{-1} is the strict <.  delta[q] is a bit mask:
+ * bit k set means delta_{k,q} = -1.  Counts / sums as oracle_dominance.
+ */
+int oracle_ecdf_delta(int d, int64_t N, const double *x, const double *y,
+                      int64_t Q, const double *z, const unsigned char *delta,
+                      int64_t *out_cnt, double *out_sum, double *out_abs,
+                      int nthreads)
+{
+    if (d < 1 || d > 8 || N < 0 || Q < 0 || !x || !z || !delta)
+        return -1;
+    if (!y && !out_cnt)
+        return -1;
+    if (y && (!out_sum || !out_abs))
+        return -1;
+    set_threads(nthreads);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < Q; ++q) {
+        int64_t cnt = 0;
+        nsum_t s = {0.0, 0.0}, a = {0.0, 0.0};
+        for (int64_t i = 0; i < N; ++i) {
+            int inside = 1;
+            for (int k = 0; k < d && inside; ++k) {
+                double xi = x[(int64_t)k * N + i];
+                double zq = z[(int64_t)k * Q + q];
+                inside = ((delta[q] >> k) & 1) ? (xi < zq) : (xi <= zq);
+            }
+            if (!inside)
+                continue;
+            if (y) {
+                nsum_add(&s, y[i]);
+                nsum_add(&a, fabs(y[i]));
+            } else {
+                ++cnt;
+            }
+        }
+        if (y) {
+            out_sum[q] = nsum_get(&s);
+            out_abs[q] = nsum_get(&a);
+        } else {
+            out_cnt[q] = cnt;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Kernel sums of two more compatible kernels (Section 3.2 and Appendix C),
+ * without their normalising constants, for nw weight channels and nh
+ * bandwidth vectors, layout as oracle_laplace_sums:
+ *
+ *   kind 0, uniform (eq. (uniform_kde_nD)):
+ *     S = sum_i w_i prod_k [ lo_k <= x_{k,i} <= hi_k ],
+ *     lo_k = z_k - h_k and hi_k = z_k + h_k, each rounded to a double
+ *   kind 1, additive Matern-3/2 (eq. (Matern32_average)): with
+ *     e_i = sum_k |x_{k,i} - z_k| / h_k,  S = sum_i w_i (1 + e_i) exp(-e_i)
+ *
+ * A holds the same sums with |w_i|.
+ */
+int oracle_kernel_sums(int kind, int d, int64_t N, const double *x, int nw,
+                       const double *w, int64_t Q, const double *z, int nh,
+                       const double *h, double *out_sum, double *out_abs,
+                       int nthreads)
+{
+    if (d < 1 || N < 0 || Q < 0 || nh < 1 || !x || !z || !h || !out_sum ||
+        !out_abs || (kind != 0 && kind != 1))
+        return -1;
+    if (w == NULL)
+        nw = 1;
+    if (nw < 1 || nw > 8 || nh > 64)
+        return -1;
+    for (int b = 0; b < nh; ++b)
+        for (int k = 0; k < d; ++k)
+            if (!(h[b * d + k] > 0.0))
+                return -1;
+    set_threads(nthreads);
+
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < Q; ++q) {
+        nsum_t acc_s[8 * 64], acc_a[8 * 64];
+        for (int t = 0; t < nw * nh; ++t) {
+            acc_s[t].s = acc_s[t].c = 0.0;
+            acc_a[t].s = acc_a[t].c = 0.0;
+        }
+        for (int64_t i = 0; i < N; ++i) {
+            for (int b = 0; b < nh; ++b) {
+                double kv;
+                if (kind == 0) {
+                    int inside = 1;
+                    for (int k = 0; k < d && inside; ++k) {
+                        double xi = x[(int64_t)k * N + i];
+                        double zq = z[(int64_t)k * Q + q];
+                        double hk = h[b * d + k];
+                        double lo = zq - hk, hi = zq + hk;
+                        inside = lo <= xi && xi <= hi;
+                    }
+                    kv = inside ? 1.0 : 0.0;
+                } else {
+                    double e = 0.0;
+                    for (int k = 0; k < d; ++k)
+                        e += fabs(x[(int64_t)k * N + i] - z[(int64_t)k * Q + q]) /
+                             h[b * d + k];
+                    kv = (1.0 + e) * exp(-e);
+                }
+                for (int c = 0; c < nw; ++c) {
+                    double wc = w ? w[(int64_t)c * N + i] : 1.0;
+                    nsum_add(&acc_s[c * nh + b], wc * kv);
+                    nsum_add(&acc_a[c * nh + b], fabs(wc) * kv);
+                }
+            }
+        }
+        for (int c = 0; c < nw; ++c)
+            for (int b = 0; b < nh; ++b) {
+                int64_t o = ((int64_t)c * nh + b) * Q + q;
+                out_sum[o] = nsum_get(&acc_s[c * nh + b]);
+                out_abs[o] = nsum_get(&acc_a[c * nh + b]);
+            }
+    }
+    return 0;
+}

@@ -42,8 +42,8 @@ int tuning_set(const int64_t *queue_max);
 int grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,
                 const double *q, void *out, int prec, hipStream_t s);
 int gridkde_run(int d, int64_t N, const double *x, const void *w, const int64_t *M,
-                const double *z, int nh, const double *h, void *out, int regression, int prec,
-                hipStream_t s);
+                const double *z, int nh, const double *h, void *out, int regression,
+                int matern, int prec, hipStream_t s);
 int kde_matrix_run(int d, int64_t N, const double *x, const void *w, int nh, const double *H,
                    void *f, double *score, int regression, int prec, hipStream_t s);
 int loclin_run(int d, int64_t N, const double *x, const void *y, int nh, const double *h,
@@ -659,8 +659,10 @@ int kreg_loclin_laplace(int d, int64_t N, const double *x, const void *y, int nh
 }
 
 static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, const double *z,
-                         int nh, const double *h, void *out, int prec) {
+                         int nh, const double *h, void *out, int prec, int matern) {
     MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (matern && d > 4)
+        return fail(MECDF_EUNSUPPORTED, "the Matern-3/2 grid sums take d <= 4");
     if (N < 1)
         return fail(MECDF_EINVAL, "grid kernel sums need N >= 1");
     if (nh < 1 || nh > 256)
@@ -678,7 +680,9 @@ static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, co
     }
     if (cells >= 2147483647.0)
         return fail(MECDF_EUNSUPPORTED, "grid has 2^31 - 1 or more cells");
-    if (nodes * (double)(1 << d) * 2.0 * 8.0 > 64e9)
+    // the corner arrays and their half-size scan outputs, two values each
+    const double slots = matern ? (double)(1 + d) : 1.0;
+    if (nodes * 1.5 * (double)(1 << d) * slots * 2.0 * 8.0 > 64e9)
         return fail(MECDF_EUNSUPPORTED, "grid too large for the 2^d channel arrays");
     return MECDF_OK;
 }
@@ -686,17 +690,33 @@ static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, co
 int kde_laplace_grid(int d, int64_t N, const double *x, const void *w, const int64_t *M,
                      const double *z, int nh, const double *h, void *f, int prec,
                      void *stream) {
-    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, f, prec));
-    return gridkde_run(d, N, x, w, M, z, nh, h, f, 0, prec, (hipStream_t)stream);
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, f, prec, 0));
+    return gridkde_run(d, N, x, w, M, z, nh, h, f, 0, 0, prec, (hipStream_t)stream);
 }
 
 int kreg_laplace_grid(int d, int64_t N, const double *x, const void *y, const int64_t *M,
                       const double *z, int nh, const double *h, void *m, int prec,
                       void *stream) {
-    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, m, prec));
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, m, prec, 0));
     if (y == nullptr)
         return fail(MECDF_EINVAL, "y is NULL");
-    return gridkde_run(d, N, x, y, M, z, nh, h, m, 1, prec, (hipStream_t)stream);
+    return gridkde_run(d, N, x, y, M, z, nh, h, m, 1, 0, prec, (hipStream_t)stream);
+}
+
+int kde_matern32_grid(int d, int64_t N, const double *x, const void *w, const int64_t *M,
+                      const double *z, int nh, const double *h, void *f, int prec,
+                      void *stream) {
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, f, prec, 1));
+    return gridkde_run(d, N, x, w, M, z, nh, h, f, 0, 1, prec, (hipStream_t)stream);
+}
+
+int kreg_matern32_grid(int d, int64_t N, const double *x, const void *y, const int64_t *M,
+                       const double *z, int nh, const double *h, void *m, int prec,
+                       void *stream) {
+    MECDF_TRY(gridkde_check(d, N, x, M, z, nh, h, m, prec, 1));
+    if (y == nullptr)
+        return fail(MECDF_EINVAL, "y is NULL");
+    return gridkde_run(d, N, x, y, M, z, nh, h, m, 1, 1, prec, (hipStream_t)stream);
 }
 
 int mecdf_grid_interp(int d, const int64_t *M, const double *z, const void *G, int64_t Q,

@@ -1,37 +1,59 @@
-// Laplacian kernel sums at the nodes of a rectilinear grid: the "fast
-// summation" kernel density estimate and Nadaraya-Watson regression of
-// Section 3 (eq. (Laplacian_kde_nD) evaluated through the decomposition of
-// eq. (Laplacian_decomposition_nD) on the grid of Section 2.1), in Langrene &
+// Kernel sums at the nodes of a rectilinear grid: the "fast summation" kernel
+// density estimate and Nadaraya-Watson regression of Section 3 (eq.
+// (Laplacian_kde_nD) evaluated through the decomposition of eq.
+// (Laplacian_decomposition_nD) on the grid of Section 2.1), and the same for
+// the additive multivariate Matern-3/2 kernel of Appendix C (eq.
+// (Matern32_average) through eq. (Matern32_decomposition_nD)), in Langrene &
 // Warin, arXiv 2005.03246.
 //
 // Along one axis, a point x in cell c (z_{c-1} < x <= z_c) reaches the nodes
 // j >= c through exp(-(z_j - x)/h) = exp(-(z_j - z_c)/h) exp(-(z_c - x)/h)
 // and the nodes j <= c-1 through exp(-(x - z_{c-1})/h) = exp(-(z_{c-1} -
-// z_j)/h) exp(-(x - z_{c-1})/h).  So each point puts, for every choice delta
-// in {up, down}^d, the weight w prod_k (its factor to the cell's upper or
-// lower node on axis k) into the bin of that corner node, and each of the
-// 2^d bin arrays is scanned along every axis with the decays between
-// neighbouring nodes: forward where delta_k = up, backward where down.  The
-// estimate at a node is the sum of the 2^d scanned arrays.  Every factor is
-// at most 1: nothing overflows.
+// z_j)/h) exp(-(x - z_{c-1})/h).  So each point puts, for every corner choice
+// delta in {up, down}^d, the weight w prod_k (its factor to the cell's upper
+// or lower node on axis k) into the bin of that corner node, and the 2^d bin
+// arrays are scanned along every axis with the decays between neighbouring
+// nodes: forward where delta_k = up, backward where down.  The estimate at a
+// node is the sum of the 2^d scanned arrays.  Every factor is at most 1.
 //
-//   k_gk_keys      the cell of every point (exact comparisons with the nodes),
-//                  one linear key per cell; points with a NaN coordinate are
-//                  left out
-//   radix sort     stable, so each cell's points are contiguous, in input order
-//   k_gk_bins      per cell, one thread adds its points' corner weights in
-//                  input order (float64, Neumaier) and writes one bin per
-//                  channel: no two cells share a bin of one channel
-//   k_gk_scan      the decayed prefix / suffix of one channel along one axis,
-//                  one thread per line, coalesced over the trailing axes
-//   k_gk_combine   the 2^d channels summed at each node, times the
-//                  normalisation (density) or as a ratio (regression)
+// The Matern-3/2 kernel (1 + sum_l |u_l|) exp(-sum_k |u_k|) needs, besides
+// the plain sum S, one channel T_l per axis holding sum w |x_l - z_l|/h_l
+// exp(-...): the paper's 2^d (d+1) channels.  Along the scan of axis l the
+// pair (S, T_l) moves by the affine step T <- dec (T + g S), S <- dec S,
+// with g the node gap over h (the distance of every point already summed
+// grows by g), so all terms stay positive; along the other axes T_l scans
+// like S.
+//
+// Operators along different axes commute, so after the scan along axis k the
+// two arrays of each corner pair that differ only on axis k take the same
+// operators from then on: they are added as the scan writes them, and the
+// scan of axis k + 1 works on half as many arrays.  The Matern channels of
+// the axes already scanned are added the same way into one channel R.
+//
+//   k_gk_keys      the cell of every point (exact comparisons with the
+//                  nodes), one linear key per cell; points with a NaN
+//                  coordinate get a key after every cell
+//   radix sort     stable: each cell's points are contiguous, in input order
+//   k_gk_gather    coordinates and weights in that order, once per call
+//   k_gk_starts    the first sorted position of every cell
+//   k_gk_bins      per bandwidth: one thread per cell (and corner group) adds
+//                  its points' corner weights in input order (float64,
+//                  Neumaier) and writes every bin of its corners; each bin of
+//                  each corner array belongs to exactly one cell
+//   k_gs_agg       per axis: decayed sums over chunks of kGkL nodes of every
+//   k_gs_carry     line (both directions), the values entering each chunk
+//   k_gs_apply     from those, and the scans of the chunks from their
+//                  entering values, corner pairs added as they are written
+//   k_gk_combine   times the normalisation (density) or as a ratio
+//                  (regression)
 #include <vector>
 
 #include "common.hpp"
 #include "radix.hpp"
 
 namespace mecdf {
+
+constexpr int kGkL = 16;  // nodes per scan chunk
 
 struct GkGrid {
     int d;
@@ -41,6 +63,7 @@ struct GkGrid {
     int64_t cst[MECDF_MAX_DIM];    // cell-key strides (C order)
     int64_t nst[MECDF_MAX_DIM];    // node-array strides (C order)
     int64_t nodes;                 // prod M
+    int64_t cells;                 // prod C
 };
 
 struct GkH {
@@ -75,76 +98,128 @@ __global__ __launch_bounds__(256) void k_gk_keys(GkGrid g, const double *__restr
     idx[i] = (uint32_t)i;
 }
 
-// One thread per sorted position that starts a run of equal keys: the run's
-// points (input order) give, for each channel delta (bit a set: the point's
-// upper node on axis a; clear: its lower node), the sum of
-// w_i prod_a (factor of point i to that node), written to the channel's bin
-// at the corner node; corners outside the node range are skipped.
-// CH = 1: weights w (or 1); CH = 2: channel pairs (1, y).
-template <int D, int CH, typename WT>
-__global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restrict__ zn,
-                                                 const double *__restrict__ x, int64_t n,
-                                                 uint32_t dropped,
-                                                 const uint32_t *__restrict__ key,
-                                                 const uint32_t *__restrict__ idx,
-                                                 const WT *__restrict__ w, GkH hb,
-                                                 double *__restrict__ bins) {
+// coordinates and weights in sorted order
+template <typename WT>
+__global__ __launch_bounds__(256) void k_gk_gather(const uint32_t *__restrict__ idx, int64_t n,
+                                                   int d, const double *__restrict__ x,
+                                                   const WT *__restrict__ w,
+                                                   double *__restrict__ xs,
+                                                   double *__restrict__ ws) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n)
         return;
-    const uint32_t kk = key[p];
-    if (kk == dropped || (p > 0 && key[p - 1] == kk))
+    const int64_t i = idx[p];
+    for (int a = 0; a < d; ++a)
+        xs[(int64_t)a * n + p] = x[(int64_t)a * n + i];
+    if (ws)
+        ws[p] = (double)w[i];
+}
+
+// start[c] = first sorted position whose key is >= c, c = 0 .. cells: cell
+// c holds the positions [start[c], start[c+1]); left-out points come after
+__global__ __launch_bounds__(256) void k_gk_starts(const uint32_t *__restrict__ key, int64_t n,
+                                                   int64_t cells, uint32_t *__restrict__ start) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c > cells)
         return;
-    // the cell vector of this run
-    int64_t c[D];
-    int64_t rem = kk;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        c[a] = rem / g.cst[a];
-        rem -= c[a] * g.cst[a];
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)key[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    constexpr int nch = 1 << D;
-    // Neumaier pairs per channel and value
-    double s[nch][CH], e[nch][CH];
-#pragma unroll
-    for (int q = 0; q < nch; ++q)
-#pragma unroll
-        for (int v = 0; v < CH; ++v)
-            s[q][v] = e[q][v] = 0.0;
-    for (int64_t r = p; r < n && key[r] == kk; ++r) {
-        const int64_t i = idx[r];
-        double up[D], dn[D];
+    start[c] = (uint32_t)lo;
+}
+
+// Corners per thread: all 2^D up to D = 2, else 4 (axes 0 and 1 vary; the
+// bits of the other axes are fixed by the thread's corner group).
+template <int D> constexpr int gk_ncg() { return D <= 2 ? (1 << D) : 4; }
+
+// Bin arrays: corner q, slot u (0: S; 1 + l: T_l, Matern only), value v
+// (CH = 1: the weights w or 1; CH = 2: 1 and y), each of g.nodes doubles at
+// ((q * NT + u) * CH + v) * g.nodes.
+template <int D, int CH, int NT>
+__global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restrict__ zn,
+                                                 const double *__restrict__ xs, int64_t n,
+                                                 const uint32_t *__restrict__ start,
+                                                 const double *__restrict__ w0,
+                                                 const double *__restrict__ w1, GkH hb,
+                                                 double *__restrict__ bins) {
+    constexpr int NCG = gk_ncg<D>();
+    constexpr int NG = (1 << D) / NCG;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= g.cells * NG)
+        return;
+    const int grp = (int)(t / g.cells);
+    const int64_t cell = t - (int64_t)grp * g.cells;
+    int64_t c[D];
+    {
+        int64_t rem = cell;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double v = x[(int64_t)a * n + i];
+            c[a] = rem / g.cst[a];
+            rem -= c[a] * g.cst[a];
+        }
+    }
+    const int qbase = grp * NCG;
+    double s[NCG][NT][CH], e[NCG][NT][CH];
+#pragma unroll
+    for (int q = 0; q < NCG; ++q)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int v = 0; v < CH; ++v)
+                s[q][u][v] = e[q][u][v] = 0.0;
+    const int64_t p0 = start[cell], p1 = start[cell + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+        double du[D], dd[D], fu[D], fd[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double v = xs[(int64_t)a * n + p];
             const double *z = zn + g.off[a];
-            up[a] = c[a] < g.M[a] ? exp(-(z[c[a]] - v) * hb.ih[a]) : 0.0;
-            dn[a] = c[a] > 0 ? exp(-(v - z[c[a] - 1]) * hb.ih[a]) : 0.0;
+            const bool hu = c[a] < g.M[a], hd = c[a] > 0;
+            du[a] = hu ? (z[c[a]] - v) * hb.ih[a] : 0.0;
+            dd[a] = hd ? (v - z[c[a] - 1]) * hb.ih[a] : 0.0;
+            // only the factors this thread's corners use
+            const bool vary = D <= 2 || a < 2;
+            const bool upb = ((qbase >> a) & 1) != 0;
+            fu[a] = (hu && (vary || upb)) ? exp(-du[a]) : 0.0;
+            fd[a] = (hd && (vary || !upb)) ? exp(-dd[a]) : 0.0;
         }
         double wv[CH];
         if (CH == 1) {
-            wv[0] = w ? (double)w[i] : 1.0;
+            wv[0] = w0 ? w0[p] : 1.0;
         } else {
             wv[0] = 1.0;
-            wv[CH - 1] = (double)w[i];
+            wv[CH - 1] = w1[p];
         }
 #pragma unroll
-        for (int q = 0; q < nch; ++q) {
+        for (int lq = 0; lq < NCG; ++lq) {
+            const int q = qbase + lq;
             double f = 1.0;
 #pragma unroll
             for (int a = 0; a < D; ++a)
-                f *= ((q >> a) & 1) ? up[a] : dn[a];
+                f *= ((q >> a) & 1) ? fu[a] : fd[a];
 #pragma unroll
-            for (int v = 0; v < CH; ++v) {
-                const double t = f * wv[v];
-                const double u = s[q][v] + t;
-                e[q][v] += fabs(s[q][v]) >= fabs(t) ? (s[q][v] - u) + t : (t - u) + s[q][v];
-                s[q][v] = u;
+            for (int u = 0; u < NT; ++u) {
+                const double fq =
+                    u == 0 ? f : f * (((q >> (u - 1)) & 1) ? du[u - 1] : dd[u - 1]);
+#pragma unroll
+                for (int v = 0; v < CH; ++v) {
+                    const double tv = fq * wv[v];
+                    const double sm = s[lq][u][v] + tv;
+                    e[lq][u][v] += fabs(s[lq][u][v]) >= fabs(tv) ? (s[lq][u][v] - sm) + tv
+                                                                  : (tv - sm) + s[lq][u][v];
+                    s[lq][u][v] = sm;
+                }
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < nch; ++q) {
+    for (int lq = 0; lq < NCG; ++lq) {
+        const int q = qbase + lq;
         int64_t node = 0;
         bool inside = true;
 #pragma unroll
@@ -156,15 +231,12 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
         if (!inside)
             continue;
 #pragma unroll
-        for (int v = 0; v < CH; ++v)
-            bins[((int64_t)q * CH + v) * g.nodes + node] = s[q][v] + e[q][v];
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int v = 0; v < CH; ++v)
+                bins[((int64_t)(q * NT + u) * CH + v) * g.nodes + node] =
+                    s[lq][u][v] + e[lq][u][v];
     }
-}
-
-__global__ void k_gk_zero(double *a, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n)
-        a[i] = 0.0;
 }
 
 // decays between neighbouring nodes: dec[off_a + j] = exp(-(z_j - z_{j-1}) ih_a), j >= 1
@@ -180,59 +252,308 @@ __global__ void k_gk_decays(GkGrid g, const double *__restrict__ zn, GkH hb, int
     dec[t] = j == 0 ? 0.0 : exp(-(zn[t] - zn[t - 1]) * hb.ih[a]);
 }
 
-// Decayed scan of each array of the batch (count arrays of g.nodes values)
-// along axis a: forward S_j = dec_j S_{j-1} + B_j (dir 0) or backward
-// S_j = dec_{j+1} S_{j+1} + B_j (dir 1), in place.  Thread per line.
-__global__ __launch_bounds__(256) void k_gk_scan(GkGrid g, int a, int dir,
-                                                 const double *__restrict__ dec,
-                                                 double *__restrict__ arr, int count) {
-    const int64_t lines = g.nodes / g.M[a];
+// ---- scans along one axis ------------------------------------------------
+//
+// Stage k scans axis k.  Its input holds 2^(d-k) corners (bit 0: axis k,
+// bit 1: axis k+1, ...), its output 2^(d-k-1): output corner co is the sum of
+// the forward scan of input corner 2co+1 (upper nodes on axis k) and the
+// backward scan of input corner 2co.  Slots: 0 = S; Matern: 1 = R (at k = 0
+// the channel T_0) and 1 + l = T_l for the axes l > k not yet scanned; the
+// pair (S, T_k) takes the affine step, the others the plain decay, and the
+// output's R is R + T_k.
+struct GsArgs {
+    const double *in;
+    double *out;
+    double *agg;        // [col][chunk][dir][nt]: chunk sums, then entering values
+    const double *dec;  // decays of axis k (dec[0] unused)
+    const double *z;    // nodes of axis k
+    double ih;
+    int64_t M, inner, outer, nodes, nck;
+    int nco, k, nt;
+};
+
+struct GsCol {
+    int co, v;
+    int64_t chunk, col, base;  // base: offset of this line's node 0 inside an array
+};
+
+template <int CH>
+__device__ __forceinline__ GsCol gs_map(const GsArgs &a, int64_t t) {
+    GsCol c;
+    int64_t r, oi, ii;
+    if (a.inner >= 16) {  // neighbouring threads on neighbouring lines
+        ii = t % a.inner;
+        r = t / a.inner;
+        c.chunk = r % a.nck;
+        r /= a.nck;
+    } else {              // neighbouring threads on neighbouring chunks
+        c.chunk = t % a.nck;
+        r = t / a.nck;
+        ii = r % a.inner;
+        r /= a.inner;
+    }
+    oi = r % a.outer;
+    r /= a.outer;
+    c.v = (int)(r % CH);
+    c.co = (int)(r / CH);
+    c.col = (((int64_t)c.co * CH + c.v) * a.outer + oi) * a.inner + ii;
+    c.base = oi * a.M * a.inner + ii;
+    return c;
+}
+
+template <int CH>
+__device__ __forceinline__ int64_t gs_arr(const GsArgs &a, int corner, int slot, int v) {
+    return ((int64_t)(corner * a.nt + slot) * CH + v) * a.nodes;
+}
+
+// Matern slots taking the plain decay at stage k: R (from the second stage
+// on) and the T_l of the axes l > k
+__device__ __forceinline__ bool gs_plain(const GsArgs &a, int slot) {
+    if (slot == 1)
+        return a.k >= 1;
+    return slot - 1 > a.k;
+}
+
+template <int CH, bool MAT>
+__global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= lines * count)
+    if (t >= total)
         return;
-    const int which = (int)(t / lines);
-    const int64_t l = t - (int64_t)which * lines;
-    // l enumerates the other axes in C order: split around axis a
-    const int64_t inner = g.nst[a];  // product of the sizes after axis a
-    const int64_t outer_i = l / inner, inner_i = l - outer_i * inner;
-    double *col = arr + (int64_t)which * g.nodes + outer_i * inner * g.M[a] + inner_i;
-    const double *dz = dec + g.off[a];
-    const int64_t M = g.M[a];
-    double run = 0.0;
-    if (dir == 0) {
-        for (int64_t j = 0; j < M; ++j) {
-            run = dz[j] * run + col[j * inner];
-            col[j * inner] = run;
+    const GsCol c = gs_map<CH>(a, t);
+    const int64_t j0 = c.chunk * kGkL;
+    const int64_t j1 = j0 + kGkL < a.M ? j0 + kGkL : a.M;
+    const int64_t st = a.inner;
+    double *ag = a.agg + (c.col * a.nck + c.chunk) * 2 * a.nt;
+    const int ps = 1 + a.k;  // the slot paired with S (Matern)
+    for (int dir = 0; dir < 2; ++dir) {
+        const int corner = 2 * c.co + (dir == 0 ? 1 : 0);  // forward: upper nodes
+        const double *sI = a.in + gs_arr<CH>(a, corner, 0, c.v) + c.base;
+        const double *tI = MAT ? a.in + gs_arr<CH>(a, corner, ps, c.v) + c.base : sI;
+        double rs = 0.0, rt = 0.0;
+        if (dir == 0) {
+            for (int64_t j = j0; j < j1; ++j) {
+                const double dk = j > j0 ? a.dec[j] : 0.0;
+                if (MAT) {
+                    const double gk = j > j0 ? (a.z[j] - a.z[j - 1]) * a.ih : 0.0;
+                    rt = dk * (rt + gk * rs) + tI[j * st];
+                }
+                rs = dk * rs + sI[j * st];
+            }
+        } else {
+            for (int64_t j = j1 - 1; j >= j0; --j) {
+                const double dk = j + 1 < j1 ? a.dec[j + 1] : 0.0;
+                if (MAT) {
+                    const double gk = j + 1 < j1 ? (a.z[j + 1] - a.z[j]) * a.ih : 0.0;
+                    rt = dk * (rt + gk * rs) + tI[j * st];
+                }
+                rs = dk * rs + sI[j * st];
+            }
         }
-    } else {
-        for (int64_t j = M - 1; j >= 0; --j) {
-            run = (j + 1 < M ? dz[j + 1] : 0.0) * run + col[j * inner];
-            col[j * inner] = run;
+        ag[dir * a.nt] = rs;
+        if (MAT) {
+            ag[dir * a.nt + ps] = rt;
+            for (int sl = 1; sl < a.nt; ++sl) {
+                if (!gs_plain(a, sl))
+                    continue;
+                const double *pI = a.in + gs_arr<CH>(a, corner, sl, c.v) + c.base;
+                double r = 0.0;
+                if (dir == 0)
+                    for (int64_t j = j0; j < j1; ++j)
+                        r = (j > j0 ? a.dec[j] : 0.0) * r + pI[j * st];
+                else
+                    for (int64_t j = j1 - 1; j >= j0; --j)
+                        r = (j + 1 < j1 ? a.dec[j + 1] : 0.0) * r + pI[j * st];
+                ag[dir * a.nt + sl] = r;
+            }
         }
     }
 }
 
-// out[node] = norm * sum of the 2^d channels (CH = 1), or the ratio of the
-// summed second to the summed first values (CH = 2), channels in order
+// One thread per (line, direction): the chunk sums become, in place, the
+// values entering each chunk (forward: the scan at the node before the
+// chunk; backward: at the node after it).
+template <bool MAT>
+__global__ __launch_bounds__(256) void k_gs_carry(GsArgs a, int64_t cols) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * cols)
+        return;
+    const int dir = (int)(t & 1);
+    const int64_t col = t >> 1;
+    const int ps = 1 + a.k;
+    constexpr int kMaxSlots = 1 + MECDF_MAX_DIM;
+    double cr[kMaxSlots];
+    for (int sl = 0; sl < kMaxSlots; ++sl)
+        cr[sl] = 0.0;
+    for (int64_t i = 0; i < a.nck; ++i) {
+        const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
+        double *ag = a.agg + (col * a.nck + ch) * 2 * a.nt + dir * a.nt;
+        const int64_t j0 = ch * kGkL;
+        const int64_t j1 = j0 + kGkL < a.M ? j0 + kGkL : a.M;
+        // from the entering value's node to the chunk's far end
+        double span = 0.0;
+        if (i > 0)
+            span = dir == 0 ? a.z[j1 - 1] - a.z[j0 - 1] : a.z[j1] - a.z[j0];
+        const double P = i > 0 ? exp(-span * a.ih) : 0.0;
+        const double G = span * a.ih;
+        const double s0 = cr[0];
+        {
+            const double v = ag[0];
+            ag[0] = s0;
+            cr[0] = P * s0 + v;
+        }
+        if (MAT) {
+            for (int sl = 1; sl < a.nt; ++sl) {
+                const bool pair = sl == ps;
+                if (!pair && !gs_plain(a, sl))
+                    continue;
+                const double v = ag[sl];
+                const double old = cr[sl];
+                ag[sl] = old;
+                cr[sl] = pair ? P * (old + G * s0) + v : P * old + v;
+            }
+        }
+    }
+}
+
+template <int CH, bool MAT>
+__global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total)
+        return;
+    const GsCol c = gs_map<CH>(a, t);
+    const int64_t j0 = c.chunk * kGkL;
+    const int n = (int)((j0 + kGkL < a.M ? j0 + kGkL : a.M) - j0);
+    const double *ag = a.agg + (c.col * a.nck + c.chunk) * 2 * a.nt;
+    const int ps = 1 + a.k;
+    // dk[i], gk[i]: the step between nodes j0+i-1 and j0+i (forward into
+    // j0+i, backward out of it); i = n is the step from the next chunk
+    double dk[kGkL + 1], gk[kGkL + 1];
+#pragma unroll
+    for (int i = 0; i <= kGkL; ++i) {
+        const int64_t j = j0 + i;
+        const bool ok = i <= n && j > 0 && j < a.M;
+        dk[i] = ok ? a.dec[j] : 0.0;
+        gk[i] = (MAT && ok) ? (a.z[j] - a.z[j - 1]) * a.ih : 0.0;
+    }
+    const int64_t st = a.inner;
+    const int64_t off = c.base + j0 * st;
+    const int up = 2 * c.co + 1, dn = 2 * c.co;
+    double fs[kGkL], ft[kGkL];
+    {
+        const double *sU = a.in + gs_arr<CH>(a, up, 0, c.v) + off;
+        const double *sD = a.in + gs_arr<CH>(a, dn, 0, c.v) + off;
+        const double *tU = MAT ? a.in + gs_arr<CH>(a, up, ps, c.v) + off : sU;
+        const double *tD = MAT ? a.in + gs_arr<CH>(a, dn, ps, c.v) + off : sD;
+        double *oS = a.out + gs_arr<CH>(a, c.co, 0, c.v) + off;
+        double rs = ag[0], rt = MAT ? ag[ps] : 0.0;
+#pragma unroll
+        for (int i = 0; i < kGkL; ++i) {
+            if (i < n) {
+                if (MAT)
+                    rt = dk[i] * (rt + gk[i] * rs) + tU[i * st];
+                rs = dk[i] * rs + sU[i * st];
+            }
+            fs[i] = rs;
+            ft[i] = rt;
+        }
+        rs = ag[a.nt];
+        rt = MAT ? ag[a.nt + ps] : 0.0;
+#pragma unroll
+        for (int i = kGkL - 1; i >= 0; --i) {
+            if (i < n) {
+                if (MAT)
+                    rt = dk[i + 1] * (rt + gk[i + 1] * rs) + tD[i * st];
+                rs = dk[i + 1] * rs + sD[i * st];
+                oS[i * st] = fs[i] + rs;
+                ft[i] += rt;
+            }
+        }
+    }
+    if constexpr (MAT) {
+        // R' = T_k + R (R from the second stage on)
+        double *oR = a.out + gs_arr<CH>(a, c.co, 1, c.v) + off;
+        if (a.k >= 1) {
+            const double *rU = a.in + gs_arr<CH>(a, up, 1, c.v) + off;
+            const double *rD = a.in + gs_arr<CH>(a, dn, 1, c.v) + off;
+            double r = ag[1];
+#pragma unroll
+            for (int i = 0; i < kGkL; ++i) {
+                if (i < n)
+                    r = dk[i] * r + rU[i * st];
+                ft[i] += r;
+            }
+            r = ag[a.nt + 1];
+#pragma unroll
+            for (int i = kGkL - 1; i >= 0; --i) {
+                if (i < n) {
+                    r = dk[i + 1] * r + rD[i * st];
+                    oR[i * st] = ft[i] + r;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kGkL; ++i)
+                if (i < n)
+                    oR[i * st] = ft[i];
+        }
+        // the T_l of the axes not yet scanned
+        for (int sl = 2 + a.k; sl < a.nt; ++sl) {
+            const double *pU = a.in + gs_arr<CH>(a, up, sl, c.v) + off;
+            const double *pD = a.in + gs_arr<CH>(a, dn, sl, c.v) + off;
+            double *oP = a.out + gs_arr<CH>(a, c.co, sl, c.v) + off;
+            double r = ag[sl];
+#pragma unroll
+            for (int i = 0; i < kGkL; ++i) {
+                if (i < n)
+                    r = dk[i] * r + pU[i * st];
+                fs[i] = r;
+            }
+            r = ag[a.nt + sl];
+#pragma unroll
+            for (int i = kGkL - 1; i >= 0; --i) {
+                if (i < n) {
+                    r = dk[i + 1] * r + pD[i * st];
+                    oP[i * st] = fs[i] + r;
+                }
+            }
+        }
+    }
+}
+
+// out[node] = norm * (S + R) (CH = 1), or the ratio of the second value's to
+// the first value's S + R (CH = 2); R only for the Matern kernel
 template <int CH, typename OutT>
-__global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__restrict__ bins,
-                                                    double norm, OutT *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__restrict__ fin,
+                                                    int matern, double norm,
+                                                    OutT *__restrict__ out) {
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (node >= g.nodes)
         return;
-    const int nch = 1 << g.d;
     double s[CH];
-    for (int v = 0; v < CH; ++v)
-        s[v] = 0.0;
-    for (int q = 0; q < nch; ++q)
-        for (int v = 0; v < CH; ++v)
-            s[v] += bins[((int64_t)q * CH + v) * g.nodes + node];
+#pragma unroll
+    for (int v = 0; v < CH; ++v) {
+        s[v] = fin[(int64_t)v * g.nodes + node];
+        if (matern)
+            s[v] += fin[(int64_t)(CH + v) * g.nodes + node];
+    }
     out[node] = CH == 1 ? (OutT)(s[0] * norm) : (OutT)(s[CH - 1] / s[0]);
+}
+
+template <int CH, bool MAT>
+static void gs_launch(const GsArgs &ga, int64_t cols, hipStream_t s) {
+    const int64_t tot = cols * ga.nck;
+    hipLaunchKernelGGL((k_gs_agg<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
+                       ga, tot);
+    hipLaunchKernelGGL(k_gs_carry<MAT>, dim3((unsigned)ceil_div(2 * cols, 256)), dim3(256), 0,
+                       s, ga, cols);
+    hipLaunchKernelGGL((k_gs_apply<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
+                       s, ga, tot);
 }
 
 template <int CH, typename WT, typename OutT>
 static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64_t *M,
-                     const double *z, int nh, const double *h, OutT *out, hipStream_t s) {
+                     const double *z, int nh, const double *h, OutT *out, int matern,
+                     hipStream_t s) {
     GkGrid g{};
     g.d = d;
     int64_t total = 0;
@@ -250,8 +571,17 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         ns *= g.M[a];
     }
     g.nodes = ns;
+    g.cells = cs;
     const int nch = 1 << d;
-    const int64_t nbins = (int64_t)nch * CH * g.nodes;
+    const int NT = matern ? 1 + d : 1;
+    const int64_t nA = (int64_t)nch * NT * CH * g.nodes;
+    const int64_t nB = (int64_t)(nch / 2) * NT * CH * g.nodes;
+    int64_t nagg = 0;
+    for (int a = 0; a < d; ++a) {
+        const int64_t cols = (int64_t)(nch >> (a + 1)) * CH * (g.nodes / g.M[a]);
+        nagg = std::max(nagg, cols * ceil_div(g.M[a], kGkL) * 2 * NT);
+    }
+    const bool has_w = CH == 2 || w != nullptr;
     ArenaPlan pl;
     pl.add<double>((size_t)total);          // nodes
     pl.add<double>((size_t)total);          // decays
@@ -259,7 +589,13 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         pl.add<uint32_t>((size_t)N);        // keys
     for (int q = 0; q < 3; ++q)
         pl.add<uint32_t>((size_t)N);        // point indices
-    pl.add<double>((size_t)nbins);
+    pl.add<double>((size_t)N * d);          // coordinates in cell order
+    if (has_w)
+        pl.add<double>((size_t)N);          // weights / responses in cell order
+    pl.add<uint32_t>((size_t)g.cells + 1);  // cell starts
+    pl.add<double>((size_t)nA);
+    pl.add<double>((size_t)nB);
+    pl.add<double>((size_t)nagg);
     radix_plan(pl, N);
     void *wsb = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &wsb));
@@ -271,11 +607,15 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
              *k2 = ar.take<uint32_t>((size_t)N);
     uint32_t *i0 = ar.take<uint32_t>((size_t)N), *i1 = ar.take<uint32_t>((size_t)N),
              *i2 = ar.take<uint32_t>((size_t)N);
-    double *bins = ar.take<double>((size_t)nbins);
+    double *xs = ar.take<double>((size_t)N * d);
+    double *ws = has_w ? ar.take<double>((size_t)N) : nullptr;
+    uint32_t *cstart = ar.take<uint32_t>((size_t)g.cells + 1);
+    double *bufA = ar.take<double>((size_t)nA);
+    double *bufB = ar.take<double>((size_t)nB);
+    double *agg = ar.take<double>((size_t)nagg);
     RadixScratch rs = radix_take(ar, N);
     MECDF_TRY(upload_small(z, sizeof(double) * (size_t)total, zn, s));
     const unsigned nbN = (unsigned)ceil_div(N, 256);
-    const uint32_t *ks = k0, *is = i0;
     // cell keys 0 .. cells-1, the value `cells` for points left out
     const uint32_t dropped = (uint32_t)cs;
     const int kbits = bits_for((uint64_t)cs);
@@ -285,8 +625,12 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         int which = 0;
         MECDF_TRY((radix_sort_bits<uint32_t, uint32_t>(k0, i0, k1, i1, k2, i2, N, 0, kbits, rs,
                                                        s, &which)));
-        ks = which == 1 ? k1 : (which == 2 ? k2 : k0);
-        is = which == 1 ? i1 : (which == 2 ? i2 : i0);
+        const uint32_t *ks = which == 1 ? k1 : (which == 2 ? k2 : k0);
+        const uint32_t *is = which == 1 ? i1 : (which == 2 ? i2 : i0);
+        hipLaunchKernelGGL((k_gk_gather<WT>), dim3(nbN), dim3(256), 0, s, is, N, d, x,
+                           has_w ? w : (const WT *)nullptr, xs, ws);
+        hipLaunchKernelGGL(k_gk_starts, dim3((unsigned)ceil_div(g.cells + 1, 256)), dim3(256), 0,
+                           s, ks, N, g.cells, cstart);
         MECDF_LAUNCH_CHECK();
     }
     for (int b = 0; b < nh; ++b) {
@@ -296,54 +640,90 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
             hb.ih[a] = 1.0 / h[(size_t)b * d + a];
             prod *= h[(size_t)b * d + a];
         }
-        ProfScope prof("gridkde_bandwidth", s);
-        hipLaunchKernelGGL(k_gk_zero, dim3((unsigned)ceil_div(nbins, 256)), dim3(256), 0, s,
-                           bins, nbins);
-        hipLaunchKernelGGL(k_gk_decays, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, g,
-                           zn, hb, total, dec);
-        switch (d) {
-#define MECDF_GKB(D)                                                                           \
-    hipLaunchKernelGGL((k_gk_bins<D, CH, WT>), dim3(nbN), dim3(256), 0, s, g, zn, x, N, dropped, \
-                       ks, is, w, hb, bins)
-        case 1: MECDF_GKB(1); break;
-        case 2: MECDF_GKB(2); break;
-        case 3: MECDF_GKB(3); break;
-        case 4: MECDF_GKB(4); break;
-        case 5: MECDF_GKB(5); break;
-        default: MECDF_GKB(6); break;
-#undef MECDF_GKB
-        }
-        // every channel along every axis, forward where the channel takes the
-        // upper node on that axis
-        for (int q = 0; q < nch; ++q)
-            for (int a = 0; a < d; ++a) {
-                const int64_t lines = g.nodes / g.M[a];
-                hipLaunchKernelGGL(k_gk_scan, dim3((unsigned)ceil_div(lines * CH, 256)),
-                                   dim3(256), 0, s, g, a, ((q >> a) & 1) ? 0 : 1, dec,
-                                   bins + (int64_t)q * CH * g.nodes, CH);
+        {
+            ProfScope prof("gridkde_bins", s);
+            hipLaunchKernelGGL(k_gk_decays, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
+                               s, g, zn, hb, total, dec);
+            const double *w0 = CH == 1 ? ws : nullptr;
+            const double *w1 = CH == 2 ? ws : nullptr;
+            const int ng = d <= 2 ? 1 : nch / 4;
+            const unsigned nbc = (unsigned)ceil_div(g.cells * ng, 256);
+#define MECDF_GKB(D, NTV)                                                                      \
+    hipLaunchKernelGGL((k_gk_bins<D, CH, NTV>), dim3(nbc), dim3(256), 0, s, g, zn, xs, N,     \
+                       cstart, w0, w1, hb, bufA)
+            if (!matern) {
+                switch (d) {
+                case 1: MECDF_GKB(1, 1); break;
+                case 2: MECDF_GKB(2, 1); break;
+                case 3: MECDF_GKB(3, 1); break;
+                case 4: MECDF_GKB(4, 1); break;
+                case 5: MECDF_GKB(5, 1); break;
+                default: MECDF_GKB(6, 1); break;
+                }
+            } else {
+                switch (d) {
+                case 1: MECDF_GKB(1, 2); break;
+                case 2: MECDF_GKB(2, 3); break;
+                case 3: MECDF_GKB(3, 4); break;
+                default: MECDF_GKB(4, 5); break;
+                }
             }
-        const double norm = 1.0 / ((double)nch * (double)N * prod);
-        hipLaunchKernelGGL((k_gk_combine<CH, OutT>), dim3((unsigned)ceil_div(g.nodes, 256)),
-                           dim3(256), 0, s, g, bins, norm, out + (int64_t)b * g.nodes);
-        MECDF_LAUNCH_CHECK();
+#undef MECDF_GKB
+            MECDF_LAUNCH_CHECK();
+        }
+        {
+            ProfScope prof("gridkde_scan", s);
+            double *in = bufA, *outb = bufB;
+            for (int a = 0; a < d; ++a) {
+                GsArgs ga{};
+                ga.in = in;
+                ga.out = outb;
+                ga.agg = agg;
+                ga.dec = dec + g.off[a];
+                ga.z = zn + g.off[a];
+                ga.ih = hb.ih[a];
+                ga.M = g.M[a];
+                ga.inner = g.nst[a];
+                ga.outer = g.nodes / (g.M[a] * g.nst[a]);
+                ga.nodes = g.nodes;
+                ga.nck = ceil_div(g.M[a], kGkL);
+                ga.nco = nch >> (a + 1);
+                ga.k = a;
+                ga.nt = NT;
+                const int64_t cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
+                if (matern)
+                    gs_launch<CH, true>(ga, cols, s);
+                else
+                    gs_launch<CH, false>(ga, cols, s);
+                MECDF_LAUNCH_CHECK();
+                std::swap(in, outb);
+            }
+            const double norm = 1.0 / ((double)nch * (matern ? (double)(1 + d) : 1.0) *
+                                       (double)N * prod);
+            hipLaunchKernelGGL((k_gk_combine<CH, OutT>), dim3((unsigned)ceil_div(g.nodes, 256)),
+                               dim3(256), 0, s, g, in, matern, norm,
+                               out + (int64_t)b * g.nodes);
+            MECDF_LAUNCH_CHECK();
+        }
     }
     return MECDF_OK;
 }
 
 int gridkde_run(int d, int64_t N, const double *x, const void *w, const int64_t *M,
-                const double *z, int nh, const double *h, void *out, int regression, int prec,
-                hipStream_t s) {
+                const double *z, int nh, const double *h, void *out, int regression,
+                int matern, int prec, hipStream_t s) {
     if (!regression) {
         if (prec == MECDF_F64)
             return gridkde_t<1, double, double>(d, N, x, (const double *)w, M, z, nh, h,
-                                                (double *)out, s);
+                                                (double *)out, matern, s);
         return gridkde_t<1, float, float>(d, N, x, (const float *)w, M, z, nh, h, (float *)out,
-                                          s);
+                                          matern, s);
     }
     if (prec == MECDF_F64)
         return gridkde_t<2, double, double>(d, N, x, (const double *)w, M, z, nh, h,
-                                            (double *)out, s);
-    return gridkde_t<2, float, float>(d, N, x, (const float *)w, M, z, nh, h, (float *)out, s);
+                                            (double *)out, matern, s);
+    return gridkde_t<2, float, float>(d, N, x, (const float *)w, M, z, nh, h, (float *)out,
+                                      matern, s);
 }
 
 }  // namespace mecdf

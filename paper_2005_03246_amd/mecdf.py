@@ -292,6 +292,41 @@ _lib.kde_laplace_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
 _lib.kde_laplace_grid.restype = _I
 _lib.kreg_laplace_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
 _lib.kreg_laplace_grid.restype = _I
+_lib.kde_matern32_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
+_lib.kde_matern32_grid.restype = _I
+_lib.kreg_matern32_grid.argtypes = [_I, _I64, _P, _P, _P, _P, _I, _P, _P, _I, _P]
+_lib.kreg_matern32_grid.restype = _I
+
+
+def _grid_sums(fn, name, x, v, nodes, h, prec, stream):
+    x = _x(x)
+    d, n = x.shape
+    p = _prec(prec)
+    v = _y(v, n, p, x)
+    ms, zs, shape = _grid_args(nodes)
+    hm = _hmat(h, d)
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    out = torch.empty((hm.shape[0],) + shape, dtype=dt, device=x.device)
+    _check(fn(d, n, _ptr(x), _ptr(v), ms, zs, hm.shape[0], hs, _ptr(out), p,
+              _stream_ptr(stream)), name)
+    return out
+
+
+def kde_matern32_grid(x, nodes, h, w=None, prec="f64", stream=None):
+    """KDE with the additive Matern-3/2 kernel at every grid node (C ABI
+    ``kde_matern32_grid``): (nh, M_1, ..., M_d) tensor."""
+    return _grid_sums(_lib.kde_matern32_grid, "kde_matern32_grid", x, w, nodes, h, prec,
+                      stream)
+
+
+def kreg_matern32_grid(x, y, nodes, h, prec="f64", stream=None):
+    """Nadaraya-Watson regression with the additive Matern-3/2 kernel at every
+    grid node (C ABI ``kreg_matern32_grid``): (nh, M_1, ..., M_d) tensor."""
+    if y is None:
+        raise ValueError("kreg_matern32_grid needs the response y")
+    return _grid_sums(_lib.kreg_matern32_grid, "kreg_matern32_grid", x, y, nodes, h, prec,
+                      stream)
 
 
 def kde_laplace_grid(x, nodes, h, w=None, prec="f64", stream=None):

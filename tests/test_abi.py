@@ -108,3 +108,25 @@ def test_host_validation_errors(lib):
     lib.mecdf_strerror.restype = ctypes.c_char_p
     assert lib.mecdf_strerror(-1) == b"invalid argument"
     assert lib.mecdf_strerror(-5) == b"file input/output error"
+
+
+def test_grid_kernel_sum_validation(lib):
+    fake = ctypes.c_void_p(0x1000)
+    M = (ctypes.c_int64 * 5)(3, 3, 3, 3, 3)
+    z = (ctypes.c_double * 15)(*([0.0, 1.0, 2.0] * 5))
+    h = (ctypes.c_double * 5)(0.1, 0.1, 0.1, 0.1, 0.1)
+    hneg = (ctypes.c_double * 5)(0.1, -0.1, 0.1, 0.1, 0.1)
+    for name in ("kde_laplace_grid", "kde_matern32_grid", "kreg_laplace_grid",
+                 "kreg_matern32_grid"):
+        f = _c(lib, name, [I, I64, P, P, P, P, I, P, P, I, P])
+        reg = name.startswith("kreg")
+        w = fake if reg else None
+        assert f(2, 0, fake, w, M, z, 1, h, fake, 0, None) == -1       # N < 1
+        assert f(2, 10, fake, w, M, z, 0, h, fake, 0, None) == -1      # nh < 1
+        assert f(2, 10, fake, w, M, z, 1, hneg, fake, 0, None) == -1   # h <= 0
+        assert f(2, 10, fake, w, M, z, 1, h, None, 0, None) == -1      # no output
+        if reg:
+            assert f(2, 10, fake, None, M, z, 1, h, fake, 0, None) == -1  # y NULL
+    # the Matern channel arrays stop at d = 4
+    mk = _c(lib, "kde_matern32_grid", [I, I64, P, P, P, P, I, P, P, I, P])
+    assert mk(5, 10, fake, None, M, z, 1, h, fake, 0, None) == -4

@@ -1,7 +1,7 @@
 """Laplacian kernel sums at grid nodes (kde_laplace_grid / kreg_laplace_grid,
 the paper's fast-summation KDE) against the brute-force oracle at every node:
-densities within 1e-12 (float64) / 1e-5 (float32) of the |w|-weighted scale,
-NW ratios within 1e-12 / 1e-5 of max |y|."""
+densities within 1e-12 (float64) / 1e-5 (float32, plus the smallest normal
+float32) of the |w|-weighted scale, NW ratios within 1e-12 of max |y|."""
 import numpy as np
 import pytest
 import torch
@@ -63,7 +63,8 @@ def test_grid_kde_and_nw_random(lib, case):
     f32 = lib.kde_laplace_grid(dev(x), nodes, hs, dev(w.astype(np.float32), torch.float32),
                                prec="f32c").cpu().numpy().reshape(len(hs), -1)
     w32, s32 = oracle.kde_laplace(x, zq, hs, w.astype(np.float32).astype(np.float64))
-    assert np.max(np.abs(f32[nz] - w32[nz]) / s32[nz]) <= 1e-5
+    # float32 holds no values below its smallest normal number
+    assert np.all(np.abs(f32[nz] - w32[nz]) <= 1e-5 * s32[nz] + np.finfo(np.float32).tiny)
 
 
 def test_grid_kde_paper_accuracy_claim(lib):
@@ -93,3 +94,63 @@ def test_grid_kde_interpolated_to_the_points(lib):
         f = lib.kde_laplace_grid(xt, nodes, [0.3])[0]
         errs.append(np.max(np.abs(lib.grid_interp(f, nodes, xt).cpu().numpy() - exact)))
     assert errs[2] < errs[1] < errs[0]
+
+
+MATERN_CASES = [(1, 1, [5]), (1, 800, [37]), (2, 2, [3, 4]), (2, 1500, [17, 40]),
+                (2, 2500, [100, 3]), (3, 1000, [9, 18, 11]), (4, 500, [5, 4, 6, 3])]
+
+
+@pytest.mark.parametrize("case", MATERN_CASES)
+def test_grid_matern32_random(lib, case):
+    """The additive Matern-3/2 kernel (Appendix C) at every node: KDE and NW
+    against the oracle's direct sums, float64 and float32."""
+    d, n, m = case
+    g = np.random.default_rng(900 + 13 * d + n)
+    x = np.round(g.normal(size=(d, n)), 2)
+    w = g.uniform(0.2, 2.0, n)
+    y = np.cos(x[0]) + 0.1 * g.normal(size=n)
+    nodes = []
+    for k in range(d):
+        z = np.sort(g.uniform(-3.0, 3.0, m[k]))
+        if m[k] > 2:
+            z[m[k] // 2] = x[k, 0]
+            z = np.unique(z)
+        nodes.append(z)
+    hs = hmat([0.05, 0.3, 1.5], d)
+    hs[1] = g.uniform(0.1, 0.6, d)
+    zq = oracle.grid_points(nodes)
+    f = lib.kde_matern32_grid(dev(x), nodes, hs, dev(w)).cpu().numpy().reshape(len(hs), -1)
+    want, scale = oracle.kde_matern32(x, zq, hs, w)
+    nz = scale > 0
+    assert np.all(f[~nz] == 0)
+    assert np.max(np.abs(f[nz] - want[nz]) / scale[nz]) <= 1e-12
+    mm = lib.kreg_matern32_grid(dev(x), dev(y), nodes, hs).cpu().numpy().reshape(len(hs), -1)
+    wm = oracle.nw_matern32(x, y, zq, hs)
+    ok = np.isfinite(wm)
+    assert np.array_equal(np.isfinite(mm), ok)
+    assert np.max(np.abs(mm[ok] - wm[ok])) <= 1e-12 * np.max(np.abs(y))
+    f32 = lib.kde_matern32_grid(dev(x), nodes, hs, dev(w.astype(np.float32), torch.float32),
+                                prec="f32c").cpu().numpy().reshape(len(hs), -1)
+    w32, s32 = oracle.kde_matern32(x, zq, hs, w.astype(np.float32).astype(np.float64))
+    # float32 holds no values below its smallest normal number
+    assert np.all(np.abs(f32[nz] - w32[nz]) <= 1e-5 * s32[nz] + np.finfo(np.float32).tiny)
+
+
+def test_grid_sums_do_not_depend_on_the_previous_call(lib):
+    """Every bin of every corner array is written by its cell's thread (no
+    clearing pass): a dense call followed by a sparse one on the same grid
+    gives the sparse call's own values."""
+    g = np.random.default_rng(77)
+    nodes = [np.linspace(-2, 2, 50), np.linspace(-2, 2, 33)]
+    zq = oracle.grid_points(nodes)
+    big = g.normal(size=(2, 20000))
+    lib.kde_laplace_grid(dev(big), nodes, [0.2])
+    lib.kde_matern32_grid(dev(big), nodes, [0.2])
+    small = g.uniform(-0.5, 0.5, size=(2, 3))
+    for fn, ref in ((lib.kde_laplace_grid, oracle.kde_laplace),
+                    (lib.kde_matern32_grid, oracle.kde_matern32)):
+        f = fn(dev(small), nodes, [0.2]).cpu().numpy().reshape(-1)
+        want, scale = ref(small, zq, [0.2])
+        nz = scale[0] > 0
+        assert np.all(f[~nz] == 0)
+        assert np.max(np.abs(f[nz] - want[0][nz]) / scale[0][nz]) <= 1e-12

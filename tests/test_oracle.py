@@ -395,3 +395,135 @@ def test_local_linear_large_bandwidth_is_least_squares():
     X = np.vstack([np.ones(50), x]).T
     coef = np.linalg.lstsq(X, y, rcond=None)[0]
     np.testing.assert_allclose(got, coef[0] + coef[1:] @ z, rtol=1e-6, atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# eq. (ECDFdelta) at arbitrary points, the uniform kernel (Section 3.2) and
+# the additive Matern-3/2 kernel (Appendix C)
+# --------------------------------------------------------------------------
+def test_ecdf_delta_hand_ties():
+    """x = 0, 1, 2 on one axis, z = 1: <= counts 2 points, < counts 1."""
+    x = np.array([[0.0, 1.0, 2.0]])
+    z = np.array([[1.0, 1.0, -1.0, 2.5]])
+    got = oracle.ecdf_delta(x, z, np.array([0, 1, 1, 1], np.uint8))
+    assert got.tolist() == [2, 1, 0, 3]
+
+
+def test_ecdf_delta_strict_is_half_step_below_on_integer_data():
+    """For integer-valued data, x < z equals x <= z - 1/2 on that axis, so each
+    strict axis of eq. (ECDFdelta) moves the query half a step down."""
+    g = np.random.default_rng(71)
+    for d in (1, 2, 3):
+        x = g.integers(-3, 4, size=(d, 400)).astype(float)
+        z = g.integers(-3, 4, size=(d, 60)).astype(float)
+        y = g.uniform(-1.0, 2.0, 400)
+        delta = g.integers(0, 1 << d, size=60).astype(np.uint8)
+        zs = z.copy()
+        for k in range(d):
+            zs[k] -= 0.5 * ((delta >> k) & 1)
+        assert np.array_equal(oracle.ecdf_delta(x, z, delta), oracle.ecdf(x, zs))
+        s, _ = oracle.ecdf_delta(x, z, delta, y)
+        w, _ = oracle.dominance_sums(x, zs, y)
+        assert np.array_equal(s, w)
+
+
+def test_ecdf_delta_all_strict_on_reflected_data_is_the_esf():
+    """1{-x < -z} on every axis is 1{x > z}: eq. (ECDFdelta) with delta = -1
+    everywhere on the reflected sample is eq. (ESF)."""
+    g = np.random.default_rng(72)
+    x = np.round(g.normal(size=(3, 500)), 1)
+    z = np.round(g.normal(size=(3, 80)), 1)
+    got = oracle.ecdf_delta(-x, -z, np.full(80, 7, np.uint8))
+    assert np.array_equal(got, oracle.esf(x, z))
+
+
+def test_uniform_box_hand_and_closed_ends():
+    """d = 1, x = 0, .25, .5, .75, 1, z = .5, h = .25: the closed box [.25, .75]
+    holds three points (dyadic values, so the ends are exact)."""
+    x = np.array([[0.0, 0.25, 0.5, 0.75, 1.0]])
+    s, _ = oracle.kernel_sums("uniform", x, np.array([[0.5]]), [0.25])
+    assert s[0, 0, 0] == 3.0
+    f, _ = oracle.kde_uniform(x, np.array([[0.5]]), [0.25])
+    assert f[0, 0] == pytest.approx(3.0 / (2 * 5 * 0.25), rel=1e-15)
+
+
+def test_uniform_is_the_signed_sum_of_shifted_ecdfs():
+    """eq. (uniform_decomposition_nD): the box count at z equals
+    sum_delta (prod_k delta_k) F_N(z + delta h, delta), with the corner
+    coordinates z + delta h rounded to doubles, bit for bit on counts."""
+    g = np.random.default_rng(73)
+    for d in (1, 2, 3):
+        x = np.round(g.normal(size=(d, 600)), 1)
+        z = np.round(g.normal(size=(d, 40)), 1)
+        h = np.round(g.uniform(0.1, 0.8, d), 1)
+        want = np.zeros(40, dtype=np.int64)
+        for dl in range(1 << d):
+            sign = (-1) ** bin(dl).count("1")
+            zc = np.stack([z[k] - h[k] if (dl >> k) & 1 else z[k] + h[k] for k in range(d)])
+            want += sign * oracle.ecdf_delta(x, zc, np.full(40, dl, np.uint8))
+        s, _ = oracle.kernel_sums("uniform", x, z, h[None, :])
+        assert np.array_equal(s[0, 0], want.astype(float))
+
+
+def _matern_general(u, p):
+    """eq. (Matern_kernel) with eq. (Matern_constant), h = 1."""
+    from math import comb, factorial
+
+    norm = sum(factorial(p) // factorial(p - k) * factorial(2 * p - k) / factorial(2 * p)
+               * 2 ** k for k in range(p + 1))
+    gam = math.sqrt(2 * p + 1) / (2 * norm)
+    poly = sum(comb(p, k) * factorial(2 * p - k) / factorial(2 * p)
+               * (2 * math.sqrt(2 * p + 1)) ** k * np.abs(u) ** k for k in range(p + 1))
+    return gam * poly * np.exp(-math.sqrt(2 * p + 1) * np.abs(u))
+
+
+def test_matern32_d1_is_the_papers_univariate_kernel():
+    """In d = 1 the additive kernel is eq. (Matern32) (the p = 1 member of eq.
+    (Matern_kernel)) with its bandwidth sqrt(3) h."""
+    g = np.random.default_rng(74)
+    x = g.normal(size=(1, 300))
+    z = np.linspace(-3, 3, 41)[None, :]
+    h = 0.4
+    f, _ = oracle.kde_matern32(x, z, [h])
+    H = math.sqrt(3.0) * h
+    u = (x[0][None, :] - z[0][:, None]) / H
+    want = _matern_general(u, 1).mean(axis=1) / H
+    assert np.max(np.abs(f[0] - want)) <= 1e-14 * np.max(want)
+
+
+def test_matern32_integrates_to_one():
+    """eq. (Matern32_average) is a density: for one point in d = 2 the
+    estimate integrates to 1 (trapezoid rule on a fine, wide grid)."""
+    t = np.linspace(-30, 30, 1201)
+    zz = np.stack(np.meshgrid(t, t, indexing="ij")).reshape(2, -1)
+    f, _ = oracle.kde_matern32(np.zeros((2, 1)), zz, [[1.0, 2.0]])
+    tot = np.trapezoid(np.trapezoid(f[0].reshape(1201, 1201), t, axis=1), t)
+    assert abs(tot - 1.0) < 1e-3
+
+
+def test_matern32_is_the_papers_decomposition():
+    """eq. (Matern32_decomposition_nD): the additive kernel sum at z equals
+    sum_delta e^{-sum_k delta_k z_k/h_k} ((1 + sum_l delta_l z_l/h_l)
+    F(delta z, delta; delta x, y0) - sum_l (delta_l/h_l) F(delta z, delta;
+    delta x, y_l)) with y0 = w e^{sum_k delta_k x_k/h_k} and y_l = x_l y0
+    (F without its 1/N; small coordinates, so the exponential weights stay
+    in range)."""
+    g = np.random.default_rng(75)
+    for d in (1, 2, 3):
+        x = g.uniform(-1.0, 1.0, size=(d, 300))
+        z = g.uniform(-1.0, 1.0, size=(d, 25))
+        w = g.uniform(0.5, 2.0, 300)
+        h = g.uniform(0.4, 0.9, d)
+        want = np.zeros(25)
+        for dl in range(1 << d):
+            sg = np.array([-1.0 if (dl >> k) & 1 else 1.0 for k in range(d)])
+            y0 = w * np.exp((sg[:, None] * x / h[:, None]).sum(0))
+            mask = np.full(25, dl, np.uint8)
+            f0, _ = oracle.ecdf_delta(sg[:, None] * x, sg[:, None] * z, mask, y0)
+            acc = (1.0 + (sg[:, None] * z / h[:, None]).sum(0)) * f0
+            for l in range(d):
+                fl, _ = oracle.ecdf_delta(sg[:, None] * x, sg[:, None] * z, mask, x[l] * y0)
+                acc -= sg[l] / h[l] * fl
+            want += np.exp(-(sg[:, None] * z / h[:, None]).sum(0)) * acc
+        s, _ = oracle.kernel_sums("matern32", x, z, h[None, :], w)
+        assert np.max(np.abs(s[0, 0] - want)) <= 1e-12 * np.max(np.abs(want))
