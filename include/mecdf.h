@@ -191,6 +191,56 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
                int prec, void *stream);
 
 /*
+ * ecdf_delta_at -- the generalized ECDF of eq. (ECDFdelta) (Section 1) at Q
+ * arbitrary points, each with its own inequality pattern:
+ *
+ *   F[q] = (1/N) sum_i y_i prod_k 1{x_{k,i} <=_{delta_{k,q}} z_{k,q}}
+ *
+ * where <=_{+1} is <= and <=_{-1} is the strict <.  The points recursion of
+ * Section 2.2 runs over the N data items and Q query items; a query's rank on
+ * each axis is found among the distinct data values, so ties with data
+ * values and the strict / non-strict choice are exact.
+ *
+ *   x      device d*N doubles (N >= 1);  y  device N weights or NULL (counts)
+ *   Q, z   Q >= 0 query points, device d*Q doubles, z[k*Q + q]
+ *   delta  device Q bytes, bit k set for delta_k = -1 (strict), clear for
+ *          <=; or NULL for <= everywhere (then F[q] = F_N(z_q) of eq. (ECDF))
+ *   F      device Q results: int64 counts (y == NULL) or double / float F_N
+ *
+ * A query with a NaN coordinate counts nothing (F = 0), as does a data point
+ * with one for every query.  Limits: N <= 2^26 and Q <= 2^26
+ * (MECDF_EUNSUPPORTED above).  Deterministic; does not wait for the device.
+ */
+int ecdf_delta_at(int d, int64_t N, const double *x, const void *y, int64_t Q,
+                  const double *z, const uint8_t *delta, void *F, int prec,
+                  void *stream);
+
+/*
+ * kde_uniform -- the weighted uniform-kernel density estimate of eq.
+ * (uniform_kde_nD) (Section 3.2) at Q arbitrary points (pass z = x for the
+ * sample points), for nh bandwidth vectors:
+ *
+ *   f[b*Q + q] = 1/(2^d N prod_k h_{b,k}) sum_i w_i prod_k 1{lo_k <= x_{k,i} <= hi_k}
+ *
+ * with lo_k = z_{k,q} - h_{b,k} and hi_k = z_{k,q} + h_{b,k}, each rounded to
+ * a double, computed as eq. (uniform_decomposition_nD): the signed sum of
+ * ecdf_delta_at at the 2^d box corners, all corners of a bandwidth in one
+ * recursion.  With w == NULL the box counts are exact integers before the
+ * final scaling; weighted sums are float64 differences of F_N values (their
+ * error is relative to the total |w| mass, not to the box's).
+ *
+ *   x, N       as ecdf_delta_at;  w  device N weights or NULL (all 1)
+ *   Q, z       device query points as ecdf_delta_at
+ *   nh, h      host nh*d positive bandwidths, h[b*d + k]
+ *   f          device nh*Q results (double, or float with MECDF_F32C)
+ *
+ * Limits: Q 2^d <= 2^26.  Deterministic; does not wait for the device.
+ */
+int kde_uniform(int d, int64_t N, const double *x, const void *w, int64_t Q,
+                const double *z, int nh, const double *h, void *f, int prec,
+                void *stream);
+
+/*
  * kde_laplace -- weighted Laplacian-kernel density estimate at the sample
  * points for nh bandwidth vectors (eq. (Laplacian_kde_nD), Section 3.1),
  * evaluated through the 2^d sign-orthant ECDF decomposition of

@@ -14,6 +14,11 @@ namespace mecdf {
 int grid_run(int d, int64_t N, const double *x, const void *y,
              const int64_t *M, const double *z, void *F, void *Fbar, int prec,
              hipStream_t s);
+int points_delta_run(int d, int64_t N, const double *x, const void *y, int64_t Q,
+                     const double *z, const uint8_t *delta, void *F, int prec, hipStream_t s);
+int kde_uniform_run(int d, int64_t N, const double *x, const void *w, int64_t Q,
+                    const double *z, int nh, const double *h, void *f, int prec,
+                    hipStream_t s);
 int points_run(int d, int64_t N, const double *x, const void *y, void *F,
                int survival, int prec, hipStream_t s);
 int kde_run(int d, int64_t N, const double *x, const void *w, int nh,
@@ -209,6 +214,43 @@ int esf_points(int d, int64_t N, const double *x, const void *y, void *F,
     if (N == 0)
         return MECDF_OK;
     return points_run(d, N, x, y, F, 1, prec, (hipStream_t)stream);
+}
+
+int ecdf_delta_at(int d, int64_t N, const double *x, const void *y, int64_t Q,
+                  const double *z, const uint8_t *delta, void *F, int prec, void *stream) {
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (N < 1)
+        return fail(MECDF_EINVAL, "queries at arbitrary points need N >= 1");
+    if (Q < 0)
+        return fail(MECDF_EINVAL, "Q must be >= 0");
+    if (Q == 0)
+        return MECDF_OK;
+    if (z == nullptr || F == nullptr)
+        return fail(MECDF_EINVAL, "z and F are required");
+    return points_delta_run(d, N, x, y, Q, z, delta, F, prec, (hipStream_t)stream);
+}
+
+int kde_uniform(int d, int64_t N, const double *x, const void *w, int64_t Q,
+                const double *z, int nh, const double *h, void *f, int prec, void *stream) {
+    MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
+    if (N < 1)
+        return fail(MECDF_EINVAL, "the uniform kernel sums need N >= 1");
+    if (Q < 0)
+        return fail(MECDF_EINVAL, "Q must be >= 0");
+    if (nh < 1 || nh > 256)
+        return fail(MECDF_EINVAL, "nh must be in 1..256");
+    if (h == nullptr)
+        return fail(MECDF_EINVAL, "h is NULL");
+    for (int i = 0; i < nh * d; ++i)
+        if (!(h[i] > 0.0) || !std::isfinite(h[i]))
+            return fail(MECDF_EINVAL, "bandwidths must be positive and finite");
+    if (Q == 0)
+        return MECDF_OK;
+    if (z == nullptr || f == nullptr)
+        return fail(MECDF_EINVAL, "z and f are required");
+    if (Q > ((int64_t(1) << 26) >> d))
+        return fail(MECDF_EUNSUPPORTED, "the uniform kernel sums take Q <= 2^26 / 2^d");
+    return kde_uniform_run(d, N, x, w, Q, z, nh, h, f, prec, (hipStream_t)stream);
 }
 
 static int kde_check(int d, int64_t N, const double *x, int nh,

@@ -162,6 +162,105 @@ __global__ __launch_bounds__(256) void k_make_items(
     }
 }
 
+// ---- queries at arbitrary points (eq. (ECDFdelta)) -----------------------
+// The distinct values of axis k in increasing key order: uv[r] = the key of
+// dense rank r.
+__global__ __launch_bounds__(256) void k_rank_values(const uint32_t *__restrict__ flags,
+                                                     const uint32_t *__restrict__ excl,
+                                                     const uint64_t *__restrict__ keys,
+                                                     int64_t n, uint64_t *__restrict__ uv) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n)
+        return;
+    if (p == 0 || flags[p])
+        uv[excl[p] + flags[p]] = keys[p];
+}
+
+// The rank a query takes on axis k: data of rank a count for it exactly when
+// a <= b, so b = (number of distinct data values <= z, or < z on an axis
+// where the query's delta bit asks for the strict inequality) - 1.  A query
+// below every data value on some axis (b < 0) or with a NaN coordinate
+// counts nothing: it is inert and its result is 0.
+__global__ __launch_bounds__(256) void k_query_ranks(const double *__restrict__ z, int64_t Q,
+                                                     int d, const uint8_t *__restrict__ delta,
+                                                     const uint64_t *__restrict__ uv, int64_t N,
+                                                     const uint32_t *__restrict__ U,
+                                                     uint32_t *__restrict__ qrank,
+                                                     uint8_t *__restrict__ qinert) {
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= Q)
+        return;
+    bool inert = false;
+    const uint32_t dl = delta ? delta[q] : 0u;
+    for (int k = 0; k < d; ++k) {
+        const double v = z[(int64_t)k * Q + q];
+        int64_t lo = 0;
+        if (v != v) {
+            inert = true;
+        } else {
+            const uint64_t key = order_key(v);
+            const bool strict = ((dl >> k) & 1u) != 0u;
+            const uint64_t *u = uv + (int64_t)k * N;
+            int64_t hi = U[k];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (strict ? u[mid] < key : u[mid] <= key)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo == 0)
+                inert = true;
+        }
+        qrank[(int64_t)k * Q + q] = lo > 0 ? (uint32_t)(lo - 1) : 0u;
+    }
+    qinert[q] = inert ? 1 : 0;
+}
+
+// Items of the data (slots 0..N-1) and of the queries (slots N..N+Q-1).  A
+// data point with a NaN coordinate and an inert query get the largest top
+// key, so they sort after every other item (the data before the queries) and
+// no live query counts them.  Data items never write a result, so their id
+// field is left 0.
+template <int NC, typename YT>
+__global__ __launch_bounds__(256) void k_make_items_ext(
+    const uint32_t *__restrict__ rank /*[d][N]*/, const uint32_t *__restrict__ drop,
+    const YT *__restrict__ y, int64_t N, const uint32_t *__restrict__ qrank /*[d][Q]*/,
+    const uint8_t *__restrict__ qinert, int64_t Q, int d, uint64_t invalid_key,
+    uint64_t *__restrict__ topkey, uint32_t *__restrict__ slot, Item<NC> *__restrict__ items,
+    double *__restrict__ W) {
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= N + Q)
+        return;
+    Item<NC> it;
+    const bool data = t < N;
+    const int64_t i = data ? t : t - N;
+    const uint32_t *r = data ? rank : qrank;
+    const int64_t n = data ? N : Q;
+    for (int k = 1; k < d && k - 1 < NC; ++k)
+        it.c[k - 1] = r[(int64_t)k * n + i];
+    for (int k = d - 1; k < NC; ++k)
+        it.c[k] = 0u;
+    bool ok;
+    if (data) {
+        ok = drop[i] == 0u;
+        it.idt = 0u;
+    } else {
+        ok = qinert[i] == 0;
+        it.idt = ((uint32_t)i << kIdShift) | 1u;
+    }
+    topkey[t] = ok ? (((uint64_t)r[i] << 1) | (data ? 0ull : 1ull)) : invalid_key;
+    slot[t] = (uint32_t)t;
+    items[t] = it;
+    if (W) {
+        double w = 1.0;
+        if constexpr (!std::is_same<YT, NoPayload>::value)
+            if (data)
+                w = (double)y[i];
+        W[t] = (data && ok) ? w : 0.0;
+    }
+}
+
 template <int NC>
 __global__ __launch_bounds__(256) void k_gather_items(const uint32_t *__restrict__ perm,
                                                       int64_t n,
@@ -911,6 +1010,23 @@ __global__ __launch_bounds__(256) void k_points_out(const AccT *__restrict__ acc
         F[i] = scale ? (OutT)(acc[i] / (double)N) : (OutT)acc[i];
 }
 
+// The result of query q (0 for an inert query).
+template <typename OutT, typename AccT>
+__global__ __launch_bounds__(256) void k_query_out(const AccT *__restrict__ acc, int64_t Q,
+                                                   int64_t N, int scale,
+                                                   const uint8_t *__restrict__ qinert,
+                                                   OutT *__restrict__ F) {
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= Q)
+        return;
+    if (qinert[q])
+        F[q] = (OutT)0;
+    else if constexpr (std::is_same<AccT, int64_t>::value)
+        F[q] = (OutT)acc[q];
+    else
+        F[q] = scale ? (OutT)(acc[q] / (double)N) : (OutT)acc[q];
+}
+
 __global__ void k_zero_u32(uint32_t *a, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n)
@@ -1037,11 +1153,20 @@ template <int NC, bool kW> struct Dnc {
     }
 };
 
+// Queries at Q arbitrary points (eq. (ECDFdelta)) instead of at the sample
+// points: coordinates z[k*Q + q] and per-query delta bit masks (device).
+struct ExtQueries {
+    int64_t Q;
+    const double *z;
+    const uint8_t *delta;  // NULL: <= on every axis
+};
+
 template <int NC, bool kW, typename YT, typename OutT>
 static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
-                        int survival, hipStream_t s) {
+                        int survival, const ExtQueries *ext, hipStream_t s) {
     using AccT = AccOf<kW>;
-    const int64_t n2 = 2 * N;
+    const int64_t nq = ext ? ext->Q : N;    // result slots
+    const int64_t n2 = ext ? N + nq : 2 * N;
     const int depths = d > 1 ? d - 1 : 1;
     ArenaPlan pl;
     pl.add<uint64_t>((size_t)N);           // keys
@@ -1055,6 +1180,11 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     pl.add<uint32_t>((size_t)N * d);       // ranks
     pl.add<uint32_t>((size_t)N);           // drop
     pl.add<uint32_t>(8);                   // U
+    if (ext) {
+        pl.add<uint64_t>((size_t)N * d);   // distinct values per axis
+        pl.add<uint32_t>((size_t)nq * d);  // query ranks
+        pl.add<uint8_t>((size_t)nq);       // inert queries
+    }
     pl.add<uint64_t>((size_t)n2);          // topkey x3
     pl.add<uint64_t>((size_t)n2);
     pl.add<uint64_t>((size_t)n2);
@@ -1077,7 +1207,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
             pl.add<double>((size_t)n2);
         }
     }
-    pl.add<AccT>((size_t)N);               // acc
+    pl.add<AccT>((size_t)nq);              // acc
     pl.add<AccT>((size_t)n2);              // P
     pl.add<PCnt<kW>>((size_t)n2);          // p and c at the last depth, x2
     pl.add<PCnt<kW>>((size_t)n2);
@@ -1097,6 +1227,9 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     uint32_t *rank = a.take<uint32_t>((size_t)N * d);
     uint32_t *drop = a.take<uint32_t>((size_t)N);
     uint32_t *U = a.take<uint32_t>(8);
+    uint64_t *uv = ext ? a.take<uint64_t>((size_t)N * d) : nullptr;
+    uint32_t *qrank = ext ? a.take<uint32_t>((size_t)nq * d) : nullptr;
+    uint8_t *qinert = ext ? a.take<uint8_t>((size_t)nq) : nullptr;
     uint64_t *tk0 = a.take<uint64_t>((size_t)n2), *tk1 = a.take<uint64_t>((size_t)n2),
              *tk2 = a.take<uint64_t>((size_t)n2);
     uint32_t *sl0 = a.take<uint32_t>((size_t)n2), *sl1 = a.take<uint32_t>((size_t)n2),
@@ -1118,7 +1251,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
         dnc.SW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
         dnc.TW[q + 1] = kW ? a.take<double>((size_t)n2) : nullptr;
     }
-    dnc.acc = a.take<AccT>((size_t)N);
+    dnc.acc = a.take<AccT>((size_t)nq);
     dnc.P = a.take<AccT>((size_t)n2);
     dnc.PCa = a.take<PCnt<kW>>((size_t)n2);
     dnc.PCb = a.take<PCnt<kW>>((size_t)n2);
@@ -1141,14 +1274,25 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
             MECDF_TRY(scan_exclusive_u32(flags, excl, N, rs.bsum, s));
             hipLaunchKernelGGL(k_rank_scatter, dim3(nbN), dim3(256), 0, s, flags, excl, is, N,
                                rank + (size_t)k * N, U + k);
+            if (ext)
+                hipLaunchKernelGGL(k_rank_values, dim3(nbN), dim3(256), 0, s, flags, excl, ks,
+                                   N, uv + (size_t)k * N);
         }
+        if (ext && nq > 0)
+            hipLaunchKernelGGL(k_query_ranks, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
+                               ext->z, nq, d, ext->delta, uv, N, U, qrank, qinert);
         MECDF_LAUNCH_CHECK();
     }
     // ---- items, sorted by (coordinate 0, type)
     const int kb = bits_for((uint64_t)N) + 1;
     const uint64_t invalid_key = (kb >= 63) ? ~0ull : ((1ull << (kb + 1)) - 1ull);
-    hipLaunchKernelGGL((k_make_items<NC, YT>), dim3(nbN), dim3(256), 0, s, rank, U, drop, y,
-                       N, d, survival, invalid_key, tk0, sl0, items, Wslot);
+    if (ext)
+        hipLaunchKernelGGL((k_make_items_ext<NC, YT>), dim3((unsigned)ceil_div(n2, 256)),
+                           dim3(256), 0, s, rank, drop, y, N, qrank, qinert, nq, d, invalid_key,
+                           tk0, sl0, items, Wslot);
+    else
+        hipLaunchKernelGGL((k_make_items<NC, YT>), dim3(nbN), dim3(256), 0, s, rank, U, drop, y,
+                           N, d, survival, invalid_key, tk0, sl0, items, Wslot);
     MECDF_LAUNCH_CHECK();
     int which = 0;
     {
@@ -1161,10 +1305,10 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     dnc.n = n;
     hipLaunchKernelGGL((k_gather_items<NC>), dim3((unsigned)ceil_div(n > 0 ? n : 1, 256)),
                        dim3(256), 0, s, perm, n, items, Wslot, dnc.S[1], dnc.SW[1]);
-    if constexpr (kW)
-        hipLaunchKernelGGL(k_zero_f64, dim3(nbN), dim3(256), 0, s, (double *)dnc.acc, N);
-    else
-        hipLaunchKernelGGL(k_zero_f64, dim3(nbN), dim3(256), 0, s, (double *)dnc.acc, N);
+    // int64 and double zeros share their bits
+    if (nq > 0)
+        hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
+                           (double *)dnc.acc, nq);
     MECDF_LAUNCH_CHECK();
 
     if (n > 0) {
@@ -1182,8 +1326,14 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
             MECDF_TRY(dnc.solve(1, H));
         }
     }
-    hipLaunchKernelGGL((k_points_out<OutT, AccT>), dim3(nbN), dim3(256), 0, s, dnc.acc, N,
-                       kW ? 1 : 0, drop, rank, U, d, survival, F);
+    if (ext) {
+        if (nq > 0)
+            hipLaunchKernelGGL((k_query_out<OutT, AccT>), dim3((unsigned)ceil_div(nq, 256)),
+                               dim3(256), 0, s, dnc.acc, nq, N, kW ? 1 : 0, qinert, F);
+    } else {
+        hipLaunchKernelGGL((k_points_out<OutT, AccT>), dim3(nbN), dim3(256), 0, s, dnc.acc, N,
+                           kW ? 1 : 0, drop, rank, U, d, survival, F);
+    }
     MECDF_LAUNCH_CHECK();
     return MECDF_OK;
 }
@@ -1345,15 +1495,32 @@ static int64_t points_direct_max() {
 
 template <int NC>
 static int points_dispatch(int d, int64_t N, const double *x, const void *y, void *F,
-                           int survival, int prec, hipStream_t s) {
+                           int survival, int prec, const ExtQueries *ext, hipStream_t s) {
     if (y == nullptr)
         return points_run_t<NC, false, NoPayload, int64_t>(d, N, x, nullptr, (int64_t *)F,
-                                                           survival, s);
+                                                           survival, ext, s);
     if (prec == MECDF_F64)
         return points_run_t<NC, true, double, double>(d, N, x, (const double *)y,
-                                                      (double *)F, survival, s);
+                                                      (double *)F, survival, ext, s);
     return points_run_t<NC, true, float, float>(d, N, x, (const float *)y, (float *)F,
-                                                survival, s);
+                                                survival, ext, s);
+}
+
+static int points_dispatch_d(int d, int64_t N, const double *x, const void *y, void *F,
+                             int survival, int prec, const ExtQueries *ext, hipStream_t s) {
+    switch (d) {
+    case 1:
+    case 2:
+        return points_dispatch<1>(d, N, x, y, F, survival, prec, ext, s);
+    case 3:
+        return points_dispatch<2>(d, N, x, y, F, survival, prec, ext, s);
+    case 4:
+        return points_dispatch<3>(d, N, x, y, F, survival, prec, ext, s);
+    case 5:
+        return points_dispatch<4>(d, N, x, y, F, survival, prec, ext, s);
+    default:
+        return points_dispatch<5>(d, N, x, y, F, survival, prec, ext, s);
+    }
 }
 
 int points_run(int d, int64_t N, const double *x, const void *y, void *F,
@@ -1372,19 +1539,17 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
         default: return points_direct_d<6>(N, x, y, F, survival, prec, s);
         }
     }
-    switch (d) {
-    case 1:
-    case 2:
-        return points_dispatch<1>(d, N, x, y, F, survival, prec, s);
-    case 3:
-        return points_dispatch<2>(d, N, x, y, F, survival, prec, s);
-    case 4:
-        return points_dispatch<3>(d, N, x, y, F, survival, prec, s);
-    case 5:
-        return points_dispatch<4>(d, N, x, y, F, survival, prec, s);
-    default:
-        return points_dispatch<5>(d, N, x, y, F, survival, prec, s);
+    return points_dispatch_d(d, N, x, y, F, survival, prec, nullptr, s);
+}
+
+int points_delta_run(int d, int64_t N, const double *x, const void *y, int64_t Q,
+                     const double *z, const uint8_t *delta, void *F, int prec, hipStream_t s) {
+    if (N > (int64_t(1) << 26) || Q > (int64_t(1) << 26)) {
+        set_error("queries at arbitrary points support N <= 2^26 and Q <= 2^26");
+        return MECDF_EUNSUPPORTED;
     }
+    const ExtQueries ext{Q, z, delta};
+    return points_dispatch_d(d, N, x, y, F, 0, prec, &ext, s);
 }
 
 }  // namespace mecdf

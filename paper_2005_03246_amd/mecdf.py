@@ -235,6 +235,52 @@ def esf_points(x, y=None, prec="f64", stream=None):
     return F
 
 
+_lib.ecdf_delta_at.argtypes = [_I, _I64, _P, _P, _I64, _P, _P, _P, _I, _P]
+_lib.ecdf_delta_at.restype = _I
+_lib.kde_uniform.argtypes = [_I, _I64, _P, _P, _I64, _P, _I, _P, _P, _I, _P]
+_lib.kde_uniform.restype = _I
+
+
+def ecdf_delta_at(x, z, delta=None, y=None, prec="f64", stream=None):
+    """F_N(z_q, delta_q) of eq. (ECDFdelta) at the points z (d, Q) (C ABI
+    ``ecdf_delta_at``); delta: (Q,) uint8 masks on the device (bit k set:
+    strict on axis k) or None.  int64 counts when y is None."""
+    x = _x(x)
+    d, n = x.shape
+    z = _x(z)
+    if z.shape[0] != d:
+        raise ValueError("z must have the dimension of x")
+    q = z.shape[1]
+    p = _prec(prec)
+    y = _y(y, n, p, x)
+    if delta is not None:
+        delta = delta.to(device=x.device, dtype=torch.uint8).contiguous()
+        if delta.shape != (q,):
+            raise ValueError("delta must have shape (Q,)")
+    F = torch.empty((q,), dtype=_out_dtype(y, p), device=x.device)
+    _check(_lib.ecdf_delta_at(d, n, _ptr(x), _ptr(y), q, _ptr(z), _ptr(delta), _ptr(F), p,
+                              _stream_ptr(stream)), "ecdf_delta_at")
+    return F
+
+
+def kde_uniform(x, h, z=None, w=None, prec="f64", stream=None):
+    """Uniform-kernel density estimate at the points z (default: the sample
+    points) for each bandwidth row of h (C ABI ``kde_uniform``): (nh, Q)."""
+    x = _x(x)
+    d, n = x.shape
+    z = x if z is None else _x(z)
+    q = z.shape[1]
+    p = _prec(prec)
+    w = _y(w, n, p, x)
+    hm = _hmat(h, d)
+    hs = (ctypes.c_double * hm.size)(*hm.reshape(-1).tolist())
+    dt = torch.float64 if p == MECDF_F64 else torch.float32
+    f = torch.empty((hm.shape[0], q), dtype=dt, device=x.device)
+    _check(_lib.kde_uniform(d, n, _ptr(x), _ptr(w), q, _ptr(z), hm.shape[0], hs, _ptr(f), p,
+                            _stream_ptr(stream)), "kde_uniform")
+    return f
+
+
 def _hmat(h, d):
     import numpy as np
 

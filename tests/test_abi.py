@@ -130,3 +130,22 @@ def test_grid_kernel_sum_validation(lib):
     # the Matern channel arrays stop at d = 4
     mk = _c(lib, "kde_matern32_grid", [I, I64, P, P, P, P, I, P, P, I, P])
     assert mk(5, 10, fake, None, M, z, 1, h, fake, 0, None) == -4
+
+
+def test_arbitrary_point_queries_validation(lib):
+    fake = ctypes.c_void_p(0x1000)
+    ed = _c(lib, "ecdf_delta_at", [I, I64, P, P, I64, P, P, P, I, P])
+    assert ed(2, 0, fake, None, 5, fake, None, fake, 0, None) == -1     # N < 1
+    assert ed(2, 10, fake, None, -1, fake, None, fake, 0, None) == -1   # Q < 0
+    assert ed(2, 10, fake, None, 5, None, None, fake, 0, None) == -1    # z NULL
+    assert ed(2, 10, fake, None, 5, fake, None, None, 0, None) == -1    # F NULL
+    assert ed(2, 10, fake, None, 0, None, None, None, 0, None) == 0     # nothing to do
+    assert ed(2, 10, fake, None, (1 << 26) + 1, fake, None, fake, 0, None) == -4
+    ku = _c(lib, "kde_uniform", [I, I64, P, P, I64, P, I, P, P, I, P])
+    h = (ctypes.c_double * 2)(0.1, 0.2)
+    hneg = (ctypes.c_double * 2)(0.1, 0.0)
+    assert ku(2, 10, fake, None, 5, fake, 0, h, fake, 0, None) == -1     # nh < 1
+    assert ku(2, 10, fake, None, 5, fake, 1, hneg, fake, 0, None) == -1  # h <= 0
+    assert ku(2, 10, fake, None, 5, fake, 1, None, fake, 0, None) == -1
+    assert ku(2, 10, fake, None, 5, fake, 1, h, None, 0, None) == -1
+    assert ku(2, 10, fake, None, (1 << 24) + 1, fake, 1, h, fake, 0, None) == -4

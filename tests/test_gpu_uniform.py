@@ -1,0 +1,124 @@
+"""Generalized ECDF of eq. (ECDFdelta) at arbitrary points (ecdf_delta_at)
+and the uniform-kernel density estimate through eq.
+(uniform_decomposition_nD) (kde_uniform) against the brute-force oracle:
+counts bit-exact, float64 within 1e-12 and float32 within 1e-5 of their
+|w| scales."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2005_03246_amd import mecdf
+
+    return mecdf
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+CASES = [(1, 1, 5), (1, 700, 900), (2, 2, 3), (2, 1500, 1000), (3, 2000, 1700), (4, 900, 600),
+         (5, 700, 400), (6, 600, 300)]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_ecdf_delta_random(lib, case):
+    d, n, q = case
+    g = np.random.default_rng(1300 + 17 * d + n)
+    x = np.round(g.normal(size=(d, n)), 1)         # many ties
+    z = np.round(g.normal(size=(d, q)), 1)
+    m = min(n, q) // 3
+    z[:, :m] = x[:, :m]                             # queries at data values
+    if n > 3 and q > 3:
+        x[0, 1] = np.nan
+        z[d - 1, 2] = np.nan
+        x[0, 2] = -0.0
+        z[0, 3] = 0.0
+    delta = g.integers(0, 1 << d, size=q).astype(np.uint8)
+    y = g.uniform(-1.0, 2.0, n)
+    got = lib.ecdf_delta_at(dev(x), dev(z), dev(delta, torch.uint8)).cpu().numpy()
+    assert np.array_equal(got, oracle.ecdf_delta(x, z, delta))
+    got = lib.ecdf_delta_at(dev(x), dev(z), dev(delta, torch.uint8), dev(y)).cpu().numpy()
+    s, a = oracle.ecdf_delta(x, z, delta, y)
+    ok = a > 0
+    assert np.all(got[~ok] == 0)
+    assert np.max(np.abs(got[ok] * n - s[ok]) / a[ok], initial=0.0) <= 1e-12
+    y32 = y.astype(np.float32)
+    got = lib.ecdf_delta_at(dev(x), dev(z), dev(delta, torch.uint8), dev(y32, torch.float32),
+                            prec="f32c").cpu().numpy().astype(np.float64)
+    s, a = oracle.ecdf_delta(x, z, delta, y32.astype(np.float64))
+    assert np.max(np.abs(got[ok] * n - s[ok]) / a[ok], initial=0.0) <= 1e-5
+
+
+def test_ecdf_delta_without_patterns_is_ecdf_points(lib):
+    """delta = NULL at z = x is the ECDF at the sample points (eq. (ECDF)),
+    which the points path computes through its own items."""
+    g = np.random.default_rng(1301)
+    x = np.round(g.normal(size=(3, 5000)), 1)
+    xt = dev(x)
+    assert np.array_equal(lib.ecdf_delta_at(xt, xt).cpu().numpy(),
+                          lib.ecdf_points(xt).cpu().numpy())
+
+
+def test_ecdf_delta_larger_sampled(lib):
+    """N = 2^17 data, Q = 2^16 queries (several merge levels), a sample of the
+    results against the oracle."""
+    g = np.random.default_rng(1302)
+    x = np.round(g.normal(size=(3, 1 << 17)), 2)
+    z = np.round(g.normal(size=(3, 1 << 16)), 2)
+    delta = g.integers(0, 8, size=1 << 16).astype(np.uint8)
+    got = lib.ecdf_delta_at(dev(x), dev(z), dev(delta, torch.uint8)).cpu().numpy()
+    pick = g.choice(1 << 16, 400, replace=False)
+    assert np.array_equal(got[pick], oracle.ecdf_delta(x, z[:, pick], delta[pick]))
+
+
+def test_ecdf_delta_all_queries_inert(lib):
+    x = np.zeros((2, 10))
+    z = np.array([[-1.0, np.nan], [5.0, 5.0]])
+    got = lib.ecdf_delta_at(dev(x), dev(z)).cpu().numpy()
+    assert got.tolist() == [0, 0]
+    empty = lib.ecdf_delta_at(dev(x), dev(np.zeros((2, 0))))
+    assert empty.numel() == 0
+
+
+UCASES = [(1, 900, 700), (2, 2, 3), (2, 2000, 1500), (3, 1500, 1000), (4, 800, 500),
+          (6, 500, 200)]
+
+
+@pytest.mark.parametrize("case", UCASES)
+def test_kde_uniform_random(lib, case):
+    d, n, q = case
+    g = np.random.default_rng(1400 + 19 * d + n)
+    x = np.round(g.normal(size=(d, n)), 1)
+    z = np.round(g.normal(size=(d, q)), 1)       # box ends on data values
+    hs = np.repeat(np.array([0.1, 0.5, 2.0])[:, None], d, 1)
+    hs[1] = np.round(g.uniform(0.1, 0.9, d), 1)
+    w = g.uniform(0.2, 2.0, n)
+    f = lib.kde_uniform(dev(x), hs, dev(z)).cpu().numpy()
+    want, _ = oracle.kde_uniform(x, z, hs)
+    assert np.allclose(f, want, rtol=1e-15, atol=0.0)
+    mass = 1.0 / (2.0 ** d * n * np.prod(hs, axis=1))[:, None]
+    fw = lib.kde_uniform(dev(x), hs, dev(z), dev(w)).cpu().numpy()
+    ww, _ = oracle.kde_uniform(x, z, hs, w)
+    assert np.max(np.abs(fw - ww) / (mass * np.sum(w))) <= 1e-12
+    f32 = lib.kde_uniform(dev(x), hs, dev(z), dev(w.astype(np.float32), torch.float32),
+                          prec="f32c").cpu().numpy().astype(np.float64)
+    w32, _ = oracle.kde_uniform(x, z, hs, w.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(f32 - w32) / (mass * np.sum(w))) <= 1e-5
+
+
+def test_kde_uniform_at_the_sample_points(lib):
+    """The default query points are the sample points (the point itself is
+    in its own box)."""
+    g = np.random.default_rng(1402)
+    x = np.round(g.uniform(0, 1, size=(2, 3000)), 2)
+    f = lib.kde_uniform(dev(x), [0.05]).cpu().numpy()
+    want, _ = oracle.kde_uniform(x, x, [0.05])
+    assert np.allclose(f, want, rtol=1e-15, atol=0.0)
+    assert np.all(f > 0)
