@@ -821,8 +821,15 @@ __global__ __launch_bounds__(256) void k_kcarry_final(const KTileAgg<T, CH, NSD>
     }
 }
 
+// Workgroups per CU the apply pass asks the compiler to fit: the float64
+// two-channel d = 2 variant otherwise takes every register of a SIMD (one
+// wavefront each) for its two scans.
+template <typename T, int CH, int NSD> constexpr int kapply_min_blocks() {
+    return (std::is_same<T, double>::value && CH == 2 && NSD == 2) ? 2 : 1;
+}
+
 template <typename T, int CH, int NSD>
-__global__ __launch_bounds__(256) void k_kapply(KLevelArgs L, KBatch kb,
+__global__ __launch_bounds__(256, (kapply_min_blocks<T, CH, NSD>())) void k_kapply(KLevelArgs L, KBatch kb,
                                                 const KCarry<T, CH, NSD> *__restrict__ car,
                                                 const double *hi,
                                                 const uint32_t *__restrict__ hmap,
