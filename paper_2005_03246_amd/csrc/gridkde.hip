@@ -70,11 +70,22 @@ struct GkH {
     double ih[MECDF_MAX_DIM];  // 1/h per axis
 };
 
+constexpr int kGkLdsNodes = 4096;  // node tables up to this size searched in LDS
+
 // cell c = #{nodes < x} on each axis; key = C-order index of the cell vector
 __global__ __launch_bounds__(256) void k_gk_keys(GkGrid g, const double *__restrict__ zn,
-                                                 const double *__restrict__ x, int64_t n,
-                                                 uint32_t dropped, uint32_t *__restrict__ key,
+                                                 int64_t total, const double *__restrict__ x,
+                                                 int64_t n, uint32_t dropped,
+                                                 uint32_t *__restrict__ key,
                                                  uint32_t *__restrict__ idx) {
+    __shared__ double sn[kGkLdsNodes];
+    const bool lds = total <= kGkLdsNodes;
+    if (lds) {
+        for (int64_t t = threadIdx.x; t < total; t += 256)
+            sn[t] = zn[t];
+        __syncthreads();
+    }
+    const double *zb = lds ? sn : zn;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n)
         return;
@@ -83,7 +94,7 @@ __global__ __launch_bounds__(256) void k_gk_keys(GkGrid g, const double *__restr
     for (int a = 0; a < g.d; ++a) {
         const double v = x[(int64_t)a * n + i];
         nan = nan || v != v;
-        const double *z = zn + g.off[a];
+        const double *z = zb + g.off[a];
         int64_t lo = 0, hi = g.M[a];  // count of nodes < v in [lo, hi]
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
@@ -264,11 +275,12 @@ __global__ void k_gk_decays(GkGrid g, const double *__restrict__ zn, GkH hb, int
 struct GsArgs {
     const double *in;
     double *out;
-    double *agg;        // [col][chunk][dir][nt]: chunk sums, then entering values
+    double *agg;        // [chunk][dir][nt][col]: chunk sums, then entering values
     const double *dec;  // decays of axis k (dec[0] unused)
     const double *z;    // nodes of axis k
+    const double *span; // [dir][chunk][2]: the transfer of each chunk (P, G)
     double ih;
-    int64_t M, inner, outer, nodes, nck;
+    int64_t M, inner, outer, nodes, nck, cols;
     int nco, k, nt;
 };
 
@@ -306,6 +318,40 @@ __device__ __forceinline__ int64_t gs_arr(const GsArgs &a, int corner, int slot,
     return ((int64_t)(corner * a.nt + slot) * CH + v) * a.nodes;
 }
 
+// the chunk-sum slot of (column, chunk, direction, slot)
+__device__ __forceinline__ int64_t gs_agg(const GsArgs &a, int64_t col, int64_t ch, int dir,
+                                          int slot) {
+    return ((ch * 2 + dir) * a.nt + slot) * a.cols + col;
+}
+
+// The transfer across each chunk, the same for every line of the axis:
+// forward, from the node before chunk c to its last node; backward, from the
+// node after it to its first node: P = exp(-span / h), G = span / h.
+__global__ __launch_bounds__(256) void k_gs_spans(const double *__restrict__ z, int64_t M,
+                                                  int64_t nck, double ih,
+                                                  double *__restrict__ span) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * nck)
+        return;
+    const int dir = (int)(t / nck);
+    const int64_t ch = t - (int64_t)dir * nck;
+    const int64_t j0 = ch * kGkL;
+    const int64_t j1 = j0 + kGkL < M ? j0 + kGkL : M;
+    double sp = 0.0;
+    bool ok;
+    if (dir == 0) {
+        ok = ch > 0;
+        if (ok)
+            sp = z[j1 - 1] - z[j0 - 1];
+    } else {
+        ok = ch + 1 < nck;
+        if (ok)
+            sp = z[j1] - z[j0];
+    }
+    span[2 * t] = ok ? exp(-sp * ih) : 0.0;
+    span[2 * t + 1] = sp * ih;
+}
+
 // Matern slots taking the plain decay at stage k: R (from the second stage
 // on) and the T_l of the axes l > k
 __device__ __forceinline__ bool gs_plain(const GsArgs &a, int slot) {
@@ -323,7 +369,6 @@ __global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
     const int64_t j0 = c.chunk * kGkL;
     const int64_t j1 = j0 + kGkL < a.M ? j0 + kGkL : a.M;
     const int64_t st = a.inner;
-    double *ag = a.agg + (c.col * a.nck + c.chunk) * 2 * a.nt;
     const int ps = 1 + a.k;  // the slot paired with S (Matern)
     for (int dir = 0; dir < 2; ++dir) {
         const int corner = 2 * c.co + (dir == 0 ? 1 : 0);  // forward: upper nodes
@@ -349,9 +394,9 @@ __global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
                 rs = dk * rs + sI[j * st];
             }
         }
-        ag[dir * a.nt] = rs;
+        a.agg[gs_agg(a, c.col, c.chunk, dir, 0)] = rs;
         if (MAT) {
-            ag[dir * a.nt + ps] = rt;
+            a.agg[gs_agg(a, c.col, c.chunk, dir, ps)] = rt;
             for (int sl = 1; sl < a.nt; ++sl) {
                 if (!gs_plain(a, sl))
                     continue;
@@ -363,7 +408,7 @@ __global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
                 else
                     for (int64_t j = j1 - 1; j >= j0; --j)
                         r = (j + 1 < j1 ? a.dec[j + 1] : 0.0) * r + pI[j * st];
-                ag[dir * a.nt + sl] = r;
+                a.agg[gs_agg(a, c.col, c.chunk, dir, sl)] = r;
             }
         }
     }
@@ -371,34 +416,29 @@ __global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
 
 // One thread per (line, direction): the chunk sums become, in place, the
 // values entering each chunk (forward: the scan at the node before the
-// chunk; backward: at the node after it).
+// chunk; backward: at the node after it).  Neighbouring threads take
+// neighbouring lines, whose chunk sums sit next to each other.
 template <bool MAT>
-__global__ __launch_bounds__(256) void k_gs_carry(GsArgs a, int64_t cols) {
+__global__ __launch_bounds__(256) void k_gs_carry(GsArgs a) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= 2 * cols)
+    if (t >= 2 * a.cols)
         return;
-    const int dir = (int)(t & 1);
-    const int64_t col = t >> 1;
+    const int dir = (int)(t / a.cols);
+    const int64_t col = t - (int64_t)dir * a.cols;
     const int ps = 1 + a.k;
     constexpr int kMaxSlots = 1 + MECDF_MAX_DIM;
     double cr[kMaxSlots];
     for (int sl = 0; sl < kMaxSlots; ++sl)
         cr[sl] = 0.0;
+    const double *sp = a.span + (int64_t)dir * a.nck * 2;
     for (int64_t i = 0; i < a.nck; ++i) {
         const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
-        double *ag = a.agg + (col * a.nck + ch) * 2 * a.nt + dir * a.nt;
-        const int64_t j0 = ch * kGkL;
-        const int64_t j1 = j0 + kGkL < a.M ? j0 + kGkL : a.M;
-        // from the entering value's node to the chunk's far end
-        double span = 0.0;
-        if (i > 0)
-            span = dir == 0 ? a.z[j1 - 1] - a.z[j0 - 1] : a.z[j1] - a.z[j0];
-        const double P = i > 0 ? exp(-span * a.ih) : 0.0;
-        const double G = span * a.ih;
+        const double P = sp[2 * ch], G = sp[2 * ch + 1];
         const double s0 = cr[0];
         {
-            const double v = ag[0];
-            ag[0] = s0;
+            double *g = a.agg + gs_agg(a, col, ch, dir, 0);
+            const double v = *g;
+            *g = s0;
             cr[0] = P * s0 + v;
         }
         if (MAT) {
@@ -406,9 +446,10 @@ __global__ __launch_bounds__(256) void k_gs_carry(GsArgs a, int64_t cols) {
                 const bool pair = sl == ps;
                 if (!pair && !gs_plain(a, sl))
                     continue;
-                const double v = ag[sl];
+                double *g = a.agg + gs_agg(a, col, ch, dir, sl);
+                const double v = *g;
                 const double old = cr[sl];
-                ag[sl] = old;
+                *g = old;
                 cr[sl] = pair ? P * (old + G * s0) + v : P * old + v;
             }
         }
@@ -423,8 +464,9 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
     const GsCol c = gs_map<CH>(a, t);
     const int64_t j0 = c.chunk * kGkL;
     const int n = (int)((j0 + kGkL < a.M ? j0 + kGkL : a.M) - j0);
-    const double *ag = a.agg + (c.col * a.nck + c.chunk) * 2 * a.nt;
+    const double *ag = a.agg;
     const int ps = 1 + a.k;
+    auto entering = [&](int dir, int slot) { return ag[gs_agg(a, c.col, c.chunk, dir, slot)]; };
     // dk[i], gk[i]: the step between nodes j0+i-1 and j0+i (forward into
     // j0+i, backward out of it); i = n is the step from the next chunk
     double dk[kGkL + 1], gk[kGkL + 1];
@@ -445,7 +487,7 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
         const double *tU = MAT ? a.in + gs_arr<CH>(a, up, ps, c.v) + off : sU;
         const double *tD = MAT ? a.in + gs_arr<CH>(a, dn, ps, c.v) + off : sD;
         double *oS = a.out + gs_arr<CH>(a, c.co, 0, c.v) + off;
-        double rs = ag[0], rt = MAT ? ag[ps] : 0.0;
+        double rs = entering(0, 0), rt = MAT ? entering(0, ps) : 0.0;
 #pragma unroll
         for (int i = 0; i < kGkL; ++i) {
             if (i < n) {
@@ -456,8 +498,8 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
             fs[i] = rs;
             ft[i] = rt;
         }
-        rs = ag[a.nt];
-        rt = MAT ? ag[a.nt + ps] : 0.0;
+        rs = entering(1, 0);
+        rt = MAT ? entering(1, ps) : 0.0;
 #pragma unroll
         for (int i = kGkL - 1; i >= 0; --i) {
             if (i < n) {
@@ -475,14 +517,14 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
         if (a.k >= 1) {
             const double *rU = a.in + gs_arr<CH>(a, up, 1, c.v) + off;
             const double *rD = a.in + gs_arr<CH>(a, dn, 1, c.v) + off;
-            double r = ag[1];
+            double r = entering(0, 1);
 #pragma unroll
             for (int i = 0; i < kGkL; ++i) {
                 if (i < n)
                     r = dk[i] * r + rU[i * st];
                 ft[i] += r;
             }
-            r = ag[a.nt + 1];
+            r = entering(1, 1);
 #pragma unroll
             for (int i = kGkL - 1; i >= 0; --i) {
                 if (i < n) {
@@ -501,14 +543,14 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
             const double *pU = a.in + gs_arr<CH>(a, up, sl, c.v) + off;
             const double *pD = a.in + gs_arr<CH>(a, dn, sl, c.v) + off;
             double *oP = a.out + gs_arr<CH>(a, c.co, sl, c.v) + off;
-            double r = ag[sl];
+            double r = entering(0, sl);
 #pragma unroll
             for (int i = 0; i < kGkL; ++i) {
                 if (i < n)
                     r = dk[i] * r + pU[i * st];
                 fs[i] = r;
             }
-            r = ag[a.nt + sl];
+            r = entering(1, sl);
 #pragma unroll
             for (int i = kGkL - 1; i >= 0; --i) {
                 if (i < n) {
@@ -540,12 +582,14 @@ __global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__re
 }
 
 template <int CH, bool MAT>
-static void gs_launch(const GsArgs &ga, int64_t cols, hipStream_t s) {
-    const int64_t tot = cols * ga.nck;
+static void gs_launch(const GsArgs &ga, hipStream_t s) {
+    const int64_t tot = ga.cols * ga.nck;
+    hipLaunchKernelGGL(k_gs_spans, dim3((unsigned)ceil_div(2 * ga.nck, 256)), dim3(256), 0, s,
+                       ga.z, ga.M, ga.nck, ga.ih, const_cast<double *>(ga.span));
     hipLaunchKernelGGL((k_gs_agg<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
                        ga, tot);
-    hipLaunchKernelGGL(k_gs_carry<MAT>, dim3((unsigned)ceil_div(2 * cols, 256)), dim3(256), 0,
-                       s, ga, cols);
+    hipLaunchKernelGGL(k_gs_carry<MAT>, dim3((unsigned)ceil_div(2 * ga.cols, 256)), dim3(256), 0,
+                       s, ga);
     hipLaunchKernelGGL((k_gs_apply<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
                        s, ga, tot);
 }
@@ -576,10 +620,11 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     const int NT = matern ? 1 + d : 1;
     const int64_t nA = (int64_t)nch * NT * CH * g.nodes;
     const int64_t nB = (int64_t)(nch / 2) * NT * CH * g.nodes;
-    int64_t nagg = 0;
+    int64_t nagg = 0, nspan = 0;
     for (int a = 0; a < d; ++a) {
         const int64_t cols = (int64_t)(nch >> (a + 1)) * CH * (g.nodes / g.M[a]);
         nagg = std::max(nagg, cols * ceil_div(g.M[a], kGkL) * 2 * NT);
+        nspan = std::max(nspan, ceil_div(g.M[a], kGkL) * 4);
     }
     const bool has_w = CH == 2 || w != nullptr;
     ArenaPlan pl;
@@ -596,6 +641,7 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     pl.add<double>((size_t)nA);
     pl.add<double>((size_t)nB);
     pl.add<double>((size_t)nagg);
+    pl.add<double>((size_t)nspan);
     radix_plan(pl, N);
     void *wsb = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &wsb));
@@ -613,6 +659,7 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     double *bufA = ar.take<double>((size_t)nA);
     double *bufB = ar.take<double>((size_t)nB);
     double *agg = ar.take<double>((size_t)nagg);
+    double *span = ar.take<double>((size_t)nspan);
     RadixScratch rs = radix_take(ar, N);
     MECDF_TRY(upload_small(z, sizeof(double) * (size_t)total, zn, s));
     const unsigned nbN = (unsigned)ceil_div(N, 256);
@@ -621,7 +668,8 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     const int kbits = bits_for((uint64_t)cs);
     {
         ProfScope prof("gridkde_sort", s);
-        hipLaunchKernelGGL(k_gk_keys, dim3(nbN), dim3(256), 0, s, g, zn, x, N, dropped, k0, i0);
+        hipLaunchKernelGGL(k_gk_keys, dim3(nbN), dim3(256), 0, s, g, zn, total, x, N, dropped, k0,
+                           i0);
         int which = 0;
         MECDF_TRY((radix_sort_bits<uint32_t, uint32_t>(k0, i0, k1, i1, k2, i2, N, 0, kbits, rs,
                                                        s, &which)));
@@ -690,11 +738,12 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
                 ga.nco = nch >> (a + 1);
                 ga.k = a;
                 ga.nt = NT;
-                const int64_t cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
+                ga.cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
+                ga.span = span;
                 if (matern)
-                    gs_launch<CH, true>(ga, cols, s);
+                    gs_launch<CH, true>(ga, s);
                 else
-                    gs_launch<CH, false>(ga, cols, s);
+                    gs_launch<CH, false>(ga, s);
                 MECDF_LAUNCH_CHECK();
                 std::swap(in, outb);
             }
