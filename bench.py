@@ -294,10 +294,20 @@ def secondary():
     h4g = h4[[0, 21, 42, 63]]
     ms_g = _time_calls(lambda: mecdf.kde_laplace_grid(x4t, nodes4, h4g), 2, 1)
     ms_gr = _time_calls(lambda: mecdf.kreg_laplace_grid(x4t, y4t, nodes4, h4g), 2, 1)
+    ms_m = _time_calls(lambda: mecdf.kde_matern32_grid(x4t, nodes4, h4g), 2, 1)
+    ms_mr = _time_calls(lambda: mecdf.kreg_matern32_grid(x4t, y4t, nodes4, h4g), 2, 1)
     out["grid_kde_nw_d2_N2^22_1024^2_4h_f64"] = {
         "ms_kde": ms_g, "ms_nw": ms_gr,
-        "Gpoint-evals/s": 2 * 4 * 1024 ** 2 / ((ms_g + ms_gr) * 1e-3) / 1e9}
-    del x4t, y4t
+        "Gpoint-evals/s": 2 * 4 * 1024 ** 2 / ((ms_g + ms_gr) * 1e-3) / 1e9,
+        "matern32_ms_kde": ms_m, "matern32_ms_nw": ms_mr}
+    # the uniform kernel at the sample points (2^d shifted ECDFs per point)
+    log("secondary: uniform kernel d=2 N=2^20")
+    xu = x4t[:, : 1 << 20].contiguous()
+    ms_u = _time_calls(lambda: mecdf.kde_uniform(xu, [h4[21]]), 2, 1)
+    out["uniform_kde_d2_N2^20_at_points_1h_counts"] = {
+        "ms_per_call": ms_u, "Gpoint-evals/s": (1 << 20) / (ms_u * 1e-3) / 1e9,
+        "queries_per_call": 4 << 20}
+    del x4t, y4t, xu
     out["interpolation_error_study"] = interpolation_study()
     return out
 
