@@ -609,10 +609,11 @@ __device__ __forceinline__ Aff<T, CH, NSD> block_aff_scan(Aff<T, CH, NSD> v,
     return v;
 }
 
-// The same scans by shuffles inside each wavefront and one exchange of the
-// four wavefront totals through LDS (wt, 4 entries): inc is the thread's inclusive
-// composition (dir 0: threads 0..t in order; dir 1: threads 255..t), exc the
-// exclusive one (identity for the first thread in scan order).
+// The same scans by lane moves inside each wavefront (wave_aff_scan below)
+// and one exchange of the four wavefront totals through LDS (wt, 4 entries):
+// inc is the thread's inclusive composition (dir 0: threads 0..t in order;
+// dir 1: threads 255..t), exc the exclusive one (identity for the first
+// thread in scan order).
 template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ Aff<T, CH, NSD> aff_shfl(const Aff<T, CH, NSD> &a, int src) {
     Aff<T, CH, NSD> r;
@@ -630,19 +631,94 @@ __device__ __forceinline__ Aff<T, CH, NSD> aff_shfl(const Aff<T, CH, NSD> &a, in
     return r;
 }
 
+// A value from another lane by a DPP move (CTRL: the DPP control word, RM:
+// the rows that receive it; other lanes keep 0).
+template <int CTRL, int RM, typename V> __device__ __forceinline__ V dpp_mov(V v) {
+    if constexpr (sizeof(V) == 8) {
+        union {
+            V t;
+            int i[2];
+        } u;
+        u.t = v;
+        u.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, RM, 0xf, false);
+        u.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, RM, 0xf, false);
+        return u.t;
+    } else {
+        union {
+            V t;
+            int i;
+        } u;
+        u.t = v;
+        u.i = __builtin_amdgcn_update_dpp(0, u.i, CTRL, RM, 0xf, false);
+        return u.t;
+    }
+}
+template <int CTRL, int RM, bool A, typename T, int CH, int NSD>
+__device__ __forceinline__ Aff<T, CH, NSD> aff_dpp(const Aff<T, CH, NSD> &a) {
+    Aff<T, CH, NSD> r;
+    r.lo = A ? dpp_mov<CTRL, RM>(a.lo) : 0.0;
+    r.hi = A ? dpp_mov<CTRL, RM>(a.hi) : 0.0;
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        r.m[b] = A ? T(1) : dpp_mov<CTRL, RM>(a.m[b]);
+#pragma unroll
+        for (int s = 0; s < NSD; ++s)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                r.l[b][s][c] = dpp_mov<CTRL, RM>(a.l[b][s][c]);
+    }
+    return r;
+}
+
+// DPP controls: row_shr:n (lane i of a 16-lane row takes lane i - n), row_shl:n
+// (lane i + n), row_bcast:15 / :31 (the last lane of row 0 / 1 to the rows
+// above it), wave_shr:1 / wave_shl:1 (lane i - 1 / i + 1 across the wave)
+constexpr int kDppRowShr = 0x110, kDppRowShl = 0x100, kDppBcast15 = 0x142, kDppBcast31 = 0x143,
+              kDppWaveShr1 = 0x138, kDppWaveShl1 = 0x130;
+
+// Inclusive scan of the wavefront's maps in lane order (dir 0: lanes 0..i
+// composed in order; dir 1: lanes 63..i).  Within each row of 16 lanes by
+// DPP row shifts (1, 2, 4, 8), then across rows: forward by the row
+// broadcasts of the last lanes of rows 0 and 1, backward by taking the first
+// lane of the next row (rows 0 and 2), then lane 32 (rows 0 and 1).
+template <bool A, typename T, int CH, int NSD>
+__device__ __forceinline__ Aff<T, CH, NSD> wave_aff_scan(Aff<T, CH, NSD> x, int dir,
+                                                         const double (&ih)[kKB]) {
+    const int lane = threadIdx.x & 63;
+    const int rl = lane & 15, row = lane >> 4;
+    if (dir == 0) {
+        { const auto o = aff_dpp<kDppRowShr + 1, 0xf, A>(x); if (rl >= 1) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShr + 2, 0xf, A>(x); if (rl >= 2) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShr + 4, 0xf, A>(x); if (rl >= 4) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShr + 8, 0xf, A>(x); if (rl >= 8) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppBcast15, 0xa, A>(x); if (row & 1) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppBcast31, 0xc, A>(x); if (row >= 2) x = aff_then<A>(o, x, ih); }
+    } else {
+        { const auto o = aff_dpp<kDppRowShl + 1, 0xf, A>(x); if (rl + 1 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShl + 2, 0xf, A>(x); if (rl + 2 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShl + 4, 0xf, A>(x); if (rl + 4 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dpp<kDppRowShl + 8, 0xf, A>(x); if (rl + 8 < 16) x = aff_then<A>(o, x, ih); }
+        {
+            const auto o = aff_shfl<A>(x, (16 * (row + 1)) & 63);
+            if ((row & 1) == 0)
+                x = aff_then<A>(o, x, ih);
+        }
+        {
+            const auto o = aff_shfl<A>(x, 32);
+            if (row < 2)
+                x = aff_then<A>(o, x, ih);
+        }
+    }
+    return x;
+}
+
 template <bool A, typename T, int CH, int NSD>
 __device__ __forceinline__ void block_aff_scan2(const Aff<T, CH, NSD> &v, Aff<T, CH, NSD> *wt,
                                                 int dir, Aff<T, CH, NSD> &inc,
                                                 Aff<T, CH, NSD> &exc, const double (&ih)[kKB]) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    Aff<T, CH, NSD> x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const Aff<T, CH, NSD> o = aff_shfl<A>(x, dir ? ((lane + off) & 63) : ((lane - off) & 63));
-        if (dir ? (lane + off < 64) : (lane >= off))
-            x = aff_then<A>(o, x, ih);
-    }
+    const Aff<T, CH, NSD> x = wave_aff_scan<A>(v, dir, ih);
     __syncthreads();  // the totals of an earlier scan have been read
     if (lane == (dir ? 0 : 63))
         wt[w] = x;
@@ -656,13 +732,14 @@ __device__ __forceinline__ void block_aff_scan2(const Aff<T, CH, NSD> &v, Aff<T,
             pre = aff_then<A>(pre, wt[q], ih);
     }
     inc = aff_then<A>(pre, x, ih);
-    const Aff<T, CH, NSD> nb = aff_shfl<A>(x, dir ? ((lane + 1) & 63) : ((lane - 1) & 63));
+    const Aff<T, CH, NSD> nb =
+        dir ? aff_dpp<kDppWaveShl1, 0xf, A>(x) : aff_dpp<kDppWaveShr1, 0xf, A>(x);
     exc = (dir ? lane == 63 : lane == 0) ? pre : aff_then<A>(pre, nb, ih);
 }
 
 // Which block scan a kernel uses: the LDS tree keeps fewer values in
 // registers, which is what float64 density sums (one channel) need to keep
-// three wavefronts per SIMD; the shuffle scan needs almost no LDS and fewer
+// three wavefronts per SIMD; the wavefront scan needs almost no LDS and fewer
 // barriers, which wins for two channels and for float32.
 template <typename T, int CH> constexpr bool shfl_scan() {
     return !(std::is_same<T, double>::value && CH == 1);
