@@ -408,8 +408,12 @@ typedef struct {
  * ints, or NULL) receives each dataset's index b of its largest score (the
  * lowest such b on ties; -1 when nh[s] = 0): the grid-search choice, and the
  * label mecdf_bw_train takes.  sets, nh and h are host arrays.  Every
- * dataset is checked before the first is run; datasets are then processed in
- * order on the stream; same errors as kde_laplace.
+ * dataset is checked before the first is run; same errors as kde_laplace.
+ * The small datasets are scored by one work-queue launch on the stream; the
+ * recursions of the larger ones run on a few streams the library keeps
+ * beside it (default priority), which wait for the work enqueued on the
+ * stream before the call and which the stream waits for before the best
+ * indices are taken, so the call is ordered on the stream as a whole.
  */
 int mecdf_kde_lcv_batched(const mecdf_dataset *sets, int nsets, const int *nh,
                           const double *h, double *lcv, int *best, int prec,

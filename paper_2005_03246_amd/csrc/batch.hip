@@ -10,8 +10,8 @@
 // point (so the logarithm exists where every kernel term is below the float64
 // range), staging the points through LDS; the 256 log terms of a unit are
 // added in a fixed tree and the units of a (dataset, bandwidth) in order.
-// Larger datasets run the orthant recursion of kde_laplace one after the
-// other.  Which size is "small" is chosen per dimension and precision by an
+// Larger datasets run the orthant recursion of kde_laplace, spread over a
+// few streams beside the caller's so that several run at once.  Which size is "small" is chosen per dimension and precision by an
 // autotuner that times both on the device (mecdf_autotune) and keeps its
 // choice in a JSON file keyed by the GPU architecture.
 //
@@ -346,25 +346,84 @@ static int dc_run(const mecdf_dataset &ds, int nh, const double *h, double *lcv,
     return kde_run(ds.d, ds.N, ds.x, nullptr, nh, hh.data(), nullptr, lcv, 0, prec, s);
 }
 
-// Eager batch on the caller's stream (the library workspace holds the queue's
-// data; it is reused by the recursions afterwards, in stream order).
+// The recursions of the larger datasets run beside each other, dataset j on
+// side stream j mod kSideStreams (each a chain of small launches that leaves
+// most of the GPU idle on its own), each stream in its own region of working
+// memory, sized for the largest of its datasets.
+static int dc_regions(const BatchLayout &L, const mecdf_dataset *sets, const int *nh,
+                      const double *h, double *lcv, int prec,
+                      size_t (&region)[kSideStreams]) {
+    for (int k = 0; k < kSideStreams; ++k)
+        region[k] = 0;
+    for (size_t j = 0; j < L.dc.size(); ++j) {
+        const int i = L.dc[j];
+        size_t b = 0;
+        set_workspace_sizing(&b);
+        const int rc = dc_run(sets[i], nh[i], h + L.off[i], lcv + L.off[i], prec, nullptr);
+        set_workspace_sizing(nullptr);
+        if (rc != kSizingOnly && rc != MECDF_OK)
+            return rc;
+        const size_t k = j % kSideStreams;
+        region[k] = std::max(region[k], (b + 255) & ~size_t(255));
+    }
+    return MECDF_OK;
+}
+
+static int dc_launch(const std::vector<mecdf_dataset> &sets, const std::vector<int> &nh,
+                     const std::vector<const double *> &h, const std::vector<double *> &lcv,
+                     int prec, char *const (&base)[kSideStreams],
+                     const size_t (&region)[kSideStreams], hipStream_t s) {
+    if (sets.empty())
+        return MECDF_OK;
+    hipStream_t side[kSideStreams];
+    MECDF_TRY(side_streams(s, side));
+    for (size_t j = 0; j < sets.size(); ++j) {
+        const size_t k = j % kSideStreams;
+        FixedWorkspace fixed(base[k], region[k]);
+        MECDF_TRY(dc_run(sets[j], nh[j], h[j], lcv[j], prec, side[k]));
+    }
+    return side_streams_join(s);
+}
+
+// Eager batch on the caller's stream: the work queue there, the recursions
+// on the side streams, joined back before the best indices are taken; the
+// library workspace holds the queue's data and the recursions' regions.
 int batch_lcv(const mecdf_dataset *sets, int nsets, const int *nh, const double *h,
               double *lcv, int *best, int prec, int force, hipStream_t s) {
     const BatchLayout L = batch_layout(sets, nsets, nh, prec, force);
-    if (!L.q.empty()) {
-        ArenaPlan pl;
+    size_t region[kSideStreams];
+    MECDF_TRY(dc_regions(L, sets, nh, h, lcv, prec, region));
+    ArenaPlan pl;
+    if (!L.q.empty())
         queue_plan(pl, L);
-        void *wsb = nullptr;
-        MECDF_TRY(workspace_reserve(pl.used, &wsb));
-        Arena a;
-        a.base = (char *)wsb;
-        const QueueMem m = queue_take(a, L);
+    for (int k = 0; k < kSideStreams; ++k)
+        pl.add<char>(region[k]);
+    void *wsb = nullptr;
+    MECDF_TRY(workspace_reserve(pl.used, &wsb));
+    Arena a;
+    a.base = (char *)wsb;
+    QueueMem m;
+    if (!L.q.empty())
+        m = queue_take(a, L);
+    char *base[kSideStreams];
+    for (int k = 0; k < kSideStreams; ++k)
+        base[k] = a.take<char>(region[k]);
+    if (!L.q.empty()) {
         MECDF_TRY(upload_small(L.q.data(), sizeof(QSet) * L.q.size(), m.sets, s));
         MECDF_TRY(upload_small(h, sizeof(double) * (size_t)L.nh_total, m.h, s));
         MECDF_TRY(queue_launch(L, m, prec, lcv, s));
     }
-    for (int i : L.dc)
-        MECDF_TRY(dc_run(sets[i], nh[i], h + L.off[i], lcv + L.off[i], prec, s));
+    std::vector<mecdf_dataset> ds;
+    std::vector<int> dn;
+    std::vector<const double *> dh;
+    std::vector<double *> dl;
+    for (int i : L.dc) {
+        ds.push_back(sets[i]);
+        dn.push_back(nh[i]);
+        dh.push_back(h + L.off[i]);
+        dl.push_back(lcv + L.off[i]);
+    }
+    MECDF_TRY(dc_launch(ds, dn, dh, dl, prec, base, region, s));
     if (best)
         MECDF_TRY(lcv_argmax(lcv, nh, nsets, best, s));
     return MECDF_OK;
@@ -375,8 +434,8 @@ int batch_lcv(const mecdf_dataset *sets, int nsets, const int *nh, const double 
 // with its own working memory.  The work queue of the small datasets (its
 // two kernels) is recorded once into a HIP graph.  A run forks that graph
 // onto the plan's side stream, enqueues the recursions of the larger datasets
-// on the caller's stream meanwhile (one chain of launches per dataset, in the
-// plan's working memory), joins the two and writes the best indices.  The
+// on the library's side streams meanwhile (one chain of launches per dataset,
+// in the plan's working memory), joins them all and writes the best indices.  The
 // recursions are not recorded: one dataset's chain is up to ~6000 launches
 // and hundreds of them would make a graph of hundreds of thousands of nodes
 // in one dependency chain.
@@ -392,8 +451,8 @@ struct LcvPlan {
     std::vector<int> dc_nh;
     std::vector<std::vector<double>> dc_h;
     std::vector<double *> dc_lcv;
-    void *dc_ws = nullptr;
-    size_t dc_bytes = 0;
+    char *dc_base[kSideStreams] = {};
+    size_t dc_region[kSideStreams] = {};
     int prec = MECDF_F64;
     int nsets = 0;
     double *lcv = nullptr;
@@ -428,26 +487,18 @@ static void plan_free(LcvPlan *p) {
 static int plan_build(LcvPlan *p, const mecdf_dataset *sets, int nsets, const int *nh,
                       const double *h, double *lcv, int *best, int prec, int force) {
     const BatchLayout L = batch_layout(sets, nsets, nh, prec, force);
-    size_t dc_bytes = 0;
-    set_workspace_sizing(&dc_bytes);
-    int rc = MECDF_OK;
-    for (int i : L.dc) {
-        rc = dc_run(sets[i], nh[i], h + L.off[i], lcv + L.off[i], prec, nullptr);
-        if (rc != kSizingOnly && rc != MECDF_OK)
-            break;
-        rc = MECDF_OK;
-    }
-    set_workspace_sizing(nullptr);
-    MECDF_TRY(rc);
+    MECDF_TRY(dc_regions(L, sets, nh, h, lcv, prec, p->dc_region));
     ArenaPlan pl;
     queue_plan(pl, L);
-    pl.add<char>(dc_bytes);
+    for (int k = 0; k < kSideStreams; ++k)
+        pl.add<char>(p->dc_region[k]);
     MECDF_TRY_HIP(hipMalloc(&p->mem, pl.used));
     Arena a;
     a.base = (char *)p->mem;
     const QueueMem m = queue_take(a, L);
-    p->dc_ws = a.take<char>(dc_bytes);
-    p->dc_bytes = dc_bytes;
+    for (int k = 0; k < kSideStreams; ++k)
+        p->dc_base[k] = a.take<char>(p->dc_region[k]);
+    int rc = MECDF_OK;
     MECDF_TRY_HIP(hipMemcpy(m.sets, L.q.data(), sizeof(QSet) * L.q.size(),
                             hipMemcpyHostToDevice));
     MECDF_TRY_HIP(hipMemcpy(m.h, h, sizeof(double) * (size_t)L.nh_total,
@@ -520,10 +571,11 @@ int lcv_plan_run(void *plan, hipStream_t s) {
         MECDF_TRY_HIP(hipEventRecord(p->join, p->side));
     }
     {
-        FixedWorkspace fixed(p->dc_ws, p->dc_bytes);
-        for (size_t k = 0; k < p->dc_sets.size(); ++k)
-            MECDF_TRY(dc_run(p->dc_sets[k], p->dc_nh[k], p->dc_h[k].data(), p->dc_lcv[k],
-                             p->prec, s));
+        std::vector<const double *> dh;
+        for (const auto &v : p->dc_h)
+            dh.push_back(v.data());
+        MECDF_TRY(dc_launch(p->dc_sets, p->dc_nh, dh, p->dc_lcv, p->prec, p->dc_base,
+                            p->dc_region, s));
     }
     if (p->exec)
         MECDF_TRY_HIP(hipStreamWaitEvent(s, p->join, 0));

@@ -54,6 +54,16 @@ struct Status {
 // synchronises the device, so buffers of earlier calls are never reused while
 // in flight.
 int workspace_reserve(size_t bytes, void **base);
+
+// Streams of the current device that run work beside the caller's stream:
+// side_streams makes each of them wait for the work enqueued on `caller` so
+// far and returns them; side_streams_join makes `caller` wait for everything
+// enqueued on them since.  Created on first use (default priority), kept
+// until the workspace is released.  Work spread over them must use disjoint
+// memory (FixedWorkspace regions).
+constexpr int kSideStreams = 8;
+int side_streams(hipStream_t caller, hipStream_t *streams);
+int side_streams_join(hipStream_t caller);
 void workspace_release_all();
 
 // While set (for the calling thread), workspace_reserve hands out this fixed

@@ -25,6 +25,11 @@ struct DeviceState {
     size_t pinned_bytes = 0;
     hipEvent_t pinned_done = nullptr;
     bool pinned_pending = false;
+    // streams beside the caller's (default priority) and their fork / join
+    // events
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
 };
 
 std::mutex g_mu;
@@ -111,6 +116,38 @@ int workspace_reserve(size_t bytes, void **base) {
         st.ws_bytes = want;
     }
     *base = st.ws;
+    return MECDF_OK;
+}
+
+int side_streams(hipStream_t caller, hipStream_t *streams) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    MECDF_TRY_HIP(hipGetDevice(&dev));
+    DeviceState &st = state(dev);
+    if (!st.fork) {
+        MECDF_TRY_HIP(hipEventCreateWithFlags(&st.fork, hipEventDisableTiming));
+        for (int k = 0; k < kSideStreams; ++k) {
+            MECDF_TRY_HIP(hipStreamCreateWithFlags(&st.side[k], hipStreamNonBlocking));
+            MECDF_TRY_HIP(hipEventCreateWithFlags(&st.join[k], hipEventDisableTiming));
+        }
+    }
+    MECDF_TRY_HIP(hipEventRecord(st.fork, caller));
+    for (int k = 0; k < kSideStreams; ++k) {
+        MECDF_TRY_HIP(hipStreamWaitEvent(st.side[k], st.fork, 0));
+        streams[k] = st.side[k];
+    }
+    return MECDF_OK;
+}
+
+int side_streams_join(hipStream_t caller) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int dev = 0;
+    MECDF_TRY_HIP(hipGetDevice(&dev));
+    DeviceState &st = state(dev);
+    for (int k = 0; k < kSideStreams; ++k) {
+        MECDF_TRY_HIP(hipEventRecord(st.join[k], st.side[k]));
+        MECDF_TRY_HIP(hipStreamWaitEvent(caller, st.join[k], 0));
+    }
     return MECDF_OK;
 }
 
@@ -216,7 +253,7 @@ void workspace_release_all() {
     (void)hipGetDevice(&cur);
     for (int dev = 0; dev < (int)g_dev.size(); ++dev) {
         DeviceState &st = g_dev[dev];
-        if (!st.ws && !st.pinned && !st.pinned_done)
+        if (!st.ws && !st.pinned && !st.pinned_done && !st.fork)
             continue;
         (void)hipSetDevice(dev);
         (void)hipDeviceSynchronize();
@@ -226,6 +263,13 @@ void workspace_release_all() {
             (void)hipHostFree(st.pinned);
         if (st.pinned_done)
             (void)hipEventDestroy(st.pinned_done);
+        if (st.fork) {
+            (void)hipEventDestroy(st.fork);
+            for (int k = 0; k < kSideStreams; ++k) {
+                (void)hipStreamDestroy(st.side[k]);
+                (void)hipEventDestroy(st.join[k]);
+            }
+        }
         st = DeviceState();
     }
     (void)hipSetDevice(cur);
