@@ -644,6 +644,9 @@ __global__ __launch_bounds__(256) void k_block_count(Item<1> *__restrict__ S,
     }
     __syncthreads();
     int cur = 0;
+    // the levels unrolled, so that each search has a fixed number of steps
+    // and the two items' searches interleave
+#pragma unroll
     for (int len = 1; len < T; len <<= 1) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -652,15 +655,22 @@ __global__ __launch_bounds__(256) void k_block_count(Item<1> *__restrict__ S,
             const bool inA = (r & len) == 0;
             const int ob = inA ? b0 + len : b0;
             const uint32_t key = sk[cur][r];
-            // A items count B keys below theirs, B items A keys at or below
-            int lo = 0, hi = len;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                const uint32_t k2 = sk[cur][ob + mid];
+            // A items count B keys below theirs, B items A keys at or below:
+            // the number of keys of the other run (sorted, len of them) that
+            // satisfy the test, by halving steps over its first len - 1 and a
+            // last look at the key it stops at
+            const uint32_t *o = sk[cur] + ob;
+            int lo = 0;
+#pragma unroll
+            for (int step = len >> 1; step > 0; step >>= 1) {
+                const uint32_t k2 = o[lo + step - 1];
                 if (inA ? (k2 < key) : (k2 <= key))
-                    lo = mid + 1;
-                else
-                    hi = mid;
+                    lo += step;
+            }
+            {
+                const uint32_t k2 = o[lo];
+                if (inA ? (k2 < key) : (k2 <= key))
+                    lo += 1;
             }
             const int slot = sx[cur][r];
             const PV other = lo > 0 ? sp[cur][ob + lo - 1] : PV(0);
