@@ -156,3 +156,32 @@ def test_grid_sums_do_not_depend_on_the_previous_call(lib):
         nz = scale[0] > 0
         assert np.all(f[~nz] == 0)
         assert np.max(np.abs(f[nz] - want[0][nz]) / scale[0][nz]) <= 1e-12
+
+
+def test_grid_sums_at_the_benchmark_size_sampled(lib):
+    """The kernel-sum workload sample (N = 2^22, d = 2) on a 1024^2 grid over
+    its range, four of its bandwidths, as the benchmark runs it: 200 sampled
+    nodes (and the corners) against the oracle, Laplacian and Matern-3/2,
+    KDE and NW."""
+    x4, y4, h4 = datagen.config4()
+    nodes = datagen.uniform_grid(x4, 1024)
+    hs = h4[[0, 21, 42, 63]]
+    xt, yt = dev(x4), dev(y4)
+    g = np.random.default_rng(78)
+    pick = np.concatenate([g.choice(1024 * 1024, 200, replace=False),
+                           [0, 1023, 1024 * 1023, 1024 * 1024 - 1]])
+    zq = oracle.grid_points(nodes)[:, pick]
+    for fn, ref in ((lib.kde_laplace_grid, oracle.kde_laplace),
+                    (lib.kde_matern32_grid, oracle.kde_matern32)):
+        f = fn(xt, nodes, hs).cpu().numpy().reshape(len(hs), -1)[:, pick]
+        want, scale = ref(x4, zq, hs)
+        nz = scale > 0
+        assert np.all(f[~nz] == 0)
+        assert np.max(np.abs(f[nz] - want[nz]) / scale[nz]) <= 1e-12
+    for fn, ref in ((lib.kreg_laplace_grid, oracle.nw_regression),
+                    (lib.kreg_matern32_grid, oracle.nw_matern32)):
+        m = fn(xt, yt, nodes, hs).cpu().numpy().reshape(len(hs), -1)[:, pick]
+        wm = ref(x4, y4, zq, hs)
+        ok = np.isfinite(wm)
+        assert np.array_equal(np.isfinite(m), ok)
+        assert np.max(np.abs(m[ok] - wm[ok])) <= 1e-12 * np.max(np.abs(y4))

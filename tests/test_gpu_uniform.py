@@ -122,3 +122,19 @@ def test_kde_uniform_at_the_sample_points(lib):
     want, _ = oracle.kde_uniform(x, x, [0.05])
     assert np.allclose(f, want, rtol=1e-15, atol=0.0)
     assert np.all(f > 0)
+
+
+def test_kde_uniform_at_the_benchmark_size_sampled(lib):
+    """The benchmark's uniform-kernel call: the first 2^20 points of the
+    kernel-sum workload sample (d = 2) at the points themselves, one
+    bandwidth (4 x 2^20 corner queries); 300 sampled points against the
+    oracle's box counts."""
+    from paper_2005_03246_amd import datagen
+
+    x4, _, h4 = datagen.config4()
+    x = np.ascontiguousarray(x4[:, : 1 << 20])
+    f = lib.kde_uniform(dev(x), [h4[21]]).cpu().numpy()[0]
+    g = np.random.default_rng(1403)
+    pick = g.choice(1 << 20, 300, replace=False)
+    want, _ = oracle.kde_uniform(x, x[:, pick], [h4[21]])
+    assert np.allclose(f[pick], want[0], rtol=1e-15, atol=0.0)
