@@ -427,30 +427,57 @@ __global__ __launch_bounds__(256) void k_gs_carry(GsArgs a) {
     const int64_t col = t - (int64_t)dir * a.cols;
     const int ps = 1 + a.k;
     constexpr int kMaxSlots = 1 + MECDF_MAX_DIM;
+    constexpr int kG = 16;  // chunk sums loaded together before the serial steps
     double cr[kMaxSlots];
     for (int sl = 0; sl < kMaxSlots; ++sl)
         cr[sl] = 0.0;
     const double *sp = a.span + (int64_t)dir * a.nck * 2;
-    for (int64_t i = 0; i < a.nck; ++i) {
-        const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
-        const double P = sp[2 * ch], G = sp[2 * ch + 1];
-        const double s0 = cr[0];
+    for (int64_t i0 = 0; i0 < a.nck; i0 += kG) {
+        const int ng = (int)(a.nck - i0 < kG ? a.nck - i0 : kG);
+        // S first: its values before each step feed the pair's update
+        double s0[kG];
         {
-            double *g = a.agg + gs_agg(a, col, ch, dir, 0);
-            const double v = *g;
-            *g = s0;
-            cr[0] = P * s0 + v;
+            double v[kG];
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                const int64_t i = i0 + g;
+                const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
+                v[g] = g < ng ? a.agg[gs_agg(a, col, ch, dir, 0)] : 0.0;
+            }
+#pragma unroll
+            for (int g = 0; g < kG; ++g) {
+                if (g >= ng)
+                    break;
+                const int64_t i = i0 + g;
+                const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
+                s0[g] = cr[0];
+                a.agg[gs_agg(a, col, ch, dir, 0)] = cr[0];
+                cr[0] = sp[2 * ch] * cr[0] + v[g];
+            }
         }
         if (MAT) {
             for (int sl = 1; sl < a.nt; ++sl) {
                 const bool pair = sl == ps;
                 if (!pair && !gs_plain(a, sl))
                     continue;
-                double *g = a.agg + gs_agg(a, col, ch, dir, sl);
-                const double v = *g;
-                const double old = cr[sl];
-                *g = old;
-                cr[sl] = pair ? P * (old + G * s0) + v : P * old + v;
+                double v[kG];
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    const int64_t i = i0 + g;
+                    const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
+                    v[g] = g < ng ? a.agg[gs_agg(a, col, ch, dir, sl)] : 0.0;
+                }
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    if (g >= ng)
+                        break;
+                    const int64_t i = i0 + g;
+                    const int64_t ch = dir == 0 ? i : a.nck - 1 - i;
+                    const double P = sp[2 * ch], G = sp[2 * ch + 1];
+                    const double old = cr[sl];
+                    a.agg[gs_agg(a, col, ch, dir, sl)] = old;
+                    cr[sl] = pair ? P * (old + G * s0[g]) + v[g] : P * old + v[g];
+                }
             }
         }
     }
