@@ -184,11 +184,31 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
             for (int v = 0; v < CH; ++v)
                 s[q][u][v] = e[q][u][v] = 0.0;
     const int64_t p0 = start[cell], p1 = start[cell + 1];
+    // the next point's coordinates and weight are loaded while this one is
+    // summed
+    double nx[D], nw = 0.0;
+    if (p0 < p1) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            nx[a] = xs[(int64_t)a * n + p0];
+        nw = CH == 1 ? (w0 ? w0[p0] : 1.0) : w1[p0];
+    }
     for (int64_t p = p0; p < p1; ++p) {
+        double cx[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            cx[a] = nx[a];
+        const double cw = nw;
+        if (p + 1 < p1) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                nx[a] = xs[(int64_t)a * n + p + 1];
+            nw = CH == 1 ? (w0 ? w0[p + 1] : 1.0) : w1[p + 1];
+        }
         double du[D], dd[D], fu[D], fd[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const double v = xs[(int64_t)a * n + p];
+            const double v = cx[a];
             const double *z = zn + g.off[a];
             const bool hu = c[a] < g.M[a], hd = c[a] > 0;
             du[a] = hu ? (z[c[a]] - v) * hb.ih[a] : 0.0;
@@ -201,10 +221,10 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
         }
         double wv[CH];
         if (CH == 1) {
-            wv[0] = w0 ? w0[p] : 1.0;
+            wv[0] = cw;
         } else {
             wv[0] = 1.0;
-            wv[CH - 1] = w1[p];
+            wv[CH - 1] = cw;
         }
 #pragma unroll
         for (int lq = 0; lq < NCG; ++lq) {
