@@ -70,6 +70,13 @@ struct GkH {
     double ih[MECDF_MAX_DIM];  // 1/h per axis
 };
 
+// Bandwidths handled by one launch (blockIdx.y picks one), each with its own
+// arrays at a fixed stride.
+constexpr int kGkGroup = 4;
+struct GkHs {
+    GkH h[kGkGroup];
+};
+
 constexpr int kGkLdsNodes = 4096;  // node tables up to this size searched in LDS
 
 // cell c = #{nodes < x} on each axis; key = C-order index of the cell vector
@@ -156,8 +163,11 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
                                                  const double *__restrict__ xs, int64_t n,
                                                  const uint32_t *__restrict__ start,
                                                  const double *__restrict__ w0,
-                                                 const double *__restrict__ w1, GkH hb,
-                                                 double *__restrict__ bins) {
+                                                 const double *__restrict__ w1, GkHs hs,
+                                                 double *__restrict__ bins_all,
+                                                 int64_t bins_stride) {
+    const GkH &hb = hs.h[blockIdx.y];
+    double *__restrict__ bins = bins_all + (int64_t)blockIdx.y * bins_stride;
     constexpr int NCG = gk_ncg<D>();
     constexpr int NG = (1 << D) / NCG;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -271,8 +281,10 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
 }
 
 // decays between neighbouring nodes: dec[off_a + j] = exp(-(z_j - z_{j-1}) ih_a), j >= 1
-__global__ void k_gk_decays(GkGrid g, const double *__restrict__ zn, GkH hb, int64_t total,
-                            double *__restrict__ dec) {
+__global__ void k_gk_decays(GkGrid g, const double *__restrict__ zn, GkHs hs, int64_t total,
+                            double *__restrict__ dec_all) {
+    const GkH &hb = hs.h[blockIdx.y];
+    double *__restrict__ dec = dec_all + (int64_t)blockIdx.y * total;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total)
         return;
@@ -302,6 +314,10 @@ struct GsArgs {
     double ih;
     int64_t M, inner, outer, nodes, nck, cols;
     int nco, k, nt;
+};
+
+struct GsBatch {
+    GsArgs a[kGkGroup];
 };
 
 struct GsCol {
@@ -347,9 +363,12 @@ __device__ __forceinline__ int64_t gs_agg(const GsArgs &a, int64_t col, int64_t 
 // The transfer across each chunk, the same for every line of the axis:
 // forward, from the node before chunk c to its last node; backward, from the
 // node after it to its first node: P = exp(-span / h), G = span / h.
-__global__ __launch_bounds__(256) void k_gs_spans(const double *__restrict__ z, int64_t M,
-                                                  int64_t nck, double ih,
-                                                  double *__restrict__ span) {
+__global__ __launch_bounds__(256) void k_gs_spans(GsBatch gb) {
+    const GsArgs &a = gb.a[blockIdx.y];
+    const double *__restrict__ z = a.z;
+    const int64_t M = a.M, nck = a.nck;
+    const double ih = a.ih;
+    double *__restrict__ span = const_cast<double *>(a.span);
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= 2 * nck)
         return;
@@ -381,7 +400,8 @@ __device__ __forceinline__ bool gs_plain(const GsArgs &a, int slot) {
 }
 
 template <int CH, bool MAT>
-__global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
+__global__ __launch_bounds__(256) void k_gs_agg(GsBatch gb, int64_t total) {
+    const GsArgs &a = gb.a[blockIdx.y];
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total)
         return;
@@ -439,7 +459,8 @@ __global__ __launch_bounds__(256) void k_gs_agg(GsArgs a, int64_t total) {
 // chunk; backward: at the node after it).  Neighbouring threads take
 // neighbouring lines, whose chunk sums sit next to each other.
 template <bool MAT>
-__global__ __launch_bounds__(256) void k_gs_carry(GsArgs a) {
+__global__ __launch_bounds__(256) void k_gs_carry(GsBatch gb) {
+    const GsArgs &a = gb.a[blockIdx.y];
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= 2 * a.cols)
         return;
@@ -504,7 +525,8 @@ __global__ __launch_bounds__(256) void k_gs_carry(GsArgs a) {
 }
 
 template <int CH, bool MAT>
-__global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
+__global__ __launch_bounds__(256) void k_gs_apply(GsBatch gb, int64_t total) {
+    const GsArgs &a = gb.a[blockIdx.y];
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total)
         return;
@@ -611,10 +633,17 @@ __global__ __launch_bounds__(256) void k_gs_apply(GsArgs a, int64_t total) {
 
 // out[node] = norm * (S + R) (CH = 1), or the ratio of the second value's to
 // the first value's S + R (CH = 2); R only for the Matern kernel
+struct GkNorms {
+    double v[kGkGroup];
+};
+
 template <int CH, typename OutT>
-__global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__restrict__ fin,
-                                                    int matern, double norm,
-                                                    OutT *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__restrict__ fin_all,
+                                                    int64_t fin_stride, int matern, GkNorms nm,
+                                                    OutT *__restrict__ out_all) {
+    const double *__restrict__ fin = fin_all + (int64_t)blockIdx.y * fin_stride;
+    OutT *__restrict__ out = out_all + (int64_t)blockIdx.y * g.nodes;
+    const double norm = nm.v[blockIdx.y];
     const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (node >= g.nodes)
         return;
@@ -628,17 +657,19 @@ __global__ __launch_bounds__(256) void k_gk_combine(GkGrid g, const double *__re
     out[node] = CH == 1 ? (OutT)(s[0] * norm) : (OutT)(s[CH - 1] / s[0]);
 }
 
+// the bandwidths of a group share every size; only pointers and 1/h differ
 template <int CH, bool MAT>
-static void gs_launch(const GsArgs &ga, hipStream_t s) {
+static void gs_launch(const GsBatch &gb, int nb, hipStream_t s) {
+    const GsArgs &ga = gb.a[0];
     const int64_t tot = ga.cols * ga.nck;
-    hipLaunchKernelGGL(k_gs_spans, dim3((unsigned)ceil_div(2 * ga.nck, 256)), dim3(256), 0, s,
-                       ga.z, ga.M, ga.nck, ga.ih, const_cast<double *>(ga.span));
-    hipLaunchKernelGGL((k_gs_agg<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, s,
-                       ga, tot);
-    hipLaunchKernelGGL(k_gs_carry<MAT>, dim3((unsigned)ceil_div(2 * ga.cols, 256)), dim3(256), 0,
-                       s, ga);
-    hipLaunchKernelGGL((k_gs_apply<CH, MAT>), dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0,
-                       s, ga, tot);
+    hipLaunchKernelGGL(k_gs_spans, dim3((unsigned)ceil_div(2 * ga.nck, 256), nb), dim3(256), 0,
+                       s, gb);
+    hipLaunchKernelGGL((k_gs_agg<CH, MAT>), dim3((unsigned)ceil_div(tot, 256), nb), dim3(256), 0,
+                       s, gb, tot);
+    hipLaunchKernelGGL(k_gs_carry<MAT>, dim3((unsigned)ceil_div(2 * ga.cols, 256), nb),
+                       dim3(256), 0, s, gb);
+    hipLaunchKernelGGL((k_gs_apply<CH, MAT>), dim3((unsigned)ceil_div(tot, 256), nb), dim3(256),
+                       0, s, gb, tot);
 }
 
 template <int CH, typename WT, typename OutT>
@@ -674,9 +705,14 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         nspan = std::max(nspan, ceil_div(g.M[a], kGkL) * 4);
     }
     const bool has_w = CH == 2 || w != nullptr;
+    // bandwidths per launch group: up to kGkGroup, fewer where the arrays of
+    // one bandwidth are large (about 16 GB for a group at most)
+    const double per_bw = 8.0 * (double)(nA + nB + nagg + nspan + total);
+    int G = (int)std::min<double>((double)kGkGroup, std::max(1.0, 16e9 / per_bw));
+    G = std::min(G, nh);
     ArenaPlan pl;
     pl.add<double>((size_t)total);          // nodes
-    pl.add<double>((size_t)total);          // decays
+    pl.add<double>((size_t)total * G);      // decays
     for (int q = 0; q < 3; ++q)
         pl.add<uint32_t>((size_t)N);        // keys
     for (int q = 0; q < 3; ++q)
@@ -685,17 +721,17 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     if (has_w)
         pl.add<double>((size_t)N);          // weights / responses in cell order
     pl.add<uint32_t>((size_t)g.cells + 1);  // cell starts
-    pl.add<double>((size_t)nA);
-    pl.add<double>((size_t)nB);
-    pl.add<double>((size_t)nagg);
-    pl.add<double>((size_t)nspan);
+    pl.add<double>((size_t)nA * G);
+    pl.add<double>((size_t)nB * G);
+    pl.add<double>((size_t)nagg * G);
+    pl.add<double>((size_t)nspan * G);
     radix_plan(pl, N);
     void *wsb = nullptr;
     MECDF_TRY(workspace_reserve(pl.used, &wsb));
     Arena ar;
     ar.base = (char *)wsb;
     double *zn = ar.take<double>((size_t)total);
-    double *dec = ar.take<double>((size_t)total);
+    double *dec = ar.take<double>((size_t)total * G);
     uint32_t *k0 = ar.take<uint32_t>((size_t)N), *k1 = ar.take<uint32_t>((size_t)N),
              *k2 = ar.take<uint32_t>((size_t)N);
     uint32_t *i0 = ar.take<uint32_t>((size_t)N), *i1 = ar.take<uint32_t>((size_t)N),
@@ -703,10 +739,10 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     double *xs = ar.take<double>((size_t)N * d);
     double *ws = has_w ? ar.take<double>((size_t)N) : nullptr;
     uint32_t *cstart = ar.take<uint32_t>((size_t)g.cells + 1);
-    double *bufA = ar.take<double>((size_t)nA);
-    double *bufB = ar.take<double>((size_t)nB);
-    double *agg = ar.take<double>((size_t)nagg);
-    double *span = ar.take<double>((size_t)nspan);
+    double *bufA = ar.take<double>((size_t)nA * G);
+    double *bufB = ar.take<double>((size_t)nB * G);
+    double *agg = ar.take<double>((size_t)nagg * G);
+    double *span = ar.take<double>((size_t)nspan * G);
     RadixScratch rs = radix_take(ar, N);
     MECDF_TRY(upload_small(z, sizeof(double) * (size_t)total, zn, s));
     const unsigned nbN = (unsigned)ceil_div(N, 256);
@@ -728,24 +764,29 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
                            s, ks, N, g.cells, cstart);
         MECDF_LAUNCH_CHECK();
     }
-    for (int b = 0; b < nh; ++b) {
-        GkH hb{};
-        double prod = 1.0;
-        for (int a = 0; a < d; ++a) {
-            hb.ih[a] = 1.0 / h[(size_t)b * d + a];
-            prod *= h[(size_t)b * d + a];
+    for (int b0 = 0; b0 < nh; b0 += G) {
+        const int nb = std::min(G, nh - b0);
+        GkHs hs{};
+        GkNorms nm{};
+        for (int j = 0; j < nb; ++j) {
+            double prod = 1.0;
+            for (int a = 0; a < d; ++a) {
+                hs.h[j].ih[a] = 1.0 / h[(size_t)(b0 + j) * d + a];
+                prod *= h[(size_t)(b0 + j) * d + a];
+            }
+            nm.v[j] = 1.0 / ((double)nch * (matern ? (double)(1 + d) : 1.0) * (double)N * prod);
         }
         {
             ProfScope prof("gridkde_bins", s);
-            hipLaunchKernelGGL(k_gk_decays, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0,
-                               s, g, zn, hb, total, dec);
+            hipLaunchKernelGGL(k_gk_decays, dim3((unsigned)ceil_div(total, 256), nb), dim3(256), 0,
+                               s, g, zn, hs, total, dec);
             const double *w0 = CH == 1 ? ws : nullptr;
             const double *w1 = CH == 2 ? ws : nullptr;
             const int ng = d <= 2 ? 1 : nch / 4;
             const unsigned nbc = (unsigned)ceil_div(g.cells * ng, 256);
 #define MECDF_GKB(D, NTV)                                                                      \
-    hipLaunchKernelGGL((k_gk_bins<D, CH, NTV>), dim3(nbc), dim3(256), 0, s, g, zn, xs, N,     \
-                       cstart, w0, w1, hb, bufA)
+    hipLaunchKernelGGL((k_gk_bins<D, CH, NTV>), dim3(nbc, nb), dim3(256), 0, s, g, zn, xs, N, \
+                       cstart, w0, w1, hs, bufA, nA)
             if (!matern) {
                 switch (d) {
                 case 1: MECDF_GKB(1, 1); break;
@@ -769,36 +810,39 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         {
             ProfScope prof("gridkde_scan", s);
             double *in = bufA, *outb = bufB;
+            int64_t in_st = nA, out_st = nB;
             for (int a = 0; a < d; ++a) {
-                GsArgs ga{};
-                ga.in = in;
-                ga.out = outb;
-                ga.agg = agg;
-                ga.dec = dec + g.off[a];
-                ga.z = zn + g.off[a];
-                ga.ih = hb.ih[a];
-                ga.M = g.M[a];
-                ga.inner = g.nst[a];
-                ga.outer = g.nodes / (g.M[a] * g.nst[a]);
-                ga.nodes = g.nodes;
-                ga.nck = ceil_div(g.M[a], kGkL);
-                ga.nco = nch >> (a + 1);
-                ga.k = a;
-                ga.nt = NT;
-                ga.cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
-                ga.span = span;
+                GsBatch gb{};
+                for (int j = 0; j < nb; ++j) {
+                    GsArgs &ga = gb.a[j];
+                    ga.in = in + (int64_t)j * in_st;
+                    ga.out = outb + (int64_t)j * out_st;
+                    ga.agg = agg + (int64_t)j * nagg;
+                    ga.dec = dec + (int64_t)j * total + g.off[a];
+                    ga.z = zn + g.off[a];
+                    ga.span = span + (int64_t)j * nspan;
+                    ga.ih = hs.h[j].ih[a];
+                    ga.M = g.M[a];
+                    ga.inner = g.nst[a];
+                    ga.outer = g.nodes / (g.M[a] * g.nst[a]);
+                    ga.nodes = g.nodes;
+                    ga.nck = ceil_div(g.M[a], kGkL);
+                    ga.nco = nch >> (a + 1);
+                    ga.k = a;
+                    ga.nt = NT;
+                    ga.cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
+                }
                 if (matern)
-                    gs_launch<CH, true>(ga, s);
+                    gs_launch<CH, true>(gb, nb, s);
                 else
-                    gs_launch<CH, false>(ga, s);
+                    gs_launch<CH, false>(gb, nb, s);
                 MECDF_LAUNCH_CHECK();
                 std::swap(in, outb);
+                std::swap(in_st, out_st);
             }
-            const double norm = 1.0 / ((double)nch * (matern ? (double)(1 + d) : 1.0) *
-                                       (double)N * prod);
-            hipLaunchKernelGGL((k_gk_combine<CH, OutT>), dim3((unsigned)ceil_div(g.nodes, 256)),
-                               dim3(256), 0, s, g, in, matern, norm,
-                               out + (int64_t)b * g.nodes);
+            hipLaunchKernelGGL((k_gk_combine<CH, OutT>),
+                               dim3((unsigned)ceil_div(g.nodes, 256), nb), dim3(256), 0, s, g, in,
+                               in_st, matern, nm, out + (int64_t)b0 * g.nodes);
             MECDF_LAUNCH_CHECK();
         }
     }

@@ -185,3 +185,27 @@ def test_grid_sums_at_the_benchmark_size_sampled(lib):
         ok = np.isfinite(wm)
         assert np.array_equal(np.isfinite(m), ok)
         assert np.max(np.abs(m[ok] - wm[ok])) <= 1e-12 * np.max(np.abs(y4))
+
+
+def test_grid_sums_in_several_bandwidth_groups(lib):
+    """Bandwidths go through the kernels in groups of four: six of them (a
+    full group and a partial one), each against the oracle."""
+    g = np.random.default_rng(79)
+    x = np.round(g.normal(size=(2, 2000)), 2)
+    y = np.sin(x[0])
+    nodes = [np.linspace(-3, 3, 45), np.linspace(-2.5, 2.5, 37)]
+    hs = hmat([0.05, 0.1, 0.2, 0.4, 0.8, 1.6], 2)
+    hs[2] = [0.15, 0.3]
+    zq = oracle.grid_points(nodes)
+    for fn, ref in ((lib.kde_laplace_grid, oracle.kde_laplace),
+                    (lib.kde_matern32_grid, oracle.kde_matern32)):
+        f = fn(dev(x), nodes, hs).cpu().numpy().reshape(len(hs), -1)
+        want, scale = ref(x, zq, hs)
+        nz = scale > 0
+        assert np.all(f[~nz] == 0)
+        assert np.max(np.abs(f[nz] - want[nz]) / scale[nz]) <= 1e-12
+    m = lib.kreg_matern32_grid(dev(x), dev(y), nodes, hs).cpu().numpy().reshape(len(hs), -1)
+    wm = oracle.nw_matern32(x, y, zq, hs)
+    ok = np.isfinite(wm)
+    assert np.array_equal(np.isfinite(m), ok)
+    assert np.max(np.abs(m[ok] - wm[ok])) <= 1e-12
