@@ -296,17 +296,40 @@ def secondary():
     ms_gr = _time_calls(lambda: mecdf.kreg_laplace_grid(x4t, y4t, nodes4, h4g), 2, 1)
     ms_m = _time_calls(lambda: mecdf.kde_matern32_grid(x4t, nodes4, h4g), 2, 1)
     ms_mr = _time_calls(lambda: mecdf.kreg_matern32_grid(x4t, y4t, nodes4, h4g), 2, 1)
+    # per bandwidth of the Laplacian KDE: the bins (coordinates of the points
+    # in cell order and the cell starts read, the 2^d corner arrays written;
+    # four exponentials per point) and the two axes' scans (each stage reads
+    # its input arrays once and writes its output arrays once: 4 + 2, then
+    # 2 + 1, then the combined array read and the result written)
+    kg = _profiled(lambda: mecdf.kde_laplace_grid(x4t, nodes4, h4g))
+    nodes_n = 1024 * 1024
+    cells = 1025 * 1025
+    bins_bytes = n4 * 16 + (cells + 1) * 4 + 4 * nodes_n * 8
+    scan_bytes = (4 + 2 + 2 + 1 + 1 + 1) * nodes_n * 8
+    gk_bins = _rate(kg, "gridkde_bins", bins_bytes)
+    if gk_bins:
+        gk_bins["fp64_exp_per_s"] = 4 * n4 / (gk_bins["avg_launch_ms"] * 1e-3)
     out["grid_kde_nw_d2_N2^22_1024^2_4h_f64"] = {
         "ms_kde": ms_g, "ms_nw": ms_gr,
         "Gpoint-evals/s": 2 * 4 * 1024 ** 2 / ((ms_g + ms_gr) * 1e-3) / 1e9,
-        "matern32_ms_kde": ms_m, "matern32_ms_nw": ms_mr}
+        "matern32_ms_kde": ms_m, "matern32_ms_nw": ms_mr,
+        "kernels_kde": {"gridkde_bins": gk_bins,
+                        "gridkde_scan": _rate(kg, "gridkde_scan", scan_bytes),
+                        "kernel_ms_per_call": {k: v[0] for k, v in kg.items()}}}
     # the uniform kernel at the sample points (2^d shifted ECDFs per point)
     log("secondary: uniform kernel d=2 N=2^20")
     xu = x4t[:, : 1 << 20].contiguous()
     ms_u = _time_calls(lambda: mecdf.kde_uniform(xu, [h4[21]]), 2, 1)
+    ku = _profiled(lambda: mecdf.kde_uniform(xu, [h4[21]]))
+    items_u = (1 << 20) + (4 << 20)  # data items and corner queries
     out["uniform_kde_d2_N2^20_at_points_1h_counts"] = {
         "ms_per_call": ms_u, "Gpoint-evals/s": (1 << 20) / (ms_u * 1e-3) / 1e9,
-        "queries_per_call": 4 << 20}
+        "queries_per_call": 4 << 20,
+        "kernels": {
+            # the counting merge levels: 8-byte item and 8-byte {prefix,
+            # count} pair, each read and written, as in the points workload
+            "points_merge_count": _rate(ku, "points_merge_count", items_u * 32),
+            "kernel_ms_per_call": {k: v[0] for k, v in ku.items()}}}
     del x4t, y4t, xu
     out["interpolation_error_study"] = interpolation_study()
     return out
