@@ -300,15 +300,17 @@ def secondary():
     # in cell order and the cell starts read, the 2^d corner arrays written;
     # four exponentials per point) and the two axes' scans (each stage reads
     # its input arrays once and writes its output arrays once: 4 + 2, then
-    # 2 + 1, then the combined array read and the result written)
+    # 2 + 1, then the combined array read and the result written); the four
+    # bandwidths go through each kernel together
     kg = _profiled(lambda: mecdf.kde_laplace_grid(x4t, nodes4, h4g))
     nodes_n = 1024 * 1024
     cells = 1025 * 1025
-    bins_bytes = n4 * 16 + (cells + 1) * 4 + 4 * nodes_n * 8
-    scan_bytes = (4 + 2 + 2 + 1 + 1 + 1) * nodes_n * 8
+    nbw = len(h4g)
+    bins_bytes = nbw * (n4 * 16 + (cells + 1) * 4 + 4 * nodes_n * 8)
+    scan_bytes = nbw * (4 + 2 + 2 + 1 + 1 + 1) * nodes_n * 8
     gk_bins = _rate(kg, "gridkde_bins", bins_bytes)
     if gk_bins:
-        gk_bins["fp64_exp_per_s"] = 4 * n4 / (gk_bins["avg_launch_ms"] * 1e-3)
+        gk_bins["fp64_exp_per_s"] = nbw * 4 * n4 / (gk_bins["avg_launch_ms"] * 1e-3)
     out["grid_kde_nw_d2_N2^22_1024^2_4h_f64"] = {
         "ms_kde": ms_g, "ms_nw": ms_gr,
         "Gpoint-evals/s": 2 * 4 * 1024 ** 2 / ((ms_g + ms_gr) * 1e-3) / 1e9,
