@@ -225,7 +225,10 @@ int ecdf_delta_at(int d, int64_t N, const double *x, const void *y, int64_t Q,
  * with lo_k = z_{k,q} - h_{b,k} and hi_k = z_{k,q} + h_{b,k}, each rounded to
  * a double, computed as eq. (uniform_decomposition_nD): the signed sum of
  * ecdf_delta_at at the 2^d box corners, all corners of a bandwidth in one
- * recursion.  With w == NULL the box counts are exact integers before the
+ * recursion.  When z is x itself (the same pointer, Q == N) the corners'
+ * ranks are read from tables over the distinct data values instead of being
+ * searched per corner (same results, bit for bit, as a copy of x passed as
+ * z).  With w == NULL the box counts are exact integers before the
  * final scaling; weighted sums are float64 differences of F_N values (their
  * error is relative to the total |w| mass, not to the box's).
  *

@@ -670,6 +670,45 @@ __device__ __forceinline__ Aff<T, CH, NSD> aff_dpp(const Aff<T, CH, NSD> &a) {
     return r;
 }
 
+// The same with the lanes that have no source lane set to 0 (bound_ctrl), for
+// controls that write every row: nothing to clear beforehand.
+template <int CTRL, typename V> __device__ __forceinline__ V dpp_movz(V v) {
+    if constexpr (sizeof(V) == 8) {
+        union {
+            V t;
+            int i[2];
+        } u;
+        u.t = v;
+        u.i[0] = __builtin_amdgcn_mov_dpp(u.i[0], CTRL, 0xf, 0xf, true);
+        u.i[1] = __builtin_amdgcn_mov_dpp(u.i[1], CTRL, 0xf, 0xf, true);
+        return u.t;
+    } else {
+        union {
+            V t;
+            int i;
+        } u;
+        u.t = v;
+        u.i = __builtin_amdgcn_mov_dpp(u.i, CTRL, 0xf, 0xf, true);
+        return u.t;
+    }
+}
+template <int CTRL, bool A, typename T, int CH, int NSD>
+__device__ __forceinline__ Aff<T, CH, NSD> aff_dppz(const Aff<T, CH, NSD> &a) {
+    Aff<T, CH, NSD> r;
+    r.lo = A ? dpp_movz<CTRL>(a.lo) : 0.0;
+    r.hi = A ? dpp_movz<CTRL>(a.hi) : 0.0;
+#pragma unroll
+    for (int b = 0; b < kKB; ++b) {
+        r.m[b] = A ? T(1) : dpp_movz<CTRL>(a.m[b]);
+#pragma unroll
+        for (int s = 0; s < NSD; ++s)
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                r.l[b][s][c] = dpp_movz<CTRL>(a.l[b][s][c]);
+    }
+    return r;
+}
+
 // DPP controls: row_shr:n (lane i of a 16-lane row takes lane i - n), row_shl:n
 // (lane i + n), row_bcast:15 / :31 (the last lane of row 0 / 1 to the rows
 // above it), wave_shr:1 / wave_shl:1 (lane i - 1 / i + 1 across the wave)
@@ -687,17 +726,17 @@ __device__ __forceinline__ Aff<T, CH, NSD> wave_aff_scan(Aff<T, CH, NSD> x, int 
     const int lane = threadIdx.x & 63;
     const int rl = lane & 15, row = lane >> 4;
     if (dir == 0) {
-        { const auto o = aff_dpp<kDppRowShr + 1, 0xf, A>(x); if (rl >= 1) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShr + 2, 0xf, A>(x); if (rl >= 2) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShr + 4, 0xf, A>(x); if (rl >= 4) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShr + 8, 0xf, A>(x); if (rl >= 8) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShr + 1, A>(x); if (rl >= 1) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShr + 2, A>(x); if (rl >= 2) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShr + 4, A>(x); if (rl >= 4) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShr + 8, A>(x); if (rl >= 8) x = aff_then<A>(o, x, ih); }
         { const auto o = aff_dpp<kDppBcast15, 0xa, A>(x); if (row & 1) x = aff_then<A>(o, x, ih); }
         { const auto o = aff_dpp<kDppBcast31, 0xc, A>(x); if (row >= 2) x = aff_then<A>(o, x, ih); }
     } else {
-        { const auto o = aff_dpp<kDppRowShl + 1, 0xf, A>(x); if (rl + 1 < 16) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShl + 2, 0xf, A>(x); if (rl + 2 < 16) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShl + 4, 0xf, A>(x); if (rl + 4 < 16) x = aff_then<A>(o, x, ih); }
-        { const auto o = aff_dpp<kDppRowShl + 8, 0xf, A>(x); if (rl + 8 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShl + 1, A>(x); if (rl + 1 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShl + 2, A>(x); if (rl + 2 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShl + 4, A>(x); if (rl + 4 < 16) x = aff_then<A>(o, x, ih); }
+        { const auto o = aff_dppz<kDppRowShl + 8, A>(x); if (rl + 8 < 16) x = aff_then<A>(o, x, ih); }
         {
             const auto o = aff_shfl<A>(x, (16 * (row + 1)) & 63);
             if ((row & 1) == 0)

@@ -217,6 +217,74 @@ __global__ __launch_bounds__(256) void k_query_ranks(const double *__restrict__ 
     qinert[q] = inert ? 1 : 0;
 }
 
+// The double whose order key is k (the inverse of order_key; -0 comes back
+// as +0 and every NaN as the one NaN the keys keep).
+__device__ __forceinline__ double key_value(uint64_t k) {
+    const uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// Queries at the 2^d corners x_i + delta h of the data points themselves
+// (coordinates x_{k,i} + h_k and x_{k,i} - h_k, rounded once): the corner's
+// rank on axis k depends only on the dense rank r of x_{k,i}, so it is found
+// once per distinct value, by the rule of k_query_ranks (<= for + h, the
+// strict < for - h): tab[r] for + h, tab[N + r] for - h, 0xffffffff where no
+// data value counts (the query is inert).  Rounding is monotone, so the
+// searches of neighbouring values hit neighbouring entries.
+constexpr uint32_t kNoRank = 0xffffffffu;
+__global__ __launch_bounds__(256) void k_shift_table(const uint64_t *__restrict__ uv,
+                                                     const uint32_t *__restrict__ U, int64_t N,
+                                                     double h, uint32_t *__restrict__ tab) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nu = *U;
+    if (r >= nu)
+        return;
+    const double v = key_value(uv[r]);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const double e = side ? v - h : v + h;
+        uint32_t out = kNoRank;
+        if (e == e) {
+            const uint64_t key = order_key(e);
+            int64_t lo = 0, hi = nu;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (side ? uv[mid] < key : uv[mid] <= key)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo > 0)
+                out = (uint32_t)(lo - 1);
+        }
+        tab[(int64_t)side * N + r] = out;
+    }
+}
+
+// Corner t = c N + i of data point i (bit k of c set: x_{k,i} - h_k, the
+// strict inequality): its ranks from the tables; a point with a NaN
+// coordinate gives inert corners, as a NaN query coordinate does.
+__global__ __launch_bounds__(256) void k_query_ranks_shift(const uint32_t *__restrict__ rank,
+                                                           const uint32_t *__restrict__ drop,
+                                                           int64_t N, int d,
+                                                           const uint32_t *__restrict__ tab,
+                                                           int64_t Q,
+                                                           uint32_t *__restrict__ qrank,
+                                                           uint8_t *__restrict__ qinert) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= Q)
+        return;
+    const int64_t c = t / N, i = t - c * N;
+    bool inert = drop[i] != 0u;
+    for (int k = 0; k < d; ++k) {
+        const uint32_t r = rank[(int64_t)k * N + i];
+        const uint32_t e = tab[(int64_t)(2 * k + ((c >> k) & 1)) * N + r];
+        inert = inert || e == kNoRank;
+        qrank[(int64_t)k * Q + t] = e == kNoRank ? 0u : e;
+    }
+    qinert[t] = inert ? 1 : 0;
+}
+
 // Items of the data (slots 0..N-1) and of the queries (slots N..N+Q-1).  A
 // data point with a NaN coordinate and an inert query get the largest top
 // key, so they sort after every other item (the data before the queries) and
@@ -1169,6 +1237,11 @@ struct ExtQueries {
     int64_t Q;
     const double *z;
     const uint8_t *delta;  // NULL: <= on every axis
+    // corners of the data points instead of z and delta: Q = 2^d N queries,
+    // corner c of point i at slot c N + i, x_{k,i} - h_k and < where bit k of
+    // c is set, x_{k,i} + h_k and <= elsewhere
+    bool corners;
+    double h[MECDF_MAX_DIM];
 };
 
 template <int NC, bool kW, typename YT, typename OutT>
@@ -1194,6 +1267,8 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
         pl.add<uint64_t>((size_t)N * d);   // distinct values per axis
         pl.add<uint32_t>((size_t)nq * d);  // query ranks
         pl.add<uint8_t>((size_t)nq);       // inert queries
+        if (ext->corners)
+            pl.add<uint32_t>((size_t)N * 2 * d);  // corner rank tables
     }
     pl.add<uint64_t>((size_t)n2);          // topkey x3
     pl.add<uint64_t>((size_t)n2);
@@ -1240,6 +1315,7 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
     uint64_t *uv = ext ? a.take<uint64_t>((size_t)N * d) : nullptr;
     uint32_t *qrank = ext ? a.take<uint32_t>((size_t)nq * d) : nullptr;
     uint8_t *qinert = ext ? a.take<uint8_t>((size_t)nq) : nullptr;
+    uint32_t *ctab = (ext && ext->corners) ? a.take<uint32_t>((size_t)N * 2 * d) : nullptr;
     uint64_t *tk0 = a.take<uint64_t>((size_t)n2), *tk1 = a.take<uint64_t>((size_t)n2),
              *tk2 = a.take<uint64_t>((size_t)n2);
     uint32_t *sl0 = a.take<uint32_t>((size_t)n2), *sl1 = a.take<uint32_t>((size_t)n2),
@@ -1288,9 +1364,16 @@ static int points_run_t(int d, int64_t N, const double *x, const YT *y, OutT *F,
                 hipLaunchKernelGGL(k_rank_values, dim3(nbN), dim3(256), 0, s, flags, excl, ks,
                                    N, uv + (size_t)k * N);
         }
-        if (ext && nq > 0)
+        if (ext && nq > 0 && ext->corners) {
+            for (int k = 0; k < d; ++k)
+                hipLaunchKernelGGL(k_shift_table, dim3(nbN), dim3(256), 0, s, uv + (size_t)k * N,
+                                   U + k, N, ext->h[k], ctab + (size_t)k * 2 * N);
+            hipLaunchKernelGGL(k_query_ranks_shift, dim3((unsigned)ceil_div(nq, 256)), dim3(256),
+                               0, s, rank, drop, N, d, ctab, nq, qrank, qinert);
+        } else if (ext && nq > 0) {
             hipLaunchKernelGGL(k_query_ranks, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
                                ext->z, nq, d, ext->delta, uv, N, U, qrank, qinert);
+        }
         MECDF_LAUNCH_CHECK();
     }
     // ---- items, sorted by (coordinate 0, type)
@@ -1558,7 +1641,27 @@ int points_delta_run(int d, int64_t N, const double *x, const void *y, int64_t Q
         set_error("queries at arbitrary points support N <= 2^26 and Q <= 2^26");
         return MECDF_EUNSUPPORTED;
     }
-    const ExtQueries ext{Q, z, delta};
+    ExtQueries ext{};
+    ext.Q = Q;
+    ext.z = z;
+    ext.delta = delta;
+    return points_dispatch_d(d, N, x, y, F, 0, prec, &ext, s);
+}
+
+// eq. (ECDFdelta) at the 2^d corners x_i + delta h of every data point (the
+// corner queries of the uniform kernel at the sample points), F[c N + i].
+int points_corners_run(int d, int64_t N, const double *x, const void *y, const double *h,
+                       void *F, int prec, hipStream_t s) {
+    const int64_t Q = N << d;
+    if (N > (int64_t(1) << 26) || Q > (int64_t(1) << 26)) {
+        set_error("queries at the corners of the points support 2^d N <= 2^26");
+        return MECDF_EUNSUPPORTED;
+    }
+    ExtQueries ext{};
+    ext.Q = Q;
+    ext.corners = true;
+    for (int k = 0; k < d; ++k)
+        ext.h[k] = h[k];
     return points_dispatch_d(d, N, x, y, F, 0, prec, &ext, s);
 }
 

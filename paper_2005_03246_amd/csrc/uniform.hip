@@ -10,7 +10,9 @@
 // the points recursion with per-query patterns.
 //
 //   k_uni_corners   the 2^d Q corner queries and their delta masks
-//   recursion       eq. (ECDFdelta) at every corner (points.hip)
+//   recursion       eq. (ECDFdelta) at every corner (points.hip); at the
+//                   sample points themselves (z is x) the corners' ranks come
+//                   from the points' own ranks and no corner is formed here
 //   k_uni_combine   the signed sum per point, times 1/(2^d N prod h): exact
 //                   integer arithmetic for counts, float64 for weights
 #include "common.hpp"
@@ -19,6 +21,8 @@ namespace mecdf {
 
 int points_delta_run(int d, int64_t N, const double *x, const void *y, int64_t Q,
                      const double *z, const uint8_t *delta, void *F, int prec, hipStream_t s);
+int points_corners_run(int d, int64_t N, const double *x, const void *y, const double *h,
+                       void *F, int prec, hipStream_t s);
 
 struct UniH {
     double h[MECDF_MAX_DIM];
@@ -70,19 +74,25 @@ int kde_uniform_run(int d, int64_t N, const double *x, const void *w, int64_t Q,
         return MECDF_OK;
     const int64_t nq = Q << d;
     const bool weighted = w != nullptr;
+    const bool at_points = z == x && Q == N;
     // working memory of one recursion over all corners (the weights go in as
     // float64: float32 weights are converted first)
     size_t inner = 0;
     set_workspace_sizing(&inner);
-    const int rs = points_delta_run(d, N, x, weighted ? (const void *)x : nullptr, nq, nullptr,
-                                    nullptr, nullptr, MECDF_F64, s);
+    const double hs[MECDF_MAX_DIM] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+    const void *ys = weighted ? (const void *)x : nullptr;
+    const int rs = at_points ? points_corners_run(d, N, x, ys, hs, nullptr, MECDF_F64, s)
+                             : points_delta_run(d, N, x, ys, nq, nullptr, nullptr, nullptr,
+                                                MECDF_F64, s);
     set_workspace_sizing(nullptr);
     if (rs != kSizingOnly)
         return rs == MECDF_OK ? MECDF_EDEVICE : rs;
     const bool conv = weighted && prec != MECDF_F64;
     ArenaPlan pl;
-    pl.add<double>((size_t)nq * d);   // corner coordinates
-    pl.add<uint8_t>((size_t)nq);      // corner masks
+    if (!at_points) {
+        pl.add<double>((size_t)nq * d);  // corner coordinates
+        pl.add<uint8_t>((size_t)nq);     // corner masks
+    }
     pl.add<int64_t>((size_t)nq);      // corner ECDFs (int64 counts or doubles)
     if (conv)
         pl.add<double>((size_t)N);    // float64 weights
@@ -91,8 +101,8 @@ int kde_uniform_run(int d, int64_t N, const double *x, const void *w, int64_t Q,
     MECDF_TRY(workspace_reserve(mine + inner, &wsb));
     Arena ar;
     ar.base = (char *)wsb;
-    double *zc = ar.take<double>((size_t)nq * d);
-    uint8_t *dl = ar.take<uint8_t>((size_t)nq);
+    double *zc = at_points ? nullptr : ar.take<double>((size_t)nq * d);
+    uint8_t *dl = at_points ? nullptr : ar.take<uint8_t>((size_t)nq);
     void *G = ar.take<int64_t>((size_t)nq);
     double *wd = conv ? ar.take<double>((size_t)N) : nullptr;
     FixedWorkspace fixed((char *)wsb + mine, inner);
@@ -111,13 +121,17 @@ int kde_uniform_run(int d, int64_t N, const double *x, const void *w, int64_t Q,
             hb.h[k] = h[(size_t)b * d + k];
             prod *= hb.h[k];
         }
-        {
-            ProfScope prof("uniform_corners", s);
-            hipLaunchKernelGGL(k_uni_corners, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s,
-                               z, Q, d, hb, zc, dl);
-            MECDF_LAUNCH_CHECK();
+        if (at_points) {
+            MECDF_TRY(points_corners_run(d, N, x, wv, hb.h, G, MECDF_F64, s));
+        } else {
+            {
+                ProfScope prof("uniform_corners", s);
+                hipLaunchKernelGGL(k_uni_corners, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0,
+                                   s, z, Q, d, hb, zc, dl);
+                MECDF_LAUNCH_CHECK();
+            }
+            MECDF_TRY(points_delta_run(d, N, x, wv, nq, zc, dl, G, MECDF_F64, s));
         }
-        MECDF_TRY(points_delta_run(d, N, x, wv, nq, zc, dl, G, MECDF_F64, s));
         // counts come back raw, weighted sums as F_N (already over N)
         const double norm = 1.0 / ((double)(1 << d) * prod * (weighted ? 1.0 : (double)N));
         void *fb = (char *)f + (size_t)b * Q * osz;

@@ -138,3 +138,29 @@ def test_kde_uniform_at_the_benchmark_size_sampled(lib):
     pick = g.choice(1 << 20, 300, replace=False)
     want, _ = oracle.kde_uniform(x, x[:, pick], [h4[21]])
     assert np.allclose(f[pick], want[0], rtol=1e-15, atol=0.0)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_kde_uniform_at_points_matches_general_queries(lib, d):
+    """At the sample points (z is x itself) the corners' ranks come from the
+    points' own ranks; a copy of x goes through the general query path: the
+    two must agree bit for bit, with ties, signed zeros, infinities, NaN
+    coordinates and weights."""
+    g = np.random.default_rng(1404 + d)
+    n = 1500
+    x = np.round(g.normal(size=(d, n)), 1)
+    x[0, :5] = [0.0, -0.0, np.inf, -np.inf, np.nan]
+    if d > 1:
+        x[d - 1, 5:8] = [-0.0, np.nan, 0.1]
+    w = g.uniform(0.2, 2.0, n)
+    hs = np.round(np.abs(g.normal(size=(3, d))) + 0.05, 1)
+    xt = dev(x)
+    for wt in (None, dev(w)):
+        a = lib.kde_uniform(xt, hs, w=wt).cpu().numpy()
+        b = lib.kde_uniform(xt, hs, z=xt.clone(), w=wt).cpu().numpy()
+        assert np.array_equal(a, b, equal_nan=True)
+    want, _ = oracle.kde_uniform(x, x, hs)
+    got = lib.kde_uniform(xt, hs).cpu().numpy()
+    ok = ~np.isnan(x).any(axis=0)
+    assert np.allclose(got[:, ok], want[:, ok], rtol=1e-15, atol=0.0)
+    assert np.all(got[:, ~ok] == 0)
