@@ -36,18 +36,24 @@
 //   radix sort     stable: each cell's points are contiguous, in input order
 //   k_gk_gather    coordinates and weights in that order, once per call
 //   k_gk_starts    the first sorted position of every cell
-//   k_gk_bins      per bandwidth: one thread per cell (and corner group) adds
-//                  its points' corner weights in input order (float64,
-//                  Neumaier) and writes every bin of its corners; each bin of
-//                  each corner array belongs to exactly one cell
+//   k_gk_bins      one thread per cell (and corner group) adds its points'
+//                  corner weights in input order (float64, Neumaier), for up
+//                  to four bandwidths of the group at once, and writes every
+//                  bin of its corners; each bin of each corner array belongs
+//                  to exactly one cell
 //   k_gs_agg       per axis: decayed sums over chunks of kGkL nodes of every
 //   k_gs_carry     line (both directions), the values entering each chunk
 //   k_gs_apply     from those, and the scans of the chunks from their
 //                  entering values, corner pairs added as they are written
+//   k_gs_rows      the contiguous axis when its lines are at most 1024 nodes:
+//   (_mat)         one wavefront per line scans it in blocks of 64 nodes
+//                  (steps composed across the lanes), both directions, in
+//                  one pass
 //   k_gk_combine   times the normalisation (density) or as a ratio
 //                  (regression)
 #include <vector>
 
+#include "cells.hpp"
 #include "common.hpp"
 #include "radix.hpp"
 
@@ -64,6 +70,9 @@ struct GkGrid {
     int64_t nst[MECDF_MAX_DIM];    // node-array strides (C order)
     int64_t nodes;                 // prod M
     int64_t cells;                 // prod C
+    double z0[MECDF_MAX_DIM];      // first and last node of each axis and the
+    double zl[MECDF_MAX_DIM];      // mesh-division scale (M - 1) / (zl - z0)
+    double gs[MECDF_MAX_DIM];
 };
 
 struct GkH {
@@ -79,41 +88,49 @@ struct GkHs {
 
 constexpr int kGkLdsNodes = 4096;  // node tables up to this size searched in LDS
 
-// cell c = #{nodes < x} on each axis; key = C-order index of the cell vector
+// cell c = #{nodes < x} on each axis (a mesh-division guess checked exactly
+// against the nodes), key = C-order index of the cell vector.  One radix
+// tile of points per workgroup, which also counts the tile's keys by the
+// first radix digit (the low hbits bits): the counts the sort's first pass
+// needs.
 __global__ __launch_bounds__(256) void k_gk_keys(GkGrid g, const double *__restrict__ zn,
                                                  int64_t total, const double *__restrict__ x,
                                                  int64_t n, uint32_t dropped,
                                                  uint32_t *__restrict__ key,
-                                                 uint32_t *__restrict__ idx) {
+                                                 uint32_t *__restrict__ idx,
+                                                 uint32_t *__restrict__ hist, int hbits) {
     __shared__ double sn[kGkLdsNodes];
+    __shared__ uint32_t h[kRadixMaxDigits];
     const bool lds = total <= kGkLdsNodes;
-    if (lds) {
+    const int R = 1 << hbits;
+    for (int t = threadIdx.x; t < R; t += 256)
+        h[t] = 0u;
+    if (lds)
         for (int64_t t = threadIdx.x; t < total; t += 256)
             sn[t] = zn[t];
-        __syncthreads();
-    }
+    __syncthreads();
     const double *zb = lds ? sn : zn;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n)
-        return;
-    int64_t k = 0;
-    bool nan = false;
-    for (int a = 0; a < g.d; ++a) {
-        const double v = x[(int64_t)a * n + i];
-        nan = nan || v != v;
-        const double *z = zb + g.off[a];
-        int64_t lo = 0, hi = g.M[a];  // count of nodes < v in [lo, hi]
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (z[mid] < v)
-                lo = mid + 1;
-            else
-                hi = mid;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int q = 0; q < kRadixItems; ++q) {
+        const int64_t i = base + (int64_t)q * 256 + threadIdx.x;
+        if (i >= n)
+            break;
+        int64_t k = 0;
+        bool nan = false;
+        for (int a = 0; a < g.d; ++a) {
+            const double v = x[(int64_t)a * n + i];
+            nan = nan || v != v;
+            k += (int64_t)cell_index(zb + g.off[a], (int)g.M[a], g.z0[a], g.zl[a], g.gs[a], v) *
+                 g.cst[a];
         }
-        k += lo * g.cst[a];
+        const uint32_t kk = nan ? dropped : (uint32_t)k;
+        key[i] = kk;
+        idx[i] = (uint32_t)i;
+        atomicAdd(&h[kk & (uint32_t)(R - 1)], 1u);
     }
-    key[i] = nan ? dropped : (uint32_t)k;
-    idx[i] = (uint32_t)i;
+    __syncthreads();
+    for (int t = threadIdx.x; t < R; t += 256)
+        hist[(int64_t)blockIdx.x * R + t] = h[t];
 }
 
 // coordinates and weights in sorted order
@@ -155,19 +172,27 @@ __global__ __launch_bounds__(256) void k_gk_starts(const uint32_t *__restrict__ 
 // bits of the other axes are fixed by the thread's corner group).
 template <int D> constexpr int gk_ncg() { return D <= 2 ? (1 << D) : 4; }
 
+// Bandwidths of a launch group each thread sums (the cell's points are read
+// once for all of them): as many as keep the sums of one thread to about 16
+// values (NCG corners x NT slots x CH values each).
+template <int D, int CH, int NT> constexpr int gk_nbw() {
+    return gk_ncg<D>() * NT * CH <= 4 ? 4 : (gk_ncg<D>() * NT * CH <= 8 ? 2 : 1);
+}
+
 // Bin arrays: corner q, slot u (0: S; 1 + l: T_l, Matern only), value v
 // (CH = 1: the weights w or 1; CH = 2: 1 and y), each of g.nodes doubles at
-// ((q * NT + u) * CH + v) * g.nodes.
-template <int D, int CH, int NT>
+// ((q * NT + u) * CH + v) * g.nodes, for bandwidth b of the group at b *
+// bins_stride.  The workgroups of grid row y take the bandwidths [y NBW,
+// y NBW + NBW) of the nb in the group.
+template <int D, int CH, int NT, int NBW>
 __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restrict__ zn,
                                                  const double *__restrict__ xs, int64_t n,
                                                  const uint32_t *__restrict__ start,
                                                  const double *__restrict__ w0,
-                                                 const double *__restrict__ w1, GkHs hs,
+                                                 const double *__restrict__ w1, GkHs hs, int nb,
                                                  double *__restrict__ bins_all,
                                                  int64_t bins_stride) {
-    const GkH &hb = hs.h[blockIdx.y];
-    double *__restrict__ bins = bins_all + (int64_t)blockIdx.y * bins_stride;
+    const int bb = (int)blockIdx.y * NBW;  // first bandwidth of this row
     constexpr int NCG = gk_ncg<D>();
     constexpr int NG = (1 << D) / NCG;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -185,14 +210,16 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
         }
     }
     const int qbase = grp * NCG;
-    double s[NCG][NT][CH], e[NCG][NT][CH];
+    double s[NBW][NCG][NT][CH], e[NBW][NCG][NT][CH];
 #pragma unroll
-    for (int q = 0; q < NCG; ++q)
+    for (int j = 0; j < NBW; ++j)
 #pragma unroll
-        for (int u = 0; u < NT; ++u)
+        for (int q = 0; q < NCG; ++q)
 #pragma unroll
-            for (int v = 0; v < CH; ++v)
-                s[q][u][v] = e[q][u][v] = 0.0;
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int v = 0; v < CH; ++v)
+                    s[j][q][u][v] = e[j][q][u][v] = 0.0;
     const int64_t p0 = start[cell], p1 = start[cell + 1];
     // the next point's coordinates and weight are loaded while this one is
     // summed
@@ -215,19 +242,17 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
                 nx[a] = xs[(int64_t)a * n + p + 1];
             nw = CH == 1 ? (w0 ? w0[p + 1] : 1.0) : w1[p + 1];
         }
-        double du[D], dd[D], fu[D], fd[D];
+        // distances to the cell's upper and lower node on each axis
+        double ru[D], rd[D];
+        bool hu[D], hd[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const double v = cx[a];
             const double *z = zn + g.off[a];
-            const bool hu = c[a] < g.M[a], hd = c[a] > 0;
-            du[a] = hu ? (z[c[a]] - v) * hb.ih[a] : 0.0;
-            dd[a] = hd ? (v - z[c[a] - 1]) * hb.ih[a] : 0.0;
-            // only the factors this thread's corners use
-            const bool vary = D <= 2 || a < 2;
-            const bool upb = ((qbase >> a) & 1) != 0;
-            fu[a] = (hu && (vary || upb)) ? exp(-du[a]) : 0.0;
-            fd[a] = (hd && (vary || !upb)) ? exp(-dd[a]) : 0.0;
+            hu[a] = c[a] < g.M[a];
+            hd[a] = c[a] > 0;
+            ru[a] = hu[a] ? z[c[a]] - v : 0.0;
+            rd[a] = hd[a] ? v - z[c[a] - 1] : 0.0;
         }
         double wv[CH];
         if (CH == 1) {
@@ -237,23 +262,41 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
             wv[CH - 1] = cw;
         }
 #pragma unroll
-        for (int lq = 0; lq < NCG; ++lq) {
-            const int q = qbase + lq;
-            double f = 1.0;
+        for (int j = 0; j < NBW; ++j) {
+            if (bb + j >= nb)
+                break;
+            const GkH &hb = hs.h[bb + j];
+            double du[D], dd[D], fu[D], fd[D];
 #pragma unroll
-            for (int a = 0; a < D; ++a)
-                f *= ((q >> a) & 1) ? fu[a] : fd[a];
+            for (int a = 0; a < D; ++a) {
+                du[a] = ru[a] * hb.ih[a];
+                dd[a] = rd[a] * hb.ih[a];
+                // only the factors this thread's corners use
+                const bool vary = D <= 2 || a < 2;
+                const bool upb = ((qbase >> a) & 1) != 0;
+                fu[a] = (hu[a] && (vary || upb)) ? exp(-du[a]) : 0.0;
+                fd[a] = (hd[a] && (vary || !upb)) ? exp(-dd[a]) : 0.0;
+            }
 #pragma unroll
-            for (int u = 0; u < NT; ++u) {
-                const double fq =
-                    u == 0 ? f : f * (((q >> (u - 1)) & 1) ? du[u - 1] : dd[u - 1]);
+            for (int lq = 0; lq < NCG; ++lq) {
+                const int q = qbase + lq;
+                double f = 1.0;
 #pragma unroll
-                for (int v = 0; v < CH; ++v) {
-                    const double tv = fq * wv[v];
-                    const double sm = s[lq][u][v] + tv;
-                    e[lq][u][v] += fabs(s[lq][u][v]) >= fabs(tv) ? (s[lq][u][v] - sm) + tv
-                                                                  : (tv - sm) + s[lq][u][v];
-                    s[lq][u][v] = sm;
+                for (int a = 0; a < D; ++a)
+                    f *= ((q >> a) & 1) ? fu[a] : fd[a];
+#pragma unroll
+                for (int u = 0; u < NT; ++u) {
+                    const double fq =
+                        u == 0 ? f : f * (((q >> (u - 1)) & 1) ? du[u - 1] : dd[u - 1]);
+#pragma unroll
+                    for (int v = 0; v < CH; ++v) {
+                        double &sv = s[j][lq][u][v];
+                        const double tv = fq * wv[v];
+                        const double sm = sv + tv;
+                        e[j][lq][u][v] +=
+                            fabs(sv) >= fabs(tv) ? (sv - sm) + tv : (tv - sm) + sv;
+                        sv = sm;
+                    }
                 }
             }
         }
@@ -265,18 +308,24 @@ __global__ __launch_bounds__(256) void k_gk_bins(GkGrid g, const double *__restr
         bool inside = true;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const int64_t j = ((q >> a) & 1) ? c[a] : c[a] - 1;
-            inside = inside && j >= 0 && j < g.M[a];
-            node += j * g.nst[a];
+            const int64_t jn = ((q >> a) & 1) ? c[a] : c[a] - 1;
+            inside = inside && jn >= 0 && jn < g.M[a];
+            node += jn * g.nst[a];
         }
         if (!inside)
             continue;
 #pragma unroll
-        for (int u = 0; u < NT; ++u)
+        for (int j = 0; j < NBW; ++j) {
+            if (bb + j >= nb)
+                break;
+            double *__restrict__ bins = bins_all + (int64_t)(bb + j) * bins_stride;
 #pragma unroll
-            for (int v = 0; v < CH; ++v)
-                bins[((int64_t)(q * NT + u) * CH + v) * g.nodes + node] =
-                    s[lq][u][v] + e[lq][u][v];
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int v = 0; v < CH; ++v)
+                    bins[((int64_t)(q * NT + u) * CH + v) * g.nodes + node] =
+                        s[j][lq][u][v] + e[j][lq][u][v];
+        }
     }
 }
 
@@ -524,6 +573,270 @@ __global__ __launch_bounds__(256) void k_gs_carry(GsBatch gb) {
     }
 }
 
+// A double from another lane by a DPP move: update (rows outside RM keep
+// 0) or with bound_ctrl (lanes without a source lane get 0).
+template <int CTRL, int RM> __device__ __forceinline__ double gs_dpp(double v) {
+    union {
+        double t;
+        int i[2];
+    } u;
+    u.t = v;
+    u.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, RM, 0xf, false);
+    u.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, RM, 0xf, false);
+    return u.t;
+}
+template <int CTRL> __device__ __forceinline__ double gs_dppz(double v) {
+    union {
+        double t;
+        int i[2];
+    } u;
+    u.t = v;
+    u.i[0] = __builtin_amdgcn_mov_dpp(u.i[0], CTRL, 0xf, 0xf, true);
+    u.i[1] = __builtin_amdgcn_mov_dpp(u.i[1], CTRL, 0xf, 0xf, true);
+    return u.t;
+}
+
+// The step y -> A y + B of each lane composed with those of the lanes before
+// it: forward (dir 0: lanes 0..i) or backward (dir 1: lanes 63..i), so that
+// lane i maps the value entering the wavefront's first lane in that order to
+// its own.  A move from a lane outside the source range brings B = 0, which
+// adds nothing; only A needs the choice.  DPP controls as in the kernel-sum
+// scans: row_shr / row_shl 1, 2, 4, 8 (0x110 + n, 0x100 + n), row_bcast:15 /
+// :31 (0x142, 0x143).
+__device__ __forceinline__ void gs_wave_affine(int dir, double &A, double &B) {
+    const int lane = threadIdx.x & 63;
+    const int rl = lane & 15, row = lane >> 4;
+#define MECDF_GS_STEP(MOVE, TAKE)                                                                 \
+    {                                                                                             \
+        const double Ao = MOVE(A), Bo = MOVE(B);                                                  \
+        B = fma(A, Bo, B);                                                                        \
+        A = (TAKE) ? A * Ao : A;                                                                  \
+    }
+    if (dir == 0) {
+        MECDF_GS_STEP(gs_dppz<0x111>, rl >= 1)
+        MECDF_GS_STEP(gs_dppz<0x112>, rl >= 2)
+        MECDF_GS_STEP(gs_dppz<0x114>, rl >= 4)
+        MECDF_GS_STEP(gs_dppz<0x118>, rl >= 8)
+        MECDF_GS_STEP((gs_dpp<0x142, 0xa>), (row & 1) != 0)
+        MECDF_GS_STEP((gs_dpp<0x143, 0xc>), row >= 2)
+    } else {
+        MECDF_GS_STEP(gs_dppz<0x101>, rl + 1 < 16)
+        MECDF_GS_STEP(gs_dppz<0x102>, rl + 2 < 16)
+        MECDF_GS_STEP(gs_dppz<0x104>, rl + 4 < 16)
+        MECDF_GS_STEP(gs_dppz<0x108>, rl + 8 < 16)
+        {
+            // the first lane of the next row (rows 0 and 2), then lane 32
+            // (rows 0 and 1); other lanes take nothing
+            const bool t1 = (row & 1) == 0;
+            const int src1 = (16 * (row + 1)) & 63;
+            const double Ao = __shfl(A, src1), Bo = __shfl(B, src1);
+            B = t1 ? fma(A, Bo, B) : B;
+            A = t1 ? A * Ao : A;
+            const bool t2 = row < 2;
+            const double Ao2 = __shfl(A, 32), Bo2 = __shfl(B, 32);
+            B = t2 ? fma(A, Bo2, B) : B;
+            A = t2 ? A * Ao2 : A;
+        }
+    }
+#undef MECDF_GS_STEP
+}
+
+// The Laplacian scan along the contiguous axis (inner == 1) when a line fits
+// kGsRowBlocks blocks of 64 nodes: one wavefront per line and corner pair,
+// 64 nodes at a time, each block's steps composed across the lanes and
+// entered by the value the block before left (its last lane forward, first
+// lane backward).  Loads and stores are whole 512-byte rows; the forward
+// results wait in registers for the backward ones, and their sum is written
+// once.  Replaces the chunk sums, carries and chunk scans of this axis.
+constexpr int kGsRowBlocks = 16;
+template <int CH>
+__global__ __launch_bounds__(256) void k_gs_rows(GsBatch gb) {
+    const GsArgs &a = gb.a[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= a.cols)
+        return;  // whole wavefronts
+    const int64_t oi = col % a.outer;
+    const int64_t r = col / a.outer;
+    const int v = (int)(r % CH), co = (int)(r / CH);
+    const int64_t M = a.M, base = oi * M;
+    const double *__restrict__ sU = a.in + gs_arr<CH>(a, 2 * co + 1, 0, v) + base;
+    const double *__restrict__ sD = a.in + gs_arr<CH>(a, 2 * co, 0, v) + base;
+    double *__restrict__ oS = a.out + gs_arr<CH>(a, co, 0, v) + base;
+    const int nb = (int)((M + 63) >> 6);
+    double fs[kGsRowBlocks];
+    double carry = 0.0;
+#pragma unroll
+    for (int b = 0; b < kGsRowBlocks; ++b) {
+        if (b < nb) {
+            // forward into node j: the decay from node j - 1 (none before node 0)
+            const int64_t j = (int64_t)b * 64 + lane;
+            const bool ok = j < M;
+            double A = (ok && j > 0) ? a.dec[j] : 0.0;
+            double B = ok ? sU[j] : 0.0;
+            gs_wave_affine(0, A, B);
+            const double y = fma(A, carry, B);
+            fs[b] = y;
+            carry = __shfl(y, 63);
+        }
+    }
+    carry = 0.0;
+#pragma unroll
+    for (int b = kGsRowBlocks - 1; b >= 0; --b) {
+        if (b < nb) {
+            // backward into node j: the decay from node j + 1 (none after the
+            // last node, which also stops the lanes past the end)
+            const int64_t j = (int64_t)b * 64 + lane;
+            const bool ok = j < M;
+            double A = (ok && j + 1 < M) ? a.dec[j + 1] : 0.0;
+            double B = ok ? sD[j] : 0.0;
+            gs_wave_affine(1, A, B);
+            const double y = fma(A, carry, B);
+            if (ok)
+                oS[j] = fs[b] + y;
+            carry = __shfl(y, 0);
+        }
+    }
+}
+
+// The Matern pair (S, T) of the scanned axis moves by (s, t) -> (d s + S_j,
+// d (t + g s) + T_j): a map with parameters (a, c, bs, bt) standing for
+// s -> a s + bs, t -> c s + a t + bt.  gs_wave_pair composes these maps across
+// the lanes as gs_wave_affine does the plain ones (moves from outside the
+// source range bring zeros: only a and c need the choice).
+__device__ __forceinline__ void gs_pair_then(double Pa, double Pc, double Pbs, double Pbt,
+                                             bool take, double &a, double &c, double &bs,
+                                             double &bt) {
+    // own map after P: bt uses the old c and a
+    bt = fma(c, Pbs, fma(a, Pbt, bt));
+    bs = fma(a, Pbs, bs);
+    const double nc = fma(c, Pa, a * Pc);
+    c = take ? nc : c;
+    a = take ? a * Pa : a;
+}
+__device__ __forceinline__ void gs_wave_pair(int dir, double &a, double &c, double &bs,
+                                             double &bt) {
+    const int lane = threadIdx.x & 63;
+    const int rl = lane & 15, row = lane >> 4;
+#define MECDF_GS_PSTEP(MOVE, TAKE)                                                               \
+    {                                                                                            \
+        const double Pa = MOVE(a), Pc = MOVE(c), Pbs = MOVE(bs), Pbt = MOVE(bt);                 \
+        gs_pair_then(Pa, Pc, Pbs, Pbt, (TAKE), a, c, bs, bt);                                    \
+    }
+    if (dir == 0) {
+        MECDF_GS_PSTEP(gs_dppz<0x111>, rl >= 1)
+        MECDF_GS_PSTEP(gs_dppz<0x112>, rl >= 2)
+        MECDF_GS_PSTEP(gs_dppz<0x114>, rl >= 4)
+        MECDF_GS_PSTEP(gs_dppz<0x118>, rl >= 8)
+        MECDF_GS_PSTEP((gs_dpp<0x142, 0xa>), (row & 1) != 0)
+        MECDF_GS_PSTEP((gs_dpp<0x143, 0xc>), row >= 2)
+    } else {
+        MECDF_GS_PSTEP(gs_dppz<0x101>, rl + 1 < 16)
+        MECDF_GS_PSTEP(gs_dppz<0x102>, rl + 2 < 16)
+        MECDF_GS_PSTEP(gs_dppz<0x104>, rl + 4 < 16)
+        MECDF_GS_PSTEP(gs_dppz<0x108>, rl + 8 < 16)
+        {
+            // every lane takes part in each shuffle (a source lane must be
+            // active); the lanes that take nothing then drop the sums
+            const bool t1 = (row & 1) == 0;
+            const int src1 = (16 * (row + 1)) & 63;
+            const double Pa = __shfl(a, src1), Pc = __shfl(c, src1);
+            const double Pbs = __shfl(bs, src1), Pbt = __shfl(bt, src1);
+            gs_pair_then(Pa, Pc, t1 ? Pbs : 0.0, t1 ? Pbt : 0.0, t1, a, c, bs, bt);
+            const bool t2 = row < 2;
+            const double Qa = __shfl(a, 32), Qc = __shfl(c, 32);
+            const double Qbs = __shfl(bs, 32), Qbt = __shfl(bt, 32);
+            gs_pair_then(Qa, Qc, t2 ? Qbs : 0.0, t2 ? Qbt : 0.0, t2, a, c, bs, bt);
+        }
+    }
+#undef MECDF_GS_PSTEP
+}
+
+// The Matern-3/2 form of k_gs_rows (the contiguous axis is the last one, so
+// no T_l of a later axis is left): S and the axis's own T_k as pairs, R
+// (slot 1, from the second axis on) by the plain steps; the output holds S
+// and R' = T_k + R, both directions added.
+template <int CH>
+__global__ __launch_bounds__(256) void k_gs_rows_mat(GsBatch gb) {
+    const GsArgs &a = gb.a[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= a.cols)
+        return;  // whole wavefronts
+    const int64_t oi = col % a.outer;
+    const int64_t r = col / a.outer;
+    const int v = (int)(r % CH), co = (int)(r / CH);
+    const int64_t M = a.M, base = oi * M;
+    const int ps = 1 + a.k;
+    const bool hasR = a.k >= 1;
+    const int up = 2 * co + 1, dn = 2 * co;
+    const double *__restrict__ sU = a.in + gs_arr<CH>(a, up, 0, v) + base;
+    const double *__restrict__ tU = a.in + gs_arr<CH>(a, up, ps, v) + base;
+    const double *__restrict__ rU = a.in + gs_arr<CH>(a, up, 1, v) + base;
+    const double *__restrict__ sD = a.in + gs_arr<CH>(a, dn, 0, v) + base;
+    const double *__restrict__ tD = a.in + gs_arr<CH>(a, dn, ps, v) + base;
+    const double *__restrict__ rD = a.in + gs_arr<CH>(a, dn, 1, v) + base;
+    double *__restrict__ oS = a.out + gs_arr<CH>(a, co, 0, v) + base;
+    double *__restrict__ oR = a.out + gs_arr<CH>(a, co, 1, v) + base;
+    const int nb = (int)((M + 63) >> 6);
+    double fs[kGsRowBlocks], ft[kGsRowBlocks];
+    double cs = 0.0, ct = 0.0, cr = 0.0;
+#pragma unroll
+    for (int b = 0; b < kGsRowBlocks; ++b) {
+        if (b < nb) {
+            const int64_t j = (int64_t)b * 64 + lane;
+            const bool ok = j < M;
+            const bool st = ok && j > 0;
+            const double dk = st ? a.dec[j] : 0.0;
+            const double gk = st ? (a.z[j] - a.z[j - 1]) * a.ih : 0.0;
+            double pa = dk, pc = dk * gk, bs = ok ? sU[j] : 0.0, bt = ok ? tU[j] : 0.0;
+            gs_wave_pair(0, pa, pc, bs, bt);
+            const double ys = fma(pa, cs, bs);
+            const double yt = fma(pc, cs, fma(pa, ct, bt));
+            fs[b] = ys;
+            ft[b] = yt;
+            cs = __shfl(ys, 63);
+            ct = __shfl(yt, 63);
+            if (hasR) {
+                double A = dk, B = ok ? rU[j] : 0.0;
+                gs_wave_affine(0, A, B);
+                const double yr = fma(A, cr, B);
+                ft[b] += yr;
+                cr = __shfl(yr, 63);
+            }
+        }
+    }
+    cs = ct = cr = 0.0;
+#pragma unroll
+    for (int b = kGsRowBlocks - 1; b >= 0; --b) {
+        if (b < nb) {
+            const int64_t j = (int64_t)b * 64 + lane;
+            const bool ok = j < M;
+            const bool st = ok && j + 1 < M;
+            const double dk = st ? a.dec[j + 1] : 0.0;
+            const double gk = st ? (a.z[j + 1] - a.z[j]) * a.ih : 0.0;
+            double pa = dk, pc = dk * gk, bs = ok ? sD[j] : 0.0, bt = ok ? tD[j] : 0.0;
+            gs_wave_pair(1, pa, pc, bs, bt);
+            const double ys = fma(pa, cs, bs);
+            const double yt = fma(pc, cs, fma(pa, ct, bt));
+            cs = __shfl(ys, 0);
+            ct = __shfl(yt, 0);
+            double tot = ft[b] + yt;
+            if (hasR) {
+                double A = dk, B = ok ? rD[j] : 0.0;
+                gs_wave_affine(1, A, B);
+                const double yr = fma(A, cr, B);
+                tot += yr;
+                cr = __shfl(yr, 0);
+            }
+            if (ok) {
+                oS[j] = fs[b] + ys;
+                oR[j] = tot;
+            }
+        }
+    }
+}
+
 template <int CH, bool MAT>
 __global__ __launch_bounds__(256) void k_gs_apply(GsBatch gb, int64_t total) {
     const GsArgs &a = gb.a[blockIdx.y];
@@ -683,6 +996,9 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
         g.M[a] = M[a];
         g.C[a] = M[a] + 1;
         g.off[a] = total;
+        g.z0[a] = z[total];
+        g.zl[a] = z[total + M[a] - 1];
+        g.gs[a] = g.zl[a] > g.z0[a] ? (double)(M[a] - 1) / (g.zl[a] - g.z0[a]) : 0.0;
         total += M[a];
     }
     int64_t cs = 1, ns = 1;
@@ -751,11 +1067,12 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
     const int kbits = bits_for((uint64_t)cs);
     {
         ProfScope prof("gridkde_sort", s);
-        hipLaunchKernelGGL(k_gk_keys, dim3(nbN), dim3(256), 0, s, g, zn, total, x, N, dropped, k0,
-                           i0);
+        const int hbits = std::min(kRadixMaxBits, kbits);
+        hipLaunchKernelGGL(k_gk_keys, dim3((unsigned)ceil_div(N, kRadixTile)), dim3(256), 0, s, g,
+                           zn, total, x, N, dropped, k0, i0, rs.hist, hbits);
         int which = 0;
         MECDF_TRY((radix_sort_bits<uint32_t, uint32_t>(k0, i0, k1, i1, k2, i2, N, 0, kbits, rs,
-                                                       s, &which)));
+                                                       s, &which, true)));
         const uint32_t *ks = which == 1 ? k1 : (which == 2 ? k2 : k0);
         const uint32_t *is = which == 1 ? i1 : (which == 2 ? i2 : i0);
         hipLaunchKernelGGL((k_gk_gather<WT>), dim3(nbN), dim3(256), 0, s, is, N, d, x,
@@ -784,9 +1101,10 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
             const double *w1 = CH == 2 ? ws : nullptr;
             const int ng = d <= 2 ? 1 : nch / 4;
             const unsigned nbc = (unsigned)ceil_div(g.cells * ng, 256);
-#define MECDF_GKB(D, NTV)                                                                      \
-    hipLaunchKernelGGL((k_gk_bins<D, CH, NTV>), dim3(nbc, nb), dim3(256), 0, s, g, zn, xs, N, \
-                       cstart, w0, w1, hs, bufA, nA)
+#define MECDF_GKB(D, NTV)                                                                   \
+    hipLaunchKernelGGL((k_gk_bins<D, CH, NTV, gk_nbw<D, CH, NTV>()>),                       \
+                       dim3(nbc, (unsigned)ceil_div(nb, gk_nbw<D, CH, NTV>())), dim3(256), 0, s, \
+                       g, zn, xs, N, cstart, w0, w1, hs, nb, bufA, nA)
             if (!matern) {
                 switch (d) {
                 case 1: MECDF_GKB(1, 1); break;
@@ -832,8 +1150,17 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
                     ga.nt = NT;
                     ga.cols = (int64_t)ga.nco * CH * ga.outer * ga.inner;
                 }
-                if (matern)
+                const bool rows = gb.a[0].inner == 1 && gb.a[0].M <= 64 * kGsRowBlocks;
+                if (matern && rows)
+                    hipLaunchKernelGGL((k_gs_rows_mat<CH>),
+                                       dim3((unsigned)ceil_div(gb.a[0].cols, 4), nb), dim3(256), 0,
+                                       s, gb);
+                else if (matern)
                     gs_launch<CH, true>(gb, nb, s);
+                else if (rows)
+                    hipLaunchKernelGGL((k_gs_rows<CH>),
+                                       dim3((unsigned)ceil_div(gb.a[0].cols, 4), nb), dim3(256), 0,
+                                       s, gb);
                 else
                     gs_launch<CH, false>(gb, nb, s);
                 MECDF_LAUNCH_CHECK();

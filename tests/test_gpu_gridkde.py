@@ -68,6 +68,29 @@ def test_grid_kde_and_nw_random(lib, case):
     assert np.all(np.abs(f32[nz] - w32[nz]) <= 1e-5 * s32[nz] + np.finfo(np.float32).tiny)
 
 
+def test_grid_kde_points_on_uniform_nodes(lib):
+    """Uniform grids with half the points exactly on nodes and the rest
+    anywhere, past both ends too: the cell of a point is guessed by mesh
+    division and checked against the nodes, so ties must land in the cell
+    whose upper node they equal."""
+    g = np.random.default_rng(341)
+    nodes = [np.linspace(-2.0, 2.0, 41), np.linspace(-1.0, 3.0, 17)]
+    n = 3000
+    x = np.empty((2, n))
+    for k in range(2):
+        pick = g.integers(0, len(nodes[k]), n)
+        x[k] = np.where(g.random(n) < 0.5, nodes[k][pick], g.uniform(-2.5, 3.5, n))
+    w = g.uniform(0.2, 2.0, n)
+    hs = hmat([0.1, 0.7], 2)
+    zq = oracle.grid_points(nodes)
+    f = lib.kde_laplace_grid(dev(x), nodes, hs, dev(w)).cpu().numpy().reshape(len(hs), -1)
+    want, scale = oracle.kde_laplace(x, zq, hs, w)
+    assert np.max(np.abs(f - want) / scale) <= 1e-12
+    f = lib.kde_matern32_grid(dev(x), nodes, hs, dev(w)).cpu().numpy().reshape(len(hs), -1)
+    want, scale = oracle.kde_matern32(x, zq, hs, w)
+    assert np.max(np.abs(f - want) / scale) <= 1e-12
+
+
 def test_grid_kde_paper_accuracy_claim(lib):
     """Section 4.2: the fast-summation KDE within 1e-14 of the naive sums for
     X ~ N(0, I_2), h = 0.1; here N = 20000 points and a 141 x 141 grid over
