@@ -749,7 +749,16 @@ __global__ __launch_bounds__(256) void k_block_count(Item<1> *__restrict__ S,
             sx[cur ^ 1][dst] = (uint16_t)slot;
             sp[cur ^ 1][dst] = sp[cur][r] + other;
         }
-        __syncthreads();
+        // up to runs of 32, the next level's blocks of 64 items lie in one
+        // wavefront's ranges (items w*64.. and 256 + w*64..), which only it
+        // reads and writes: its own LDS accesses are ordered, no barrier
+        if (len <= 16) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
         cur ^= 1;
     }
 #pragma unroll
