@@ -805,7 +805,11 @@ __device__ __forceinline__ void tile_coords(const KLevelArgs &L, int64_t t0, dou
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
                                                    KTileAgg<T, CH, NSD> *__restrict__ agg) {
-    __shared__ Aff<T, CH, NSD> buf[shfl_scan<T, CH>() ? 4 : 256];
+    // the wavefront scans also for float64 density sums up to d = 2: only
+    // the tile totals are kept, which leaves them the registers of the
+    // LDS tree variant
+    constexpr bool kShfl = shfl_scan<T, CH>() || NSD <= 2;
+    __shared__ Aff<T, CH, NSD> buf[kShfl ? 4 : 256];
     const int64_t base = (int64_t)blockIdx.x * kKTile + (int64_t)threadIdx.x * kKItems;
     T alpha[kKItems + 1][kKB], f[kKItems][kKB], wv[kKItems][CH];
     int sd[kKItems];
@@ -815,7 +819,7 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
     double ih[kKB];
     scan_ih(kb, L.sc, ih);
     double fi_lo, fi_hi, bi_lo, bi_hi;  // the unused pair of tile_coords
-    if constexpr (shfl_scan<T, CH>()) {
+    if constexpr (kShfl) {
         Aff<T, CH, NSD> fi, fe, bi, be;
         block_aff_scan2<!tile_products<T>(), T, CH, NSD>(thread_aff<T, CH, NSD>(alpha, f, sd, wv, val, ps, 0), buf,
                                     0, fi, fe, ih);
