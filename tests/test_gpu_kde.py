@@ -227,6 +227,29 @@ def test_kde_config4_full_size_sampled(lib):
     assert np.all(np.isfinite(c32.cpu().numpy()))
 
 
+@pytest.mark.parametrize("d,n", [(1, 300001), (2, 300001), (3, 280003)])
+def test_kde_tile_carries_in_runs_sampled(lib, d, n):
+    """More than 256 tiles of 1024 items: the tile carries go through groups
+    of 256 tiles and a per-tile composition of the group totals before it;
+    densities and NW at sampled points (ragged last tile and group) against
+    the oracle, float64 and the float32 path."""
+    g = np.random.default_rng(12 + d)
+    x = g.normal(size=(d, n))
+    y = np.sin(x[0]) + 0.1 * g.normal(size=n)
+    hs = np.array([0.02, 0.15, 0.9])
+    xt = dev(x)
+    idx = np.concatenate([g.choice(n, 48, replace=False), np.argmax(x, axis=1),
+                          np.argmin(x, axis=1)])
+    want, scale = oracle.kde_laplace(x, x[:, idx], hs)
+    f, _ = lib.kde_laplace(xt, hs)
+    assert rel_err(f.cpu().numpy()[:, idx], want, scale) <= 1e-12
+    f32, _ = lib.kde_laplace(xt, hs, prec="f32c")
+    assert rel_err(f32.cpu().numpy()[:, idx], want, scale) <= 1e-5
+    m, _ = lib.kreg_laplace(xt, dev(y), hs)
+    wantm = oracle.nw_regression(x, y, x[:, idx], hs)
+    assert np.max(np.abs(m.cpu().numpy()[:, idx] - wantm)) <= 1e-12 * np.max(np.abs(y))
+
+
 def test_kde_deterministic(lib):
     g = np.random.default_rng(11)
     x = dev(g.normal(size=(2, 30000)))
