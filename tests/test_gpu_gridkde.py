@@ -28,8 +28,8 @@ def hmat(hs, d):
 
 
 CASES = [(1, 1, [5]), (1, 700, [1]), (1, 900, [40]), (1, 3000, [2500]), (2, 2, [3, 4]),
-         (2, 1500, [17, 23]), (2, 3000, [64, 1]), (3, 1200, [9, 7, 11]),
-         (4, 600, [5, 4, 6, 3]), (6, 300, [3, 2, 4, 1, 3, 2])]
+         (2, 1500, [17, 23]), (2, 3000, [64, 1]), (2, 2000, [30, 65]), (2, 1500, [7, 1000]),
+         (3, 1200, [9, 7, 11]), (4, 600, [5, 4, 6, 3]), (6, 300, [3, 2, 4, 1, 3, 2])]
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -121,8 +121,9 @@ def test_grid_kde_interpolated_to_the_points(lib):
 
 
 MATERN_CASES = [(1, 1, [5]), (1, 800, [37]), (1, 3000, [2500]), (2, 2, [3, 4]),
-                (2, 1500, [17, 40]), (2, 2500, [100, 3]), (3, 700, [1, 9, 20]),
-                (3, 1000, [9, 18, 11]), (4, 500, [5, 4, 6, 3])]
+                (2, 1500, [17, 40]), (2, 2500, [100, 3]), (2, 1500, [9, 130]),
+                (2, 2000, [5, 1024]), (3, 700, [1, 9, 20]), (3, 1000, [9, 18, 11]),
+                (4, 500, [5, 4, 6, 3])]
 
 
 @pytest.mark.parametrize("case", MATERN_CASES)
