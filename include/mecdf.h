@@ -376,7 +376,7 @@ int kreg_laplace_grid(int d, int64_t N, const double *x, const void *y,
  * channels, the plain exponential sums and one distance-weighted sum per
  * axis, spread by decayed scans (the distance sums move with the plain sums
  * along their own axis).  Arguments, layout, errors and precision as
- * kde_laplace_grid; d <= 4 (MECDF_EUNSUPPORTED above).
+ * kde_laplace_grid; d = 1..6.
  */
 int kde_matern32_grid(int d, int64_t N, const double *x, const void *w,
                       const int64_t *M, const double *z, int nh, const double *h,
@@ -385,7 +385,7 @@ int kde_matern32_grid(int d, int64_t N, const double *x, const void *w,
 /*
  * kreg_matern32_grid -- the Nadaraya-Watson estimate with the same kernel at
  * every grid node: m[b*G + node] = sum_i y_i K / sum_i K (NaN where both sums
- * underflow).  Arguments as kreg_laplace_grid; d <= 4.
+ * underflow).  Arguments as kreg_laplace_grid; d = 1..6.
  */
 int kreg_matern32_grid(int d, int64_t N, const double *x, const void *y,
                        const int64_t *M, const double *z, int nh, const double *h,

@@ -703,8 +703,6 @@ int kreg_loclin_laplace(int d, int64_t N, const double *x, const void *y, int nh
 static int gridkde_check(int d, int64_t N, const double *x, const int64_t *M, const double *z,
                          int nh, const double *h, void *out, int prec, int matern) {
     MECDF_TRY(check_common(d, N, x, prec, MECDF_MAX_DIM));
-    if (matern && d > 4)
-        return fail(MECDF_EUNSUPPORTED, "the Matern-3/2 grid sums take d <= 4");
     if (N < 1)
         return fail(MECDF_EINVAL, "grid kernel sums need N >= 1");
     if (nh < 1 || nh > 256)

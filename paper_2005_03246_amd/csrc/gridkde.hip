@@ -1119,7 +1119,9 @@ static int gridkde_t(int d, int64_t N, const double *x, const WT *w, const int64
                 case 1: MECDF_GKB(1, 2); break;
                 case 2: MECDF_GKB(2, 3); break;
                 case 3: MECDF_GKB(3, 4); break;
-                default: MECDF_GKB(4, 5); break;
+                case 4: MECDF_GKB(4, 5); break;
+                case 5: MECDF_GKB(5, 6); break;
+                default: MECDF_GKB(6, 7); break;
                 }
             }
 #undef MECDF_GKB

@@ -127,9 +127,9 @@ def test_grid_kernel_sum_validation(lib):
         assert f(2, 10, fake, w, M, z, 1, h, None, 0, None) == -1      # no output
         if reg:
             assert f(2, 10, fake, None, M, z, 1, h, fake, 0, None) == -1  # y NULL
-    # the Matern channel arrays stop at d = 4
+    # d beyond 6 is refused before anything is read or launched
     mk = _c(lib, "kde_matern32_grid", [I, I64, P, P, P, P, I, P, P, I, P])
-    assert mk(5, 10, fake, None, M, z, 1, h, fake, 0, None) == -4
+    assert mk(7, 10, fake, None, M, z, 1, h, fake, 0, None) == -1
 
 
 def test_arbitrary_point_queries_validation(lib):

@@ -123,7 +123,7 @@ def test_grid_kde_interpolated_to_the_points(lib):
 MATERN_CASES = [(1, 1, [5]), (1, 800, [37]), (1, 3000, [2500]), (2, 2, [3, 4]),
                 (2, 1500, [17, 40]), (2, 2500, [100, 3]), (2, 1500, [9, 130]),
                 (2, 2000, [5, 1024]), (3, 700, [1, 9, 20]), (3, 1000, [9, 18, 11]),
-                (4, 500, [5, 4, 6, 3])]
+                (4, 500, [5, 4, 6, 3]), (5, 300, [3, 2, 4, 2, 3]), (6, 200, [2, 3, 2, 1, 2, 3])]
 
 
 @pytest.mark.parametrize("case", MATERN_CASES)
