@@ -116,6 +116,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the "
                          "reference kernel that scales the HBM byte counters)")
+    ap.add_argument("--kde-calls", action="store_true",
+                    help="only run one LOO-CV density call and one Nadaraya-Watson call "
+                         "of the kernel-sum workload (N = 2^22, 64 bandwidths, FP64), "
+                         "for instruction-counter runs")
     return ap.parse_args()
 
 
@@ -690,10 +694,30 @@ def cpu_legs(target_s):
     return legs
 
 
+def kde_calls():
+    """One LOO-CV density call and one Nadaraya-Watson call at N = 2^22 x 64
+    bandwidths in float64 (the kernel-sum workload), nothing timed."""
+    import torch
+
+    from paper_2005_03246_amd import datagen, mecdf
+
+    x4, y4, h4 = datagen.config4()
+    x = torch.from_numpy(x4).cuda()
+    y = torch.from_numpy(y4).cuda()
+    mecdf.kde_laplace(x, h4)
+    torch.cuda.synchronize()
+    mecdf.kreg_laplace(x, y, h4)
+    torch.cuda.synchronize()
+    print(json.dumps({"kde_calls": "done"}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.kde_calls:
+        kde_calls()
         return
     if args.secondary_only:
         print(json.dumps({"secondary": secondary()}), flush=True)
