@@ -116,6 +116,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three device-to-device copies of 1 GiB (the "
                          "reference kernel that scales the HBM byte counters)")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="only time the workloads of the paper's timing tables (Section 4: "
+                         "X ~ N(0, I_d), d = 2 and 6, h = 0.1, N = 20k .. 1.28M, M = N "
+                         "evaluation points) beside the paper's CPU seconds")
     ap.add_argument("--kde-calls", action="store_true",
                     help="only run one LOO-CV density call and one Nadaraya-Watson call "
                          "of the kernel-sum workload (N = 2^22, 64 bandwidths, FP64), "
@@ -694,6 +698,71 @@ def cpu_legs(target_s):
     return legs
 
 
+# Seconds the paper reports for its C++ code on one laptop CPU (Section 4,
+# Tables tab:2DCDFCalc, tab:6DCDFCalc, tab:2DKDECalc, tab:6DKDECalc), per
+# sample size N = 20k, 40k, ..., 1.28M; None where the table has no entry.
+PAPER_NS = [20000, 40000, 80000, 160000, 320000, 640000, 1280000]
+PAPER_SECONDS = {
+    "ecdf_grid_d2": [0.01, 0.01, 0.02, 0.04, 0.07, 0.15, 0.32],
+    "ecdf_points_d2": [0.01, 0.02, 0.05, 0.1, 0.29, 0.66, 1.5],
+    "ecdf_grid_d6": [0.01, 0.02, 0.05, 0.09, 0.22, 0.47, 0.96],
+    "ecdf_points_d6": [1.2, 3.1, 7.8, 19.7, 50.1, 125.1, 312.3],
+    "kde_grid_d2": [0.01, 0.01, 0.04, 0.08, 0.14, 0.34, None],
+    "kde_points_d2": [0.05, 0.08, 0.19, 0.43, 0.99, 2.29, None],
+    "kde_grid_d6": [0.18, 0.26, 0.65, 1.51, 3.59, 7.97, 16.11],
+    "kde_points_d6": [15, 41, 111, 294, 777, 2040, 5344],
+}
+
+
+def paper_tables():
+    """The paper's timing workloads on this GPU: X ~ N(0, I_d), h = 0.1 on
+    every axis, M = N evaluation points (the sample points, or a grid of
+    round(N^(1/d)) uniform nodes per axis over the sample's range), ECDF
+    counts and Laplacian KDE, one call each (median of three after a warm-up
+    call).  The paper's seconds are from a laptop CPU: context, not a target.
+    KDE at the points for d >= 4 sums every pair directly and takes
+    N <= 2^20."""
+    import torch
+
+    from paper_2005_03246_amd import datagen, mecdf
+
+    def med(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+
+    rows = []
+    for d in (2, 6):
+        for i, n in enumerate(PAPER_NS):
+            x = datagen.paper_normal(n, d)
+            xt = torch.from_numpy(x).cuda()
+            m = max(1, int(round(n ** (1.0 / d))))
+            nodes = datagen.uniform_grid(x, m)
+            work = {
+                f"ecdf_grid_d{d}": lambda: mecdf.ecdf_grid(xt, nodes),
+                f"ecdf_points_d{d}": lambda: mecdf.ecdf_points(xt),
+                f"kde_grid_d{d}": lambda: mecdf.kde_laplace_grid(xt, nodes, [0.1]),
+                f"kde_points_d{d}": lambda: mecdf.kde_laplace(xt, [0.1], want_lcv=False),
+            }
+            for key, fn in work.items():
+                if key == "kde_points_d6" and n > (1 << 20):
+                    continue
+                t = med(fn)
+                ps = PAPER_SECONDS[key][i]
+                rows.append({"workload": key, "N": n, "grid_nodes_per_axis": m
+                             if "grid" in key else None, "ms": t * 1e3, "paper_s": ps,
+                             "paper_s_over_ours": (ps / t) if ps else None})
+                log(f"paper table {key} N={n}: {t * 1e3:.3f} ms (paper {ps} s)")
+            del xt
+    return rows
+
+
 def kde_calls():
     """One LOO-CV density call and one Nadaraya-Watson call at N = 2^22 x 64
     bandwidths in float64 (the kernel-sum workload), nothing timed."""
@@ -718,6 +787,9 @@ def main():
         return
     if args.kde_calls:
         kde_calls()
+        return
+    if args.paper_tables:
+        print(json.dumps({"paper_tables": paper_tables()}), flush=True)
         return
     if args.secondary_only:
         print(json.dumps({"secondary": secondary()}), flush=True)

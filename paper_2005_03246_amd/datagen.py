@@ -108,6 +108,12 @@ def config4(n: int = 1 << 22, seed: int | None = None):
     return x, y, bandwidths(64)
 
 
+def paper_normal(n: int, d: int, seed: int | None = None) -> np.ndarray:
+    """The timing workload of Section 4: X ~ N(0, I_d), (d, n)."""
+    g = rng(10 + d, seed)
+    return g.standard_normal((d, n))
+
+
 def mixture_dataset(g: np.random.Generator, n: int, d: int) -> np.ndarray:
     """One random Gaussian mixture sample: K ~ U{1..5} components, Dirichlet(1)
     weights, means U[-3,3]^d, covariances Wishart(d+2, I/(d+2))."""
