@@ -1587,12 +1587,16 @@ static int points_direct_d(int64_t N, const double *x, const void *y, void *F, i
 }
 
 // Samples up to this size use the direct evaluation (cost N^2 d); the
-// environment variable MECDF_POINTS_DIRECT_MAX overrides it (0: never).
-static int64_t points_direct_max() {
+// environment variable MECDF_POINTS_DIRECT_MAX overrides it (0: never).  The
+// sizes per d are where the two paths took the same time on one MI355X
+// (weighted and count calls; the recursion's cost grows with d as
+// N log^(d-1) N, the direct one as d N^2).
+static int64_t points_direct_max(int d) {
     const char *e = std::getenv("MECDF_POINTS_DIRECT_MAX");
     if (e && *e)
         return (int64_t)std::strtoll(e, nullptr, 10);
-    return int64_t(1) << 16;
+    static const int64_t kMax[MECDF_MAX_DIM] = {20000, 24000, 32000, 46000, 80000, 150000};
+    return kMax[(d < 1 ? 1 : (d > MECDF_MAX_DIM ? MECDF_MAX_DIM : d)) - 1];
 }
 
 template <int NC>
@@ -1631,7 +1635,7 @@ int points_run(int d, int64_t N, const double *x, const void *y, void *F,
         set_error("the points path supports N <= 2^26");
         return MECDF_EUNSUPPORTED;
     }
-    if (N > 0 && N <= points_direct_max()) {
+    if (N > 0 && N <= points_direct_max(d)) {
         switch (d) {
         case 1: return points_direct_d<1>(N, x, y, F, survival, prec, s);
         case 2: return points_direct_d<2>(N, x, y, F, survival, prec, s);
