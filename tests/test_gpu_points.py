@@ -155,3 +155,40 @@ def test_nan_points_weighted(lib, path, d):
         np.testing.assert_array_equal(fn(dev(x)).cpu().numpy(), ofn(x, x))
         want, _ = ofn(x, x, y)
         np.testing.assert_array_equal(fn(dev(x), dev(y)).cpu().numpy(), want)
+
+
+# Largest sample sizes of the direct (all pairs) kernel for d = 1 .. 6 when
+# MECDF_POINTS_DIRECT_MAX is not set; one point more takes the recursion.
+DIRECT_MAX = {1: 20000, 2: 24000, 3: 32000, 4: 46000, 5: 80000, 6: 150000}
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
+def test_points_at_the_path_switch(lib, monkeypatch, d):
+    """Both sides of the size where the default path changes, for each d:
+    counts at sampled points (and the extreme points) equal to the brute
+    force, weights within 1e-12 of the |y| scale; the direct and the
+    recursive evaluation of the same sample give the same counts at every
+    point."""
+    monkeypatch.delenv("MECDF_POINTS_DIRECT_MAX", raising=False)
+    g = np.random.default_rng(500 + d)
+    for n in (DIRECT_MAX[d], DIRECT_MAX[d] + 1):
+        x = np.round(g.normal(size=(d, n)), 2)   # ties on purpose
+        y = g.normal(size=n)
+        xt, yt = dev(x), dev(y)
+        idx = np.concatenate([g.choice(n, 150, replace=False), [0, n - 1],
+                              np.argmax(x, axis=1), np.argmin(x, axis=1)])
+        z = x[:, idx]
+        F = lib.ecdf_points(xt).cpu().numpy()
+        Fb = lib.esf_points(xt).cpu().numpy()
+        np.testing.assert_array_equal(F[idx], oracle.ecdf(x, z))
+        np.testing.assert_array_equal(Fb[idx], oracle.esf(x, z))
+        w, a = oracle.ecdf(x, z, y)
+        check_weighted(lib.ecdf_points(xt, yt).cpu().numpy()[idx], w, a, 1e-12)
+        w, a = oracle.esf(x, z, y)
+        check_weighted(lib.esf_points(xt, yt).cpu().numpy()[idx], w, a, 1e-12)
+        # the other path on the same sample
+        other = "0" if n <= DIRECT_MAX[d] else str(1 << 30)
+        monkeypatch.setenv("MECDF_POINTS_DIRECT_MAX", other)
+        np.testing.assert_array_equal(lib.ecdf_points(xt).cpu().numpy(), F)
+        np.testing.assert_array_equal(lib.esf_points(xt).cpu().numpy(), Fb)
+        monkeypatch.delenv("MECDF_POINTS_DIRECT_MAX")
