@@ -34,17 +34,17 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "e8dcd20fa04d4b9895b82f8c599a84f0a36cfc92a89ea8298021908a68d62af4",
+        "sha256": "6df058824dc50db1c2216eda21d9b4e210750765f93dfec859c07bc52022f9e6",
         "prec": "f64",
-        "fetch_kib": 131125.6, "fetch_factor": 2.0,
+        "fetch_kib": 131125.2, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
         "source": "paper_2005_03246_amd/csrc/radix.hpp",
-        "sha256": "f9754c33fa54a1abb6764c46b72814a7e1059147050d289374d33af86e60e554",
+        "sha256": "f5ede7775f9f2d3bc0050939dcae1b046fc9c495aac3f11e97a0ab085d2e250a",
         "prec": "f64",
-        "fetch_kib": 102444.9, "fetch_factor": 2.0,
-        "write_kib": 225431.6, "write_factor": 1.0,
+        "fetch_kib": 102452.7, "fetch_factor": 2.0,
+        "write_kib": 199834.1, "write_factor": 1.0,
     },
 }
 

@@ -627,7 +627,9 @@ __global__ __launch_bounds__(256) void k_axis_scan(T *__restrict__ A, T *__restr
                                                    int64_t outer, int64_t Mk,
                                                    int64_t inner, int sufA, int scale,
                                                    double N) {
-    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // consecutive column blocks on one XCD (the rows of neighbouring blocks
+    // share a line at each end)
+    int64_t t = xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (t >= outer * inner)
         return;
     T *arr = blockIdx.y ? B : A;

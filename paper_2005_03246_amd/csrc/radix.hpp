@@ -263,6 +263,22 @@ constexpr int kScatThreads = kScatWaves * 64;
 constexpr int kScatItems = kRadixTile / kScatThreads;  // 8 keys per thread
 static_assert(kScatThreads >= kRadixMaxDigits, "one digit per thread");
 
+// The tile that workgroup b of a launch of nt workgroups works on.  The
+// dispatcher hands workgroups to the eight XCDs in turn (b mod 8); here each
+// XCD takes a contiguous range of tiles, in order, so that what neighbouring
+// tiles write next to each other (the runs of one digit in the radix scatter,
+// the row ends of neighbouring column blocks in the axis scans) goes through
+// one L2, which merges the cache lines they share instead of sending two
+// partial lines to memory.  A bijection of [0, nt) for any nt.  Not for work
+// of uneven size (the grid lines): one XCD would get a whole region of long
+// lines.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
+    const int64_t q = nt / kXcds, r = nt % kXcds;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 template <typename K, typename P>
 __global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
     const K *__restrict__ kin, const P *__restrict__ pin, K *__restrict__ kout,
@@ -288,7 +304,7 @@ __global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int lane = tid & 63;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, ntiles);
     const int64_t base = tile * kRadixTile;
 
     // all global loads first, so that they are in flight together;
@@ -396,7 +412,6 @@ __global__ __launch_bounds__(kScatThreads) void k_radix_scatter(
                 pout[dst[i]] = s_pay[q];
         }
     }
-    (void)ntiles;
 }
 
 // All per-(tile, digit) offsets in one workgroup, for at most kOffSmall
