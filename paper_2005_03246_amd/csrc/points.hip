@@ -602,7 +602,9 @@ __global__ __launch_bounds__(256) void k_merge_path(
     __shared__ uint16_t sSrc[kMpT];   // per output: source slot in sI
     __shared__ int64_t sspl[2];
     const int tid = threadIdx.x;
-    const int64_t o0 = (int64_t)blockIdx.x * kMpT;
+    // consecutive output tiles on one XCD: neighbouring tiles read the ends
+    // of each other's input ranges and search near the same diagonals
+    const int64_t o0 = xcd_tile(blockIdx.x, gridDim.x) * kMpT;
     const int64_t s = (o0 / (2 * h)) * (2 * h);
     const int64_t ha = (n - s) < h ? (n - s) : h;
     const int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
@@ -800,7 +802,9 @@ __global__ __launch_bounds__(256) void k_merge_count(
     __shared__ int64_t sspl[2];
     __shared__ PV sPrev[2];           // p just before the A and the B range
     const int tid = threadIdx.x;
-    const int64_t o0 = (int64_t)blockIdx.x * kMpT;
+    // consecutive output tiles on one XCD: neighbouring tiles read the ends
+    // of each other's input ranges and search near the same diagonals
+    const int64_t o0 = xcd_tile(blockIdx.x, gridDim.x) * kMpT;
     const int64_t s = (o0 / (2 * h)) * (2 * h);
     const int64_t ha = (n - s) < h ? (n - s) : h;
     const int64_t hb = (n - s - ha) < h ? (n - s - ha) : h;
