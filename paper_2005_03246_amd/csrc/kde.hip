@@ -866,26 +866,23 @@ __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__re
                                                       KTileAgg<T, CH, NSD> *__restrict__ grp,
                                                       KCarry<T, CH, NSD> *__restrict__ car,
                                                       KBatch kb, int sc) {
-    __shared__ Aff<T, CH, NSD> buf[256];
+    __shared__ Aff<T, CH, NSD> wt[4];
     const int t = threadIdx.x;
     double ih[kKB];
     scan_ih(kb, sc, ih);
     const int64_t q = (int64_t)blockIdx.x * 256 + t;
-    Aff<T, CH, NSD> fa, ba, id;
-    aff_identity(id);
-    fa = id;
-    ba = id;
+    Aff<T, CH, NSD> fa, ba;
+    aff_identity(fa);
+    aff_identity(ba);
     if (q < nt) {
         fa = agg[q].fwd;
         ba = agg[q].bwd;
     }
-    Aff<T, CH, NSD> fi = block_aff_scan<true, T, CH, NSD>(fa, buf, 0, ih);
-    Aff<T, CH, NSD> fex = t == 0 ? id : aff_get<true>(buf, t - 1);
+    Aff<T, CH, NSD> fi, fex, bi, bex;
+    block_aff_scan2<true, T, CH, NSD>(fa, wt, 0, fi, fex, ih);
     if (t == 255)
         grp[blockIdx.x].fwd = fi;
-    __syncthreads();
-    Aff<T, CH, NSD> bi = block_aff_scan<true, T, CH, NSD>(ba, buf, 1, ih);
-    Aff<T, CH, NSD> bex = t == 255 ? id : aff_get<true>(buf, t + 1);
+    block_aff_scan2<true, T, CH, NSD>(ba, wt, 1, bi, bex, ih);
     if (t == 0)
         grp[blockIdx.x].bwd = bi;
     if (q >= nt)
@@ -914,19 +911,48 @@ __global__ __launch_bounds__(256) void k_kcarry_final(const KTileAgg<T, CH, NSD>
                                                       const KTileAgg<T, CH, NSD> *__restrict__ grp,
                                                       KCarry<T, CH, NSD> *__restrict__ car,
                                                       KBatch kb, int sc) {
+    __shared__ Aff<T, CH, NSD> ent[2];  // the maps entering this group, both ways
     const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (q >= nt)
-        return;
     double ih[kKB];
     scan_ih(kb, sc, ih);
-    const int64_t g = q / 256, ng = ceil_div_dev(nt, (int64_t)256);
+    const int64_t g = blockIdx.x, ng = ceil_div_dev(nt, (int64_t)256);
     Aff<T, CH, NSD> cf, cb;
     aff_identity(cf);
     aff_identity(cb);
-    for (int64_t j = 0; j < g; ++j)
-        cf = aff_then<true>(cf, grp[j].fwd, ih);
-    for (int64_t j = ng - 1; j > g; --j)
-        cb = aff_then<true>(cb, grp[j].bwd, ih);
+    if (ng <= 64) {
+        // the first wavefront (all its lanes active) scans the group maps,
+        // lane j holding group j (identity past the last group)
+        if (threadIdx.x < 64) {
+            const int j = (int)threadIdx.x;
+            Aff<T, CH, NSD> f = cf, b = cb;
+            if (j < ng) {
+                f = grp[j].fwd;
+                b = grp[j].bwd;
+            }
+            f = wave_aff_scan<true>(f, 0, ih);  // groups 0..j
+            b = wave_aff_scan<true>(b, 1, ih);  // groups ng-1 down to j
+            // lane g - 1 / g + 1 holds what enters group g; the first and
+            // the last group keep the identity
+            if (g > 0 && j == g - 1)
+                ent[0] = f;
+            if (g + 1 < ng && j == g + 1)
+                ent[1] = b;
+            if (g == 0 && j == 0)
+                ent[0] = cf;
+            if (g + 1 == ng && j == 0)
+                ent[1] = cb;
+        }
+        __syncthreads();
+        cf = ent[0];
+        cb = ent[1];
+    } else {
+        for (int64_t j = 0; j < g; ++j)
+            cf = aff_then<true>(cf, grp[j].fwd, ih);
+        for (int64_t j = ng - 1; j > g; --j)
+            cb = aff_then<true>(cb, grp[j].bwd, ih);
+    }
+    if (q >= nt)
+        return;
     const Aff<T, CH, NSD> ef = loc[q].fwd, eb = loc[q].bwd;
 #pragma unroll
     for (int b = 0; b < kKB; ++b) {
