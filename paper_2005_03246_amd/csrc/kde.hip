@@ -854,12 +854,14 @@ __global__ __launch_bounds__(256) void k_ktile_agg(KLevelArgs L, KBatch kb,
 }
 
 // Tile carries in two steps.  k_kcarry_local: per group of 256 consecutive
-// tiles, the exclusive tree scans of the tile maps inside the group (forward:
-// tiles in ascending order; backward: descending), written over the tile
-// aggregates, and the group totals; with one group (car != null) it writes
-// the carries itself.  k_kcarry_final: per tile, the maps of
-// the groups before it (forward) or after it (backward) composed in order,
-// then the tile's own exclusive map: the state entering the tile.
+// tiles, the exclusive scans of the tile maps inside the group (forward:
+// tiles in ascending order; backward: descending; wavefront scans, then the
+// four wavefront totals), written over the tile aggregates, and the group
+// totals; with one group (car != null) it writes the carries itself.
+// k_kcarry_final: per group, the maps of the groups before it (forward) or
+// after it (backward) composed in order (by one wavefront's scan of the group
+// totals when there are at most 64 groups, else one after the other), then
+// per tile its own exclusive map: the state entering the tile.
 template <typename T, int CH, int NSD>
 __global__ __launch_bounds__(256) void k_kcarry_local(KTileAgg<T, CH, NSD> *__restrict__ agg,
                                                       int64_t nt,
