@@ -34,9 +34,9 @@ LOG2N = 24
 TRAFFIC = {
     "grid_axis_scan": {
         "source": "paper_2005_03246_amd/csrc/grid.hip",
-        "sha256": "6df058824dc50db1c2216eda21d9b4e210750765f93dfec859c07bc52022f9e6",
+        "sha256": "be0c75b410b16a5b7c81f0d3b896865b2a214c5edec161cf12063805490fe88f",
         "prec": "f64",
-        "fetch_kib": 131125.2, "fetch_factor": 2.0,
+        "fetch_kib": 131106.2, "fetch_factor": 2.0,
         "write_kib": 262144.0, "write_factor": 1.0,
     },
     "radix_scatter": {
